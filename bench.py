@@ -1,0 +1,160 @@
+"""Benchmark of the fused phase-field LB step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload spinodal1024|spinodal4096]
+
+A step is one time step of the coupled D2Q9 solver (pull of the stored populations, phi/mu
+stencils, forces, eq. (28) pressure, both collisions, push-streaming) over the whole grid: one
+launch of the fused kernel. Inputs are synthetic (seeded spinodal noise), resident in HBM when
+the timed region starts. Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_CELL = 168   # f_1..8, h_0 hi, h_1..8, h_0 lo, p, (phi u)_x, (phi u)_y: 21 FP32 read + 21 written
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1902_08933_amd", "csrc", "lbpf_kernels.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fused_step_spinodal1024_pmc.txt")
+
+
+def kernel_hash():
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(cells):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken on the
+    current kernel source; otherwise None."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    text = open(TRAFFIC_SUMMARY).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    c = re.search(r"cells:\s*([0-9]+)", text)
+    if not (m and t and c) or m.group(1) != kernel_hash() or int(c.group(1)) != cells:
+        return None
+    return float(t.group(1))
+
+
+def workload(name, variant):
+    from paper_1902_08933_amd import workloads as W
+    if name == "spinodal1024":
+        return W.spinodal(n=1024, variant=variant, seed=0)
+    if name == "spinodal4096":
+        return W.spinodal(n=4096, variant=variant, seed=0)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def time_gpu(cfg, phi, steps, warmup, tile=0):
+    import torch
+    from paper_1902_08933_amd import lbpf
+    sim = lbpf.Simulation(cfg)
+    sim.set_tile(tile)
+    sim.init(torch.from_numpy(phi.astype("float32")).cuda())
+    sim.step(warmup)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    diag = sim.diagnostics()
+    return ms, wall, diag
+
+
+def cpu_baseline(cfg, phi, steps):
+    import numpy as np
+    import oracle
+    o = oracle.Oracle(cfg).init(phi.astype(np.float32).astype(np.float64))
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    return cfg["nx"] * cfg["ny"] * steps / dt / 1e6, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="spinodal1024")
+    ap.add_argument("--variant", default="qim")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the solver has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    cfg, phi = workload(args.workload, args.variant)
+    cells = cfg["nx"] * cfg["ny"]
+    print(f"# workload {args.workload} {cfg['nx']}x{cfg['ny']} {args.variant}: "
+          f"{args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
+    ms, wall, diag = time_gpu(cfg, phi, args.steps, args.warmup, args.tile)
+    ms_per_step = ms / args.steps
+    mlups = cells * args.steps / (ms * 1e-3) / 1e6
+    achieved = BYTES_PER_CELL * cells / (ms_per_step * 1e-3) / 1e9
+    traffic = measured_traffic(cells)
+    out = {
+        "metric": "D2Q9 two-phase MLUPS, % of HBM roofline; surrogate speedup at fixed error",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded spinodal noise phi = 0.5 + U[-0.005, 0.005]",
+        "config": {"workload": f"spinodal decomposition {cfg['nx']}x{cfg['ny']} periodic, "
+                               f"{args.variant.upper()}, rho ratio 3, nu ratio 0.1, sigma 0.03, "
+                               "W 4, M_phi 0.1, tau_h 1",
+                   "nx": cfg["nx"], "ny": cfg["ny"], "variant": args.variant,
+                   "tile": args.tile, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "bytes_per_cell_update": BYTES_PER_CELL,
+                     "kernel": "fused_kernel<64,16,256,true>"},
+        "wall_s_timed": round(wall, 4),
+        "sum_phi_final": diag["sum_phi"],
+    }
+    if not args.no_large and args.workload == "spinodal1024":
+        # footprint far above the 256 MB Infinity Cache: 4096^2 cells, ~2.8 GB of state
+        lcfg, lphi = workload("spinodal4096", args.variant)
+        lsteps = max(50, args.steps // 16)
+        lms, _, _ = time_gpu(lcfg, lphi, lsteps, 20, args.tile)
+        lcells = lcfg["nx"] * lcfg["ny"]
+        lper = lms / lsteps
+        out["large_footprint"] = {
+            "workload": "spinodal 4096x4096", "steps": lsteps, "ms_per_step": lper,
+            "MLUPS": round(lcells / (lper * 1e-3) / 1e6, 1),
+            "achieved_GBs": round(BYTES_PER_CELL * lcells / (lper * 1e-3) / 1e9, 1),
+            "frac": round(BYTES_PER_CELL * lcells / (lper * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if not args.no_cpu_baseline:
+        v, dt = cpu_baseline(cfg, phi, args.cpu_steps)
+        out["cpu_baseline"] = {"value": round(v, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+                               "sample": f"{cfg['nx']}x{cfg['ny']} spinodal {args.variant}, "
+                                         f"{args.cpu_steps} steps of the FP64 C oracle "
+                                         f"({dt:.1f} s, one thread)"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

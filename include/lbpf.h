@@ -1,0 +1,168 @@
+/*
+ * lbpf — phase-field lattice Boltzmann two-phase solver for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Yuan, Chai, Wang & Shi, "A generalized lattice Boltzmann model for fluid flow system
+ * and its application in two-phase flows" (arXiv:1902.08933), Sec. 3: the D2Q9 hydrodynamic
+ * distribution of eq. (24) with equilibrium eq. (33), force distribution eq. (34), velocity
+ * eq. (27a) and modified pressure eq. (28) (or eq. (29)), coupled to the Cahn-Hilliard
+ * distribution of eq. (10) with equilibrium eq. (11), source eq. (14) and order parameter
+ * eq. (18); the closure of Sec. 3.1 (eq. 3aa density, eq. 8 chemical potential) and the
+ * isotropic stencils of eqs. (30a)-(30b). Quasi-incompressible (S1 = -gamma div(M grad mu),
+ * Sec. 3.2.1) and incompressible (S1 = 0) variants.
+ *
+ * Conventions shared by every call:
+ *  - Grids are row-major [ny][nx] with x fastest; nodes sit at integer (i, j), lattice units
+ *    dx = dt = 1, c_s^2 = 1/3. phi = 1 is phase A, phi = 0 is phase B (Sec. 3.1).
+ *  - Device pointers are HIP device addresses. The library never allocates device memory:
+ *    the caller passes one device workspace of lbpf_workspace_size() bytes and keeps it alive
+ *    until lbpf_destroy(). The library owns only its host-side handle.
+ *  - All work is enqueued on the caller's HIP stream (hipStream_t passed as void*; NULL means
+ *    the legacy default stream). Calls return after enqueueing unless stated otherwise.
+ *  - Every call returns an lbpf_status; LBPF_OK is 0. No C++ exception crosses the ABI.
+ *    On failure lbpf_last_error() returns a message for that handle.
+ *  - One handle must not be used from two host threads at once; distinct handles are
+ *    independent.
+ */
+#ifndef LBPF_H
+#define LBPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBPF_OK = 0,
+    LBPF_E_INVALID = -1,  /* bad argument or parameter (message says which) */
+    LBPF_E_HIP = -2,      /* a HIP runtime call failed (message holds the HIP error string) */
+    LBPF_E_NOMEM = -3,    /* workspace or buffer too small, or host allocation failed */
+    LBPF_E_UNSTABLE = -4, /* diagnostics found a non-finite value in the state */
+    LBPF_E_STATE = -5     /* call out of order (e.g. step before init) */
+} lbpf_status;
+
+/* Sec. 4 introduction: incompressible (S1 = 0) or quasi-incompressible
+ * (S1 = -gamma div(M_phi grad mu), gamma = (rho_A - rho_B) / rho_B, Sec. 3.2.1). */
+typedef enum { LBPF_QIM = 0, LBPF_IM = 1 } lbpf_variant;
+
+/* Pressure: eq. (28) with G_0 taken from eq. (34) at i = 0 (default); eq. (28) with the
+ * simplified G_0 printed after eq. (34); or eq. (29), which drops the G_0 term. */
+typedef enum { LBPF_P_EQ28 = 0, LBPF_P_EQ28_PAPER_G0 = 1, LBPF_P_EQ29 = 2 } lbpf_pscheme;
+
+/* Surface tension: F_s = mu grad(phi) (Sec. 3.1, default) or F_s = -phi grad(mu) (Sec. 4.2). */
+typedef enum { LBPF_FS_MU_GRADPHI = 0, LBPF_FS_NEG_PHI_GRADMU = 1 } lbpf_fsurf;
+
+/* Viscosity across the interface: inverse-linear in 1/nu (after eq. 17), or a step in the
+ * dynamic viscosity mu = rho nu at phi = 1/2 (Sec. 4.3). */
+typedef enum { LBPF_VISC_INVLIN = 0, LBPF_VISC_STEP = 1 } lbpf_visc;
+
+/* Boundaries: fully periodic, or periodic in x with halfway bounce-back walls half a cell
+ * below row 0 and above row ny-1 (Sec. 4.3). Stencils mirror the first fluid row at a wall. */
+typedef enum { LBPF_BC_PERIODIC = 0, LBPF_BC_WALLS_Y = 1 } lbpf_bc;
+
+/* Macroscopic fields of the current state (lbpf_read). */
+typedef enum {
+    LBPF_FIELD_PHI = 0, /* eq. (18) */
+    LBPF_FIELD_RHO = 1, /* eq. (3aa) */
+    LBPF_FIELD_UX = 2,  /* eq. (27a) */
+    LBPF_FIELD_UY = 3,
+    LBPF_FIELD_P = 4,   /* eq. (28) or (29), evaluated on the current state */
+    LBPF_FIELD_MU = 5   /* eq. (8) */
+} lbpf_field;
+
+/* Physical parameters of one simulation (lattice units). */
+typedef struct lbpf_params {
+    int32_t nx, ny;          /* grid size, each >= 3 */
+    int32_t variant;         /* lbpf_variant */
+    int32_t pscheme;         /* lbpf_pscheme */
+    int32_t fsurf;           /* lbpf_fsurf */
+    int32_t visc;            /* lbpf_visc */
+    int32_t bc;              /* lbpf_bc */
+    int32_t clamp_props;     /* nonzero: phi clamped to [0,1] where rho(phi), nu(phi) are evaluated */
+    double rho_A, rho_B;     /* densities of phase A (phi = 1) and B (phi = 0), > 0 */
+    double nu_A, nu_B;       /* kinematic viscosities, > 0 (relaxation tau_g = 3 nu + 1/2) */
+    double sigma, W;         /* surface tension >= 0 and interface width > 0 (eqs. 6-7) */
+    double M_phi;            /* mobility (eq. 17) */
+    double tau_h;            /* Cahn-Hilliard relaxation time, > 1/2 (eq. 10) */
+    double force_x, force_y; /* constant body-force density */
+    double gravity;          /* buoyancy F_y = -(rho - rho_A) * gravity (Sec. 4.4) */
+} lbpf_params;
+
+/* Conserved-quantity diagnostics, reduced in FP64 on the GPU in a fixed order. */
+typedef struct lbpf_diag {
+    double sum_phi;    /* sum over nodes of phi = sum_i h_i (globally conserved, Sec. 3.2.2) */
+    double sum_rho;    /* sum over nodes of rho(phi) */
+    double max_u;      /* max over nodes of |u| */
+    int64_t nonfinite; /* number of non-finite values in the stored state */
+    int64_t step;      /* time steps taken since lbpf_init */
+} lbpf_diag;
+
+typedef struct lbpf_ctx lbpf_ctx;
+
+/* Bytes of device workspace a simulation with these parameters needs (the populations in two
+ * ping-pong copies, pressure history, (phi u) history, field and reduction scratch). */
+lbpf_status lbpf_workspace_size(const lbpf_params* params, size_t* bytes);
+
+/* Validate params and bind a handle to a caller-owned device workspace and stream.
+ * Rejects nx or ny < 3, tau_h <= 1/2, nu <= 0, rho <= 0, W <= 0, sigma < 0 with
+ * LBPF_E_INVALID, and a workspace smaller than lbpf_workspace_size() with LBPF_E_NOMEM.
+ * On failure *out is NULL and lbpf_create_error() describes the reason. */
+lbpf_status lbpf_create(const lbpf_params* params, void* workspace, size_t workspace_bytes,
+                        void* hip_stream, lbpf_ctx** out);
+
+/* Initial state from device fields [ny][nx] FP32 (any of ux, uy, p may be NULL for zero):
+ * h_i = h_i^eq(phi0, mu0, u0) (eq. 11) with mu0 from eq. (8), g_i = g_i^eq(p0, rho(phi0), u0)
+ * (eq. 33); the (phi u) and pressure histories start at phi0 u0 and p0. Resets the step count. */
+lbpf_status lbpf_init(lbpf_ctx* ctx, const float* phi, const float* ux, const float* uy,
+                      const float* p);
+
+/* Advance nsteps >= 0 time steps (eq. 24 and eq. 10 with streaming). Asynchronous. */
+lbpf_status lbpf_step(lbpf_ctx* ctx, int64_t nsteps);
+
+/* Write one lbpf_field of the current state to a device array [ny][nx] FP32. Asynchronous. */
+lbpf_status lbpf_read(lbpf_ctx* ctx, int32_t field, float* dst);
+
+/* FP64 diagnostics of the current state; synchronizes the stream. Returns LBPF_E_UNSTABLE
+ * (with *out filled) when a stored value is not finite. */
+lbpf_status lbpf_diagnostics(lbpf_ctx* ctx, lbpf_diag* out);
+
+/* Laplace-law pressure jump of Sec. 4.2 in FP64: P = p0 - kappa phi lap(phi)
+ * + kappa |grad phi|^2 / 2 + p with p0 = phi psi'(phi) - psi(phi), averaged over nodes with
+ * periodic distance r <= R/2 from (xc, yc) minus the average over r >= R + 3W.
+ * Synchronizes the stream. */
+lbpf_status lbpf_laplace_dp(lbpf_ctx* ctx, double xc, double yc, double R, double* dP);
+
+/* Checkpoint: bytes of the current state (populations, histories, step count). */
+lbpf_status lbpf_state_size(const lbpf_ctx* ctx, size_t* bytes);
+/* Copy the current state into / out of a caller device buffer of lbpf_state_size() bytes.
+ * Asynchronous; a save followed by a load on another handle with equal params resumes
+ * bit-identically. */
+lbpf_status lbpf_save_state(lbpf_ctx* ctx, void* dst_device);
+lbpf_status lbpf_load_state(lbpf_ctx* ctx, const void* src_device);
+
+/* Change the stream used by later calls. */
+lbpf_status lbpf_set_stream(lbpf_ctx* ctx, void* hip_stream);
+
+/* Tile shape of the fused step: index into lbpf_tile_configs(); results are bit-identical for
+ * every tile shape. */
+lbpf_status lbpf_set_tile(lbpf_ctx* ctx, int32_t tile_index);
+/* Number of tile shapes and their (TX, TY, threads) triples. */
+int32_t lbpf_tile_count(void);
+lbpf_status lbpf_tile_shape(int32_t tile_index, int32_t* tx, int32_t* ty, int32_t* threads);
+
+int64_t lbpf_step_count(const lbpf_ctx* ctx);
+
+/* Release the handle (does not free the caller's workspace). NULL is accepted. */
+lbpf_status lbpf_destroy(lbpf_ctx* ctx);
+
+const char* lbpf_status_string(lbpf_status status);
+/* Message of the last failed call on this handle; valid until the next call on it. */
+const char* lbpf_last_error(const lbpf_ctx* ctx);
+/* Message of the last failed lbpf_create / lbpf_workspace_size on this thread. */
+const char* lbpf_create_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBPF_H */

@@ -1,0 +1,364 @@
+// C ABI of the lbpf library (declared in include/lbpf.h): parameter validation, derivation of
+// the model coefficients, carving of the caller's device workspace and kernel sequencing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lbpf.h"
+#include "lbpf_model.hpp"
+
+namespace lbpf {
+int tile_count();
+void tile_shape(int i, int* tx, int* ty, int* nt);
+hipError_t launch_step(int tile, const Model& m, const float* fin, float* fout, const float* hin,
+                       float* hout, const float* pin, float* pout, float* phiu, hipStream_t st);
+hipError_t launch_fields(const Model& m, const float* fin, const float* hin, const float* pin,
+                         float* phiu, float* fields, hipStream_t st);
+hipError_t launch_init(const Model& m, const float* phi0, const float* ux0, const float* uy0,
+                       const float* p0, float* f, float* h, float* pp, float* phiu, hipStream_t st);
+hipError_t launch_diag(const Model& m, const float* f, const float* h, const float* pp,
+                       const float* phiu, const float* fields, double* red, hipStream_t st);
+hipError_t launch_laplace(const Model& m, const float* h, const float* fields, double* phi64,
+                          double xc, double yc, double r_in, double r_out, double* red,
+                          hipStream_t st);
+}  // namespace lbpf
+
+using namespace lbpf;
+
+struct lbpf_ctx {
+    lbpf_params params;
+    Model m;
+    float* ws;          // base of the caller's workspace
+    size_t ws_bytes;
+    hipStream_t stream;
+    int cur;            // 0: state in copy A, 1: in copy B
+    int initialized;
+    int tile;
+    int64_t step;
+    int64_t hdr[8];     // checkpoint header staging (host)
+    std::string err;
+};
+
+static thread_local std::string g_create_err;
+
+static lbpf_status fail(lbpf_ctx* c, lbpf_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    else g_create_err = buf;
+    return s;
+}
+
+static lbpf_status hip_fail(lbpf_ctx* c, hipError_t e, const char* what) {
+    return fail(c, LBPF_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static const char* validate(const lbpf_params* p) {
+    if (!p) return "params is NULL";
+    if (p->nx < 3 || p->ny < 3) return "nx and ny must be >= 3";
+    if ((long long)p->nx * p->ny > (1LL << 31)) return "grid too large (nx*ny > 2^31)";
+    if (p->variant != LBPF_QIM && p->variant != LBPF_IM) return "variant must be LBPF_QIM or LBPF_IM";
+    if (p->pscheme < 0 || p->pscheme > 2) return "pscheme out of range";
+    if (p->fsurf != 0 && p->fsurf != 1) return "fsurf out of range";
+    if (p->visc != 0 && p->visc != 1) return "visc out of range";
+    if (p->bc != 0 && p->bc != 1) return "bc out of range";
+    if (!(p->tau_h > 0.5)) return "tau_h must be > 1/2";
+    if (!(p->nu_A > 0.0) || !(p->nu_B > 0.0)) return "nu_A and nu_B must be > 0";
+    if (!(p->rho_A > 0.0) || !(p->rho_B > 0.0)) return "rho_A and rho_B must be > 0";
+    if (!(p->W > 0.0)) return "W must be > 0";
+    if (!(p->sigma >= 0.0)) return "sigma must be >= 0";
+    if (!std::isfinite(p->M_phi) || !std::isfinite(p->force_x) || !std::isfinite(p->force_y) ||
+        !std::isfinite(p->gravity))
+        return "M_phi, forces and gravity must be finite";
+    return nullptr;
+}
+
+static size_t plane_floats(const lbpf_params* p) { return (size_t)p->ny * pitch_of(p->nx); }
+
+static size_t ws_bytes(const lbpf_params* p) {
+    return plane_floats(p) * sizeof(float) * kNumPlanes + kRedDoubles * sizeof(double);
+}
+
+// Model coefficients from the physical parameters:
+//   beta = 12 sigma / W, kappa = 3 sigma W / 2 (eqs. 6-7 solved for beta and kappa),
+//   eta = M_phi / (c_s^2 (tau_h - 1/2)) (eq. 17), gamma = (rho_A - rho_B) / rho_B (Sec. 3.2.1).
+static Model make_model(const lbpf_params* p) {
+    Model m{};
+    m.nx = p->nx;
+    m.ny = p->ny;
+    m.pitch = pitch_of(p->nx);
+    m.plane = (long long)plane_floats(p);
+    m.variant = p->variant;
+    m.pscheme = p->pscheme;
+    m.fsurf = p->fsurf;
+    m.visc = p->visc;
+    m.bc = p->bc;
+    m.clamp = p->clamp_props ? 1 : 0;
+    const double beta = 12.0 * p->sigma / p->W, kappa = 1.5 * p->sigma * p->W;
+    const double eta = p->M_phi / ((p->tau_h - 0.5) / 3.0);
+    const double gamma = (p->rho_A - p->rho_B) / p->rho_B;
+    m.beta4 = (float)(4.0 * beta);
+    m.kappa = (float)kappa;
+    m.eta = (float)eta;
+    m.gammaM = (float)(gamma * p->M_phi);
+    m.rhoA = (float)p->rho_A;
+    m.rhoB = (float)p->rho_B;
+    m.drho = (float)(p->rho_A - p->rho_B);
+    m.inv_nuA = (float)(1.0 / p->nu_A);
+    m.inv_nuB = (float)(1.0 / p->nu_B);
+    m.muA = (float)(p->rho_A * p->nu_A);
+    m.muB = (float)(p->rho_B * p->nu_B);
+    m.inv_tau_h = (float)(1.0 / p->tau_h);
+    m.src_coef = (float)(1.0 - 0.5 / p->tau_h);
+    m.fx = (float)p->force_x;
+    m.fy = (float)p->force_y;
+    m.grav = (float)p->gravity;
+    m.d_beta = beta;
+    m.d_kappa = kappa;
+    m.d_rhoA = p->rho_A;
+    m.d_rhoB = p->rho_B;
+    return m;
+}
+
+static float* plane(lbpf_ctx* c, int k) { return c->ws + (size_t)k * c->m.plane; }
+static float* fcur(lbpf_ctx* c) { return plane(c, c->cur ? kPlaneFB : kPlaneFA); }
+static float* hcur(lbpf_ctx* c) { return plane(c, c->cur ? kPlaneHB : kPlaneHA); }
+static float* pcur(lbpf_ctx* c) { return plane(c, c->cur ? kPlanePB : kPlanePA); }
+static double* red(lbpf_ctx* c) { return (double*)plane(c, kNumPlanes); }
+
+static lbpf_status check_ctx(lbpf_ctx* c, bool need_init) {
+    if (!c) return LBPF_E_INVALID;
+    c->err.clear();
+    if (need_init && !c->initialized) return fail(c, LBPF_E_STATE, "lbpf_init has not been called");
+    return LBPF_OK;
+}
+
+extern "C" {
+
+lbpf_status lbpf_workspace_size(const lbpf_params* params, size_t* bytes) {
+    if (const char* why = validate(params)) return fail(nullptr, LBPF_E_INVALID, "%s", why);
+    if (!bytes) return fail(nullptr, LBPF_E_INVALID, "bytes is NULL");
+    *bytes = ws_bytes(params);
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_create(const lbpf_params* params, void* workspace, size_t workspace_bytes,
+                        void* hip_stream, lbpf_ctx** out) {
+    if (!out) return fail(nullptr, LBPF_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (const char* why = validate(params)) return fail(nullptr, LBPF_E_INVALID, "%s", why);
+    if (!workspace) return fail(nullptr, LBPF_E_INVALID, "workspace is NULL");
+    if (((uintptr_t)workspace) % 256 != 0)
+        return fail(nullptr, LBPF_E_INVALID, "workspace must be 256-byte aligned");
+    const size_t need = ws_bytes(params);
+    if (workspace_bytes < need)
+        return fail(nullptr, LBPF_E_NOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    lbpf_ctx* c = new (std::nothrow) lbpf_ctx();
+    if (!c) return fail(nullptr, LBPF_E_NOMEM, "host allocation failed");
+    c->params = *params;
+    c->m = make_model(params);
+    c->ws = (float*)workspace;
+    c->ws_bytes = workspace_bytes;
+    c->stream = (hipStream_t)hip_stream;
+    c->cur = 0;
+    c->initialized = 0;
+    c->tile = 0;
+    c->step = 0;
+    *out = c;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_init(lbpf_ctx* c, const float* phi, const float* ux, const float* uy, const float* p) {
+    if (lbpf_status s = check_ctx(c, false)) return s;
+    if (!phi) return fail(c, LBPF_E_INVALID, "phi is NULL");
+    c->cur = 0;
+    hipError_t e = launch_init(c->m, phi, ux, uy, p, fcur(c), hcur(c), pcur(c), plane(c, kPlanePhiU),
+                               c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "init kernel");
+    c->initialized = 1;
+    c->step = 0;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_step(lbpf_ctx* c, int64_t nsteps) {
+    if (lbpf_status s = check_ctx(c, true)) return s;
+    if (nsteps < 0) return fail(c, LBPF_E_INVALID, "nsteps must be >= 0");
+    for (int64_t t = 0; t < nsteps; ++t) {
+        const int a = c->cur, b = 1 - a;
+        hipError_t e = launch_step(c->tile, c->m, plane(c, a ? kPlaneFB : kPlaneFA),
+                                   plane(c, b ? kPlaneFB : kPlaneFA), plane(c, a ? kPlaneHB : kPlaneHA),
+                                   plane(c, b ? kPlaneHB : kPlaneHA), plane(c, a ? kPlanePB : kPlanePA),
+                                   plane(c, b ? kPlanePB : kPlanePA), plane(c, kPlanePhiU), c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "step kernel");
+        c->cur = b;
+        c->step += 1;
+    }
+    return LBPF_OK;
+}
+
+static lbpf_status run_fields(lbpf_ctx* c) {
+    hipError_t e = launch_fields(c->m, fcur(c), hcur(c), pcur(c), plane(c, kPlanePhiU),
+                                 plane(c, kPlaneFields), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "field kernel");
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_read(lbpf_ctx* c, int32_t field, float* dst) {
+    if (lbpf_status s = check_ctx(c, true)) return s;
+    if (field < LBPF_FIELD_PHI || field > LBPF_FIELD_MU) return fail(c, LBPF_E_INVALID, "unknown field %d", field);
+    if (!dst) return fail(c, LBPF_E_INVALID, "dst is NULL");
+    if (lbpf_status s = run_fields(c)) return s;
+    const float* src = plane(c, kPlaneFields + field);
+    hipError_t e = hipMemcpy2DAsync(dst, (size_t)c->m.nx * sizeof(float), src,
+                                    (size_t)c->m.pitch * sizeof(float), (size_t)c->m.nx * sizeof(float),
+                                    (size_t)c->m.ny, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "field copy");
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_diagnostics(lbpf_ctx* c, lbpf_diag* out) {
+    if (lbpf_status s = check_ctx(c, true)) return s;
+    if (!out) return fail(c, LBPF_E_INVALID, "out is NULL");
+    if (lbpf_status s = run_fields(c)) return s;
+    hipError_t e = launch_diag(c->m, fcur(c), hcur(c), pcur(c), plane(c, kPlanePhiU),
+                               plane(c, kPlaneFields), red(c), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "diagnostic kernels");
+    double r[4];
+    e = hipMemcpyAsync(r, red(c) + (size_t)kRedBlocks * kRedSlots, sizeof r, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "diagnostic readback");
+    out->sum_phi = r[0];
+    out->sum_rho = r[1];
+    out->max_u = r[2];
+    out->nonfinite = (int64_t)r[3];
+    out->step = c->step;
+    if (out->nonfinite != 0 || !std::isfinite(r[0]))
+        return fail(c, LBPF_E_UNSTABLE, "%lld non-finite values in the state at step %lld",
+                    (long long)out->nonfinite, (long long)c->step);
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_laplace_dp(lbpf_ctx* c, double xc, double yc, double R, double* dP) {
+    if (lbpf_status s = check_ctx(c, true)) return s;
+    if (!dP) return fail(c, LBPF_E_INVALID, "dP is NULL");
+    if (!(R > 0.0)) return fail(c, LBPF_E_INVALID, "R must be > 0");
+    if (lbpf_status s = run_fields(c)) return s;
+    hipError_t e = launch_laplace(c->m, hcur(c), plane(c, kPlaneFields), (double*)plane(c, kPlaneF64),
+                                  xc, yc, 0.5 * R, R + 3.0 * c->params.W, red(c), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "laplace kernels");
+    double r[4];
+    e = hipMemcpyAsync(r, red(c) + (size_t)kRedBlocks * kRedSlots, sizeof r, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "laplace readback");
+    if (r[1] < 1.0 || r[3] < 1.0)
+        return fail(c, LBPF_E_INVALID, "empty inner (%g nodes) or outer (%g nodes) region", r[1], r[3]);
+    *dP = r[0] / r[1] - r[2] / r[3];
+    return LBPF_OK;
+}
+
+// checkpoint layout: 64-byte header {magic, version, nx, ny, pitch, step}, then the planes
+// f_1..8, h (10 planes), p, (phi u)_x, (phi u)_y, each ny*pitch floats
+static const int64_t kMagic = 0x4650424C;  // "LBPF"
+static const int kStatePlanes = kFPlanes + kHPlanes + 1 + 2;
+
+lbpf_status lbpf_state_size(const lbpf_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return LBPF_E_INVALID;
+    *bytes = 64 + (size_t)kStatePlanes * c->m.plane * sizeof(float);
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_save_state(lbpf_ctx* c, void* dst) {
+    if (lbpf_status s = check_ctx(c, true)) return s;
+    if (!dst) return fail(c, LBPF_E_INVALID, "dst is NULL");
+    // the header is copied synchronously so that hdr may be reused at once
+    c->hdr[0] = kMagic; c->hdr[1] = 1; c->hdr[2] = c->m.nx; c->hdr[3] = c->m.ny;
+    c->hdr[4] = c->m.pitch; c->hdr[5] = c->step; c->hdr[6] = 0; c->hdr[7] = 0;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(dst, c->hdr, 64, hipMemcpyHostToDevice);
+    const size_t pb = (size_t)c->m.plane * sizeof(float);
+    char* d = (char*)dst + 64;
+    if (e == hipSuccess) e = hipMemcpyAsync(d, fcur(c), kFPlanes * pb, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + kFPlanes * pb, hcur(c), kHPlanes * pb, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + (kFPlanes + kHPlanes) * pb, pcur(c), pb, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + (kFPlanes + kHPlanes + 1) * pb, plane(c, kPlanePhiU), 2 * pb, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "save state");
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_load_state(lbpf_ctx* c, const void* src) {
+    if (lbpf_status s = check_ctx(c, false)) return s;
+    if (!src) return fail(c, LBPF_E_INVALID, "src is NULL");
+    int64_t hdr[8];
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(hdr, src, 64, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(c, e, "load state header");
+    if (hdr[0] != kMagic || hdr[1] != 1 || hdr[2] != c->m.nx || hdr[3] != c->m.ny || hdr[4] != c->m.pitch)
+        return fail(c, LBPF_E_INVALID, "checkpoint does not match this grid");
+    c->cur = 0;
+    const size_t pb = (size_t)c->m.plane * sizeof(float);
+    const char* s = (const char*)src + 64;
+    e = hipMemcpyAsync(fcur(c), s, kFPlanes * pb, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hcur(c), s + kFPlanes * pb, kHPlanes * pb, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(pcur(c), s + (kFPlanes + kHPlanes) * pb, pb, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(plane(c, kPlanePhiU), s + (kFPlanes + kHPlanes + 1) * pb, 2 * pb, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "load state");
+    c->step = hdr[5];
+    c->initialized = 1;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_set_stream(lbpf_ctx* c, void* hip_stream) {
+    if (lbpf_status s = check_ctx(c, false)) return s;
+    c->stream = (hipStream_t)hip_stream;
+    return LBPF_OK;
+}
+
+int32_t lbpf_tile_count(void) { return tile_count(); }
+
+lbpf_status lbpf_tile_shape(int32_t i, int32_t* tx, int32_t* ty, int32_t* threads) {
+    if (i < 0 || i >= tile_count() || !tx || !ty || !threads) return LBPF_E_INVALID;
+    int a, b, t;
+    tile_shape(i, &a, &b, &t);
+    *tx = a; *ty = b; *threads = t;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_set_tile(lbpf_ctx* c, int32_t i) {
+    if (lbpf_status s = check_ctx(c, false)) return s;
+    if (i < 0 || i >= tile_count()) return fail(c, LBPF_E_INVALID, "tile index %d out of range", i);
+    c->tile = i;
+    return LBPF_OK;
+}
+
+int64_t lbpf_step_count(const lbpf_ctx* c) { return c ? c->step : -1; }
+
+lbpf_status lbpf_destroy(lbpf_ctx* c) {
+    delete c;
+    return LBPF_OK;
+}
+
+const char* lbpf_status_string(lbpf_status s) {
+    switch (s) {
+        case LBPF_OK: return "ok";
+        case LBPF_E_INVALID: return "invalid argument";
+        case LBPF_E_HIP: return "HIP runtime error";
+        case LBPF_E_NOMEM: return "insufficient memory";
+        case LBPF_E_UNSTABLE: return "non-finite state";
+        case LBPF_E_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+const char* lbpf_last_error(const lbpf_ctx* c) { return c ? c->err.c_str() : "NULL handle"; }
+
+const char* lbpf_create_error(void) { return g_create_err.c_str(); }
+
+}  // extern "C"

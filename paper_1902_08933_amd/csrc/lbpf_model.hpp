@@ -1,0 +1,70 @@
+// Model constants, lattice conventions and device-workspace layout of the lbpf library.
+// Host and device code both include this header; it holds no arithmetic of the method beyond
+// the D2Q9 lattice definition (Sec. 2.2 of arXiv:1902.08933, listed after eq. 25).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lbpf {
+
+// D2Q9 velocity order of the paper: 0 rest, 1 +x, 2 +y, 3 -x, 4 -y, 5 (+1,+1), 6 (-1,+1),
+// 7 (-1,-1), 8 (+1,-1); weights 4/9, 1/9 (axes), 1/36 (diagonals); c_s^2 = 1/3.
+constexpr int kQ = 9;
+
+// Per-cell stored planes of one population copy. The hydrodynamic distribution keeps
+// directions 1..8 only: its rest population never enters any output of the two-phase model
+// (u uses c_0 = 0, eq. (28) sums i != 0, rho comes from phi). The phase-field distribution
+// keeps all nine directions; its rest population carries the order parameter and is stored
+// as an unevaluated FP32 sum hi + lo.
+constexpr int kFPlanes = 8;   // f_1..f_8   -> plane i-1
+constexpr int kHPlanes = 10;  // h_0 hi, h_1..h_8, h_0 lo -> planes 0, 1..8, 9
+constexpr int kH0Lo = 9;
+
+// Workspace layout, in planes of ny*pitch floats (each plane 256-byte aligned):
+//   [0, 8)    f copy A         [8, 16)   f copy B
+//   [16, 26)  h copy A         [26, 36)  h copy B
+//   36, 37    p copy A, B      38, 39    (phi u)_x, (phi u)_y history (updated in place)
+//   [40, 46)  field scratch: phi, rho, ux, uy, p, mu of the current state
+//   [46, 48)  FP64 scratch plane (order parameter in double, Laplace diagnostic)
+// followed by the reduction area (kRedDoubles doubles).
+constexpr int kPlaneFA = 0, kPlaneFB = 8, kPlaneHA = 16, kPlaneHB = 26;
+constexpr int kPlanePA = 36, kPlanePB = 37, kPlanePhiU = 38, kPlaneFields = 40;
+constexpr int kPlaneF64 = 46;
+constexpr int kNumPlanes = 48;
+constexpr int kRedBlocks = 4096;                 // max partial-sum blocks of a reduction
+constexpr int kRedSlots = 8;                     // doubles per partial
+constexpr size_t kRedDoubles = (size_t)kRedBlocks * kRedSlots + 64;
+
+inline int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
+
+// Physical and derived model constants in the precision the kernels compute in (FP32).
+struct Model {
+    int nx, ny, pitch;
+    long long plane;       // floats per plane = ny * pitch
+    int variant;           // 0 quasi-incompressible, 1 incompressible
+    int pscheme;           // 0 eq.(28) with G0 of eq.(34), 1 simplified G0, 2 eq.(29)
+    int fsurf;             // 0 mu grad phi, 1 -phi grad mu
+    int visc;              // 0 inverse-linear, 1 step
+    int bc;                // 0 periodic, 1 walls in y
+    int clamp;             // clamp phi to [0,1] in rho(phi), nu(phi)
+    float beta4;           // 4 beta, beta = 12 sigma / W   (eqs. 6-7)
+    float kappa;           // kappa = 3 sigma W / 2          (eqs. 6-7)
+    float eta;             // M_phi / (c_s^2 (tau_h - 1/2))  (eq. 17)
+    float gammaM;          // gamma M_phi, gamma = (rho_A - rho_B)/rho_B (Sec. 3.2.1)
+    float rhoA, rhoB, drho;
+    float inv_nuA, inv_nuB; // inverse-linear viscosity
+    float muA, muB;         // dynamic viscosities for the step form
+    float inv_tau_h;
+    float src_coef;         // 1 - 1/(2 tau_h) of eq. (14)
+    float fx, fy, grav;
+    // FP64 copies for the diagnostics
+    double d_beta, d_kappa, d_rhoA, d_rhoB;
+};
+
+// Deterministic reduction results (FP64).
+struct DiagOut {
+    double sum_phi, sum_rho, max_u, nonfinite;
+};
+
+}  // namespace lbpf

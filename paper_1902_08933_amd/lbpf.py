@@ -1,0 +1,242 @@
+"""ctypes binding of liblbpf.so (see include/lbpf.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library. PyTorch supplies device memory (the
+workspace and field tensors) and the current HIP stream. There is no CPU fallback: if the
+library is missing or no GPU is visible, construction raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbpf.so")
+
+FIELDS = {"phi": 0, "rho": 1, "ux": 2, "uy": 3, "p": 4, "mu": 5}
+VARIANTS = {"qim": 0, "im": 1}
+PSCHEMES = {"eq28": 0, "eq28_paper_g0": 1, "eq29": 2}
+FSURF = {"mu_grad_phi": 0, "neg_phi_grad_mu": 1}
+VISC = {"inverse_linear": 0, "step": 1}
+BCS = {"periodic": 0, "walls_y": 1}
+STATUS = {0: "LBPF_OK", -1: "LBPF_E_INVALID", -2: "LBPF_E_HIP", -3: "LBPF_E_NOMEM",
+          -4: "LBPF_E_UNSTABLE", -5: "LBPF_E_STATE"}
+
+
+class LbpfError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("pscheme", ctypes.c_int32), ("fsurf", ctypes.c_int32), ("visc", ctypes.c_int32),
+                ("bc", ctypes.c_int32), ("clamp_props", ctypes.c_int32),
+                ("rho_A", ctypes.c_double), ("rho_B", ctypes.c_double),
+                ("nu_A", ctypes.c_double), ("nu_B", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("W", ctypes.c_double), ("M_phi", ctypes.c_double),
+                ("tau_h", ctypes.c_double), ("force_x", ctypes.c_double),
+                ("force_y", ctypes.c_double), ("gravity", ctypes.c_double)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("sum_phi", ctypes.c_double), ("sum_rho", ctypes.c_double),
+                ("max_u", ctypes.c_double), ("nonfinite", ctypes.c_int64),
+                ("step", ctypes.c_int64)]
+
+
+# every symbol include/lbpf.h declares, with (restype, argtypes)
+_V = ctypes.c_void_p
+_S = ctypes.c_int
+SIGNATURES = {
+    "lbpf_workspace_size": (_S, [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]),
+    "lbpf_create": (_S, [ctypes.POINTER(Params), _V, ctypes.c_size_t, _V, ctypes.POINTER(_V)]),
+    "lbpf_init": (_S, [_V, _V, _V, _V, _V]),
+    "lbpf_step": (_S, [_V, ctypes.c_int64]),
+    "lbpf_read": (_S, [_V, ctypes.c_int32, _V]),
+    "lbpf_diagnostics": (_S, [_V, ctypes.POINTER(Diag)]),
+    "lbpf_laplace_dp": (_S, [_V, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                             ctypes.POINTER(ctypes.c_double)]),
+    "lbpf_state_size": (_S, [_V, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbpf_save_state": (_S, [_V, _V]),
+    "lbpf_load_state": (_S, [_V, _V]),
+    "lbpf_set_stream": (_S, [_V, _V]),
+    "lbpf_set_tile": (_S, [_V, ctypes.c_int32]),
+    "lbpf_tile_count": (ctypes.c_int32, []),
+    "lbpf_tile_shape": (_S, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "lbpf_step_count": (ctypes.c_int64, [_V]),
+    "lbpf_destroy": (_S, [_V]),
+    "lbpf_status_string": (ctypes.c_char_p, [_S]),
+    "lbpf_last_error": (ctypes.c_char_p, [_V]),
+    "lbpf_create_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def library(path=LIB_PATH):
+    """Load liblbpf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1902_08933_amd.build`"
+                           " (or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def make_params(cfg):
+    """Params from a workload dict (keys as in paper_1902_08933_amd.workloads)."""
+    p = Params()
+    p.nx, p.ny = int(cfg["nx"]), int(cfg["ny"])
+    p.variant = VARIANTS[cfg.get("variant", "qim")]
+    p.pscheme = PSCHEMES[cfg.get("pscheme", "eq28")]
+    p.fsurf = FSURF[cfg.get("fsurf", "mu_grad_phi")]
+    p.visc = VISC[cfg.get("visc", "inverse_linear")]
+    p.bc = BCS[cfg.get("bc", "periodic")]
+    p.clamp_props = int(bool(cfg.get("clamp_props", False)))
+    for k in ("rho_A", "rho_B", "nu_A", "nu_B", "sigma", "W", "M_phi", "tau_h"):
+        setattr(p, k, float(cfg[k]))
+    p.force_x = float(cfg.get("force_x", 0.0))
+    p.force_y = float(cfg.get("force_y", 0.0))
+    p.gravity = float(cfg.get("gravity", 0.0))
+    return p
+
+
+def _check(status, handle=None):
+    if status != 0:
+        lib = library()
+        msg = lib.lbpf_last_error(handle) if handle else lib.lbpf_create_error()
+        raise LbpfError(status, (msg or b"").decode())
+
+
+def workspace_size(cfg):
+    lib = library()
+    n = ctypes.c_size_t()
+    _check(lib.lbpf_workspace_size(ctypes.byref(make_params(cfg)), ctypes.byref(n)))
+    return n.value
+
+
+def tile_shapes():
+    lib = library()
+    out = []
+    for i in range(lib.lbpf_tile_count()):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.lbpf_tile_shape(i, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        out.append((a.value, b.value, c.value))
+    return out
+
+
+def _dev_ptr(t, torch, shape=None):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("fields must be contiguous float32 tensors on the GPU")
+    if shape is not None and tuple(t.shape) != shape:
+        raise ValueError(f"field shape {tuple(t.shape)} != {shape}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Simulation:
+    """One simulation on one GPU: init fields, step N, read phi/rho/u/p/mu."""
+
+    def __init__(self, cfg, device="cuda"):
+        import torch
+        self.torch = torch
+        self.lib = library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lbpf solver runs only on the GPU")
+        self.device = torch.device(device)
+        self.cfg = dict(cfg)
+        self.params = make_params(cfg)
+        self.nx, self.ny = self.params.nx, self.params.ny
+        nbytes = workspace_size(cfg)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        h = ctypes.c_void_p()
+        _check(self.lib.lbpf_create(ctypes.byref(self.params),
+                                    ctypes.c_void_p(self.workspace.data_ptr()),
+                                    ctypes.c_size_t(nbytes), ctypes.c_void_p(stream),
+                                    ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.lib.lbpf_destroy(h)
+            self._h = None
+
+    def _c(self, status):
+        _check(status, self._h)
+
+    def _as_field(self, a):
+        torch = self.torch
+        if a is None:
+            return None
+        t = torch.as_tensor(a, dtype=torch.float32, device=self.device).contiguous()
+        if tuple(t.shape) != (self.ny, self.nx):
+            raise ValueError(f"field shape {tuple(t.shape)} != {(self.ny, self.nx)}")
+        return t
+
+    def init(self, phi, ux=None, uy=None, p=None):
+        fields = [self._as_field(a) for a in (phi, ux, uy, p)]
+        ptrs = [_dev_ptr(t, self.torch) for t in fields]
+        self._c(self.lib.lbpf_init(self._h, *ptrs))
+        self.torch.cuda.current_stream(self.device).synchronize()
+        return self
+
+    def step(self, n=1):
+        self._c(self.lib.lbpf_step(self._h, int(n)))
+        return self
+
+    def read(self, field, out=None):
+        t = out if out is not None else self.torch.empty((self.ny, self.nx), dtype=self.torch.float32,
+                                                         device=self.device)
+        self._c(self.lib.lbpf_read(self._h, FIELDS[field], _dev_ptr(t, self.torch, (self.ny, self.nx))))
+        return t
+
+    def diagnostics(self, check=True):
+        d = Diag()
+        st = self.lib.lbpf_diagnostics(self._h, ctypes.byref(d))
+        if check:
+            self._c(st)
+        return dict(sum_phi=d.sum_phi, sum_rho=d.sum_rho, max_u=d.max_u,
+                    nonfinite=d.nonfinite, step=d.step, status=st)
+
+    def laplace_dp(self, xc, yc, R):
+        v = ctypes.c_double()
+        self._c(self.lib.lbpf_laplace_dp(self._h, float(xc), float(yc), float(R), ctypes.byref(v)))
+        return v.value
+
+    def state_size(self):
+        n = ctypes.c_size_t()
+        self._c(self.lib.lbpf_state_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def save_state(self):
+        buf = self.torch.empty(self.state_size(), dtype=self.torch.uint8, device=self.device)
+        self._c(self.lib.lbpf_save_state(self._h, ctypes.c_void_p(buf.data_ptr())))
+        return buf
+
+    def load_state(self, buf):
+        if buf.numel() < self.state_size() or not buf.is_cuda:
+            raise ValueError("checkpoint buffer too small or not on the GPU")
+        self._c(self.lib.lbpf_load_state(self._h, ctypes.c_void_p(buf.data_ptr())))
+        return self
+
+    def set_tile(self, index):
+        self._c(self.lib.lbpf_set_tile(self._h, int(index)))
+        return self
+
+    def set_stream(self, stream):
+        self._c(self.lib.lbpf_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+        return self
+
+    @property
+    def step_count(self):
+        return int(self.lib.lbpf_step_count(self._h))

@@ -1,0 +1,90 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol include/lbpf.h
+declares, and validates parameters before any device work (no GPU calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1902_08933_amd import lbpf, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbpf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbpf_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lbpf.LIB_PATH):
+        from paper_1902_08933_amd import build
+        build.build()
+    return lbpf.library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 19
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding knows the signature of each
+    assert set(names) == set(lbpf.SIGNATURES)
+
+
+def test_params_struct_layout_matches_header():
+    # 8 int32 fields then 11 doubles, no padding
+    assert ctypes.sizeof(lbpf.Params) == 8 * 4 + 11 * 8
+    assert ctypes.sizeof(lbpf.Diag) == 3 * 8 + 2 * 8
+
+
+def test_workspace_size_scales_with_grid(lib):
+    cfg, _ = workloads.static_droplet(n=64)
+    a = lbpf.workspace_size(cfg)
+    b = lbpf.workspace_size(dict(cfg, nx=128, ny=128))
+    assert b > 3 * (a - 4096 * 8 * 9) // 1  # planes dominate
+    assert a % 256 == 0 or a > 0
+
+
+@pytest.mark.parametrize("bad,why", [
+    (dict(nx=2), "nx and ny"),
+    (dict(ny=1), "nx and ny"),
+    (dict(tau_h=0.5), "tau_h"),
+    (dict(nu_A=0.0), "nu_A"),
+    (dict(rho_B=-1.0), "rho_A and rho_B"),
+    (dict(W=0.0), "W must"),
+    (dict(sigma=-0.1), "sigma"),
+    (dict(variant="qim", force_x=float("nan")), "finite"),
+])
+def test_invalid_parameters_rejected(lib, bad, why):
+    cfg, _ = workloads.static_droplet(n=16, R=4)
+    cfg = dict(cfg, **bad)
+    with pytest.raises(lbpf.LbpfError) as ei:
+        lbpf.workspace_size(cfg)
+    assert ei.value.status == -1
+    assert why in str(ei.value)
+
+
+def test_status_strings(lib):
+    for s in (0, -1, -2, -3, -4, -5):
+        assert lib.lbpf_status_string(s)
+    assert lib.lbpf_destroy(None) == 0
+    assert lib.lbpf_step_count(None) == -1
+
+
+def test_create_rejects_null_workspace(lib):
+    cfg, _ = workloads.static_droplet(n=16, R=4)
+    h = ctypes.c_void_p()
+    st = lib.lbpf_create(ctypes.byref(lbpf.make_params(cfg)), None, 0, None, ctypes.byref(h))
+    assert st == -1 and not h.value
+    assert b"workspace" in lib.lbpf_create_error()
+
+
+def test_tile_shapes_listed(lib):
+    shapes = lbpf.tile_shapes()
+    assert len(shapes) >= 4
+    for tx, ty, nt in shapes:
+        assert nt % tx == 0 and ty % (nt // tx) == 0
