@@ -8,7 +8,6 @@ launch of the fused kernel. Inputs are synthetic (seeded spinodal noise), reside
 the timed region starts. Prints one JSON line.
 """
 import argparse
-import hashlib
 import json
 import os
 import re
@@ -20,25 +19,24 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_CELL = 168   # f_1..8, h_0 hi, h_1..8, h_0 lo, p, (phi u)_x, (phi u)_y: 21 FP32 read + 21 written
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1902_08933_amd", "csrc", "lbpf_kernels.hip")
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fused_step_spinodal1024_pmc.txt")
 
 
-def kernel_hash():
-    with open(KERNEL_SOURCE, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+def traffic_summary_path(workload):
+    return os.path.join(ROOT, "profiles", f"fused_step_{workload}_pmc.txt")
 
 
-def measured_traffic(cells):
+def measured_traffic(workload, cells):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken on the
     current kernel source; otherwise None."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+    from paper_1902_08933_amd.rocprof_summary import kernel_source_hash
+    path = traffic_summary_path(workload)
+    if not os.path.exists(path):
         return None
-    text = open(TRAFFIC_SUMMARY).read()
+    text = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     c = re.search(r"cells:\s*([0-9]+)", text)
-    if not (m and t and c) or m.group(1) != kernel_hash() or int(c.group(1)) != cells:
+    if not (m and t and c) or m.group(1) != kernel_source_hash() or int(c.group(1)) != cells:
         return None
     return float(t.group(1))
 
@@ -52,11 +50,12 @@ def workload(name, variant):
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_gpu(cfg, phi, steps, warmup, tile=0):
+def time_gpu(cfg, phi, steps, warmup, tile=None):
     import torch
     from paper_1902_08933_amd import lbpf
     sim = lbpf.Simulation(cfg)
-    sim.set_tile(tile)
+    if tile is not None:
+        sim.set_tile(tile)
     sim.init(torch.from_numpy(phi.astype("float32")).cuda())
     sim.step(warmup)
     stream = torch.cuda.current_stream()
@@ -71,7 +70,29 @@ def time_gpu(cfg, phi, steps, warmup, tile=0):
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     diag = sim.diagnostics()
-    return ms, wall, diag
+    return ms, wall, diag, lbpf.tile_shapes()[sim.tile]
+
+
+def probe_copy_gbs(mib=2048, reps=10):
+    """Bandwidth probe (plain 16-byte copy kernel): the practical HBM reference on this GPU."""
+    import torch
+    from paper_1902_08933_amd import lbpf
+    nbytes = mib << 20
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    best = 0.0
+    for blocks in (512, 1024, 2048):
+        lbpf.bw_probe(0, x, y, nbytes, blocks)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            lbpf.bw_probe(0, x, y, nbytes, blocks)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del x, y
+    return best
 
 
 def cpu_baseline(cfg, phi, steps):
@@ -91,7 +112,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="spinodal1024")
     ap.add_argument("--variant", default="qim")
-    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=None, help="strip shape index (default: library default)")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
@@ -105,11 +126,11 @@ def main():
     cells = cfg["nx"] * cfg["ny"]
     print(f"# workload {args.workload} {cfg['nx']}x{cfg['ny']} {args.variant}: "
           f"{args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
-    ms, wall, diag = time_gpu(cfg, phi, args.steps, args.warmup, args.tile)
+    ms, wall, diag, shape = time_gpu(cfg, phi, args.steps, args.warmup, args.tile)
     ms_per_step = ms / args.steps
     mlups = cells * args.steps / (ms * 1e-3) / 1e6
     achieved = BYTES_PER_CELL * cells / (ms_per_step * 1e-3) / 1e9
-    traffic = measured_traffic(cells)
+    traffic = measured_traffic(args.workload, cells)
     out = {
         "metric": "D2Q9 two-phase MLUPS, % of HBM roofline; surrogate speedup at fixed error",
         "value": round(mlups, 1),
@@ -127,11 +148,13 @@ def main():
                                f"{args.variant.upper()}, rho ratio 3, nu ratio 0.1, sigma 0.03, "
                                "W 4, M_phi 0.1, tau_h 1",
                    "nx": cfg["nx"], "ny": cfg["ny"], "variant": args.variant,
-                   "tile": args.tile, "parallelism": "single GPU"},
+                   "strip": {"tx": shape[0], "rows": shape[1], "threads": shape[2]},
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "bytes_per_cell_update": BYTES_PER_CELL,
-                     "kernel": "fused_kernel<64,16,256,true>"},
+                     "kernel": f"strip_kernel<{shape[0]},{shape[2]},{shape[1]}>",
+                     "copy_probe_GBs": None},
         "wall_s_timed": round(wall, 4),
         "sum_phi_final": diag["sum_phi"],
     }
@@ -139,14 +162,16 @@ def main():
         # footprint far above the 256 MB Infinity Cache: 4096^2 cells, ~2.8 GB of state
         lcfg, lphi = workload("spinodal4096", args.variant)
         lsteps = max(50, args.steps // 16)
-        lms, _, _ = time_gpu(lcfg, lphi, lsteps, 20, args.tile)
+        lms, _, _, _ = time_gpu(lcfg, lphi, lsteps, 20, args.tile)
         lcells = lcfg["nx"] * lcfg["ny"]
         lper = lms / lsteps
         out["large_footprint"] = {
             "workload": "spinodal 4096x4096", "steps": lsteps, "ms_per_step": lper,
             "MLUPS": round(lcells / (lper * 1e-3) / 1e6, 1),
             "achieved_GBs": round(BYTES_PER_CELL * lcells / (lper * 1e-3) / 1e9, 1),
-            "frac": round(BYTES_PER_CELL * lcells / (lper * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "frac": round(BYTES_PER_CELL * lcells / (lper * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("spinodal4096", lcells)}
+    out["roofline"]["copy_probe_GBs"] = round(probe_copy_gbs(), 1)
     if not args.no_cpu_baseline:
         v, dt = cpu_baseline(cfg, phi, args.cpu_steps)
         out["cpu_baseline"] = {"value": round(v, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",

@@ -144,14 +144,33 @@ lbpf_status lbpf_load_state(lbpf_ctx* ctx, const void* src_device);
 /* Change the stream used by later calls. */
 lbpf_status lbpf_set_stream(lbpf_ctx* ctx, void* hip_stream);
 
-/* Tile shape of the fused step: index into lbpf_tile_configs(); results are bit-identical for
- * every tile shape. */
+/* Work shape of the fused step: index into the list of strip shapes. A workgroup of `threads`
+ * threads owns a strip `tx` nodes wide and `rows` rows tall and marches up it. Results are
+ * bit-identical for every shape. */
 lbpf_status lbpf_set_tile(lbpf_ctx* ctx, int32_t tile_index);
-/* Number of tile shapes and their (TX, TY, threads) triples. */
+/* Autotuner: times every strip shape over trial_steps steps (after one warm-up launch each)
+ * on this simulation's own grid and parameters, writes the mean milliseconds per step of shape i
+ * to ms_out[i] (may be NULL; else lbpf_tile_count() floats), selects the fastest shape and
+ * returns its index in *best_out. The state is saved to scratch_state (a device buffer of
+ * lbpf_state_size() bytes) first and restored afterwards, step count included, so the tuned
+ * simulation continues bit-identically. Synchronizes the stream. */
+lbpf_status lbpf_autotune(lbpf_ctx* ctx, int32_t trial_steps, void* scratch_state, float* ms_out,
+                          int32_t* best_out);
+/* Strip shape in use (-1 for a NULL handle). */
+int32_t lbpf_get_tile(const lbpf_ctx* ctx);
+/* Number of strip shapes, and the (tx, rows, threads) triple of one of them. */
 int32_t lbpf_tile_count(void);
-lbpf_status lbpf_tile_shape(int32_t tile_index, int32_t* tx, int32_t* ty, int32_t* threads);
+lbpf_status lbpf_tile_shape(int32_t tile_index, int32_t* tx, int32_t* rows, int32_t* threads);
 
 int64_t lbpf_step_count(const lbpf_ctx* ctx);
+
+/* HBM bandwidth probe (the reference point of the roofline): mode 0 copies `bytes` from src to
+ * dst, mode 1 reads src (dst must hold one float per workgroup; it is written only when a
+ * partial sum equals an improbable sentinel), mode 2 writes zeros to dst. 16-byte accesses, grid-stride over `blocks` workgroups of
+ * 256 threads (blocks <= 0: 4096). bytes must be a multiple of 16; buffers are caller-owned
+ * device memory. Asynchronous on hip_stream; errors via lbpf_create_error(). */
+lbpf_status lbpf_bw_probe(int32_t mode, const void* src, void* dst, size_t bytes, int32_t blocks,
+                          void* hip_stream);
 
 /* Release the handle (does not free the caller's workspace). NULL is accepted. */
 lbpf_status lbpf_destroy(lbpf_ctx* ctx);

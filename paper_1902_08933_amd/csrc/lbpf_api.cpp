@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -14,7 +15,7 @@
 
 namespace lbpf {
 int tile_count();
-void tile_shape(int i, int* tx, int* ty, int* nt);
+void tile_shape(int i, int* tx, int* rows, int* nt);
 hipError_t launch_step(int tile, const Model& m, const float* fin, float* fout, const float* hin,
                        float* hout, const float* pin, float* pout, float* phiu, hipStream_t st);
 hipError_t launch_fields(const Model& m, const float* fin, const float* hin, const float* pin,
@@ -26,6 +27,7 @@ hipError_t launch_diag(const Model& m, const float* f, const float* h, const flo
 hipError_t launch_laplace(const Model& m, const float* h, const float* fields, double* phi64,
                           double xc, double yc, double r_in, double r_out, double* red,
                           hipStream_t st);
+hipError_t launch_probe(int mode, const void* src, void* dst, size_t bytes, int blocks, hipStream_t st);
 }  // namespace lbpf
 
 using namespace lbpf;
@@ -45,6 +47,7 @@ struct lbpf_ctx {
 };
 
 static thread_local std::string g_create_err;
+static const int kDefaultTile = 1;  // strip 64 wide, 16 rows, 256 threads
 
 static lbpf_status fail(lbpf_ctx* c, lbpf_status s, const char* fmt, ...) {
     char buf[512];
@@ -81,7 +84,17 @@ static const char* validate(const lbpf_params* p) {
     return nullptr;
 }
 
-static size_t plane_floats(const lbpf_params* p) { return (size_t)p->ny * pitch_of(p->nx); }
+// Distance between consecutive planes: ny rows of `pitch` floats plus a layout pad. The pad
+// (LBPF_PLANE_PAD_FLOATS, a multiple of 64, default kDefaultPlanePad) keeps the 21 planes of a
+// node from sitting a power of two apart, which would map them to the same DRAM banks. It must
+// not change between lbpf_workspace_size() and lbpf_create() of one simulation.
+static size_t plane_pad() {
+    const char* e = getenv("LBPF_PLANE_PAD_FLOATS");
+    long v = e ? strtol(e, nullptr, 10) : kDefaultPlanePad;
+    if (v < 0) v = 0;
+    return (size_t)(v + 63) / 64 * 64;
+}
+static size_t plane_floats(const lbpf_params* p) { return (size_t)p->ny * pitch_of(p->nx) + plane_pad(); }
 
 static size_t ws_bytes(const lbpf_params* p) {
     return plane_floats(p) * sizeof(float) * kNumPlanes + kRedDoubles * sizeof(double);
@@ -170,7 +183,7 @@ lbpf_status lbpf_create(const lbpf_params* params, void* workspace, size_t works
     c->stream = (hipStream_t)hip_stream;
     c->cur = 0;
     c->initialized = 0;
-    c->tile = 0;
+    c->tile = kDefaultTile;
     c->step = 0;
     *out = c;
     return LBPF_OK;
@@ -280,7 +293,7 @@ lbpf_status lbpf_save_state(lbpf_ctx* c, void* dst) {
     if (!dst) return fail(c, LBPF_E_INVALID, "dst is NULL");
     // the header is copied synchronously so that hdr may be reused at once
     c->hdr[0] = kMagic; c->hdr[1] = 1; c->hdr[2] = c->m.nx; c->hdr[3] = c->m.ny;
-    c->hdr[4] = c->m.pitch; c->hdr[5] = c->step; c->hdr[6] = 0; c->hdr[7] = 0;
+    c->hdr[4] = c->m.pitch; c->hdr[5] = c->step; c->hdr[6] = c->m.plane; c->hdr[7] = 0;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = hipMemcpy(dst, c->hdr, 64, hipMemcpyHostToDevice);
     const size_t pb = (size_t)c->m.plane * sizeof(float);
@@ -300,7 +313,8 @@ lbpf_status lbpf_load_state(lbpf_ctx* c, const void* src) {
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = hipMemcpy(hdr, src, 64, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(c, e, "load state header");
-    if (hdr[0] != kMagic || hdr[1] != 1 || hdr[2] != c->m.nx || hdr[3] != c->m.ny || hdr[4] != c->m.pitch)
+    if (hdr[0] != kMagic || hdr[1] != 1 || hdr[2] != c->m.nx || hdr[3] != c->m.ny || hdr[4] != c->m.pitch ||
+        hdr[6] != c->m.plane)
         return fail(c, LBPF_E_INVALID, "checkpoint does not match this grid");
     c->cur = 0;
     const size_t pb = (size_t)c->m.plane * sizeof(float);
@@ -321,13 +335,52 @@ lbpf_status lbpf_set_stream(lbpf_ctx* c, void* hip_stream) {
     return LBPF_OK;
 }
 
+lbpf_status lbpf_autotune(lbpf_ctx* c, int32_t trial_steps, void* scratch_state, float* ms_out,
+                          int32_t* best_out) {
+    if (lbpf_status s = check_ctx(c, true)) return s;
+    if (trial_steps < 1 || !scratch_state) return fail(c, LBPF_E_INVALID, "trial_steps >= 1 and a state buffer are required");
+    if (lbpf_status s = lbpf_save_state(c, scratch_state)) return s;
+    const int64_t step0 = c->step;
+    const int keep = c->tile;
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_fail(c, e, "autotune events");
+    int best = keep;
+    float best_ms = 0.0f;
+    lbpf_status st = LBPF_OK;
+    for (int t = 0; t < tile_count() && st == LBPF_OK; ++t) {
+        c->tile = t;
+        st = lbpf_step(c, 1);  // warm-up launch of this shape
+        if (st != LBPF_OK) break;
+        e = hipEventRecord(e0, c->stream);
+        if (e == hipSuccess && (st = lbpf_step(c, trial_steps)) == LBPF_OK) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess && st == LBPF_OK) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess && st == LBPF_OK) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { st = hip_fail(c, e, "autotune timing"); break; }
+        ms /= (float)trial_steps;
+        if (ms_out) ms_out[t] = ms;
+        if (t == 0 || ms < best_ms) { best_ms = ms; best = t; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->tile = keep;
+    if (st != LBPF_OK) return st;
+    if (lbpf_status s = lbpf_load_state(c, scratch_state)) return s;
+    c->step = step0;
+    c->tile = best;
+    if (best_out) *best_out = best;
+    return LBPF_OK;
+}
+
 int32_t lbpf_tile_count(void) { return tile_count(); }
 
-lbpf_status lbpf_tile_shape(int32_t i, int32_t* tx, int32_t* ty, int32_t* threads) {
-    if (i < 0 || i >= tile_count() || !tx || !ty || !threads) return LBPF_E_INVALID;
+lbpf_status lbpf_tile_shape(int32_t i, int32_t* tx, int32_t* rows, int32_t* threads) {
+    if (i < 0 || i >= tile_count() || !tx || !rows || !threads) return LBPF_E_INVALID;
     int a, b, t;
     tile_shape(i, &a, &b, &t);
-    *tx = a; *ty = b; *threads = t;
+    *tx = a; *rows = b; *threads = t;
     return LBPF_OK;
 }
 
@@ -338,7 +391,19 @@ lbpf_status lbpf_set_tile(lbpf_ctx* c, int32_t i) {
     return LBPF_OK;
 }
 
+lbpf_status lbpf_bw_probe(int32_t mode, const void* src, void* dst, size_t bytes, int32_t blocks,
+                          void* hip_stream) {
+    if (mode < 0 || mode > 2) return fail(nullptr, LBPF_E_INVALID, "probe mode must be 0, 1 or 2");
+    if (bytes % 16 != 0) return fail(nullptr, LBPF_E_INVALID, "probe size must be a multiple of 16 bytes");
+    if ((mode != 2 && !src) || !dst) return fail(nullptr, LBPF_E_INVALID, "probe buffer is NULL");
+    hipError_t e = launch_probe(mode, src, dst, bytes, blocks, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(nullptr, LBPF_E_HIP, "probe kernel: %s", hipGetErrorString(e));
+    return LBPF_OK;
+}
+
 int64_t lbpf_step_count(const lbpf_ctx* c) { return c ? c->step : -1; }
+
+int32_t lbpf_get_tile(const lbpf_ctx* c) { return c ? c->tile : -1; }
 
 lbpf_status lbpf_destroy(lbpf_ctx* c) {
     delete c;

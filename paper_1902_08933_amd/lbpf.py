@@ -60,10 +60,14 @@ SIGNATURES = {
     "lbpf_load_state": (_S, [_V, _V]),
     "lbpf_set_stream": (_S, [_V, _V]),
     "lbpf_set_tile": (_S, [_V, ctypes.c_int32]),
+    "lbpf_autotune": (_S, [_V, ctypes.c_int32, _V, ctypes.POINTER(ctypes.c_float),
+                           ctypes.POINTER(ctypes.c_int32)]),
+    "lbpf_get_tile": (ctypes.c_int32, [_V]),
     "lbpf_tile_count": (ctypes.c_int32, []),
     "lbpf_tile_shape": (_S, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "lbpf_step_count": (ctypes.c_int64, [_V]),
+    "lbpf_bw_probe": (_S, [ctypes.c_int32, _V, _V, ctypes.c_size_t, ctypes.c_int32, _V]),
     "lbpf_destroy": (_S, [_V]),
     "lbpf_status_string": (ctypes.c_char_p, [_S]),
     "lbpf_last_error": (ctypes.c_char_p, [_V]),
@@ -130,6 +134,16 @@ def tile_shapes():
         _check(lib.lbpf_tile_shape(i, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         out.append((a.value, b.value, c.value))
     return out
+
+
+def bw_probe(mode, src, dst, nbytes, blocks=0, stream=None):
+    """Launch the bandwidth probe (mode 0 copy, 1 read, 2 write) on torch tensors."""
+    import torch
+    lib = library()
+    st = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(lib.lbpf_bw_probe(int(mode), ctypes.c_void_p(src.data_ptr()) if src is not None else None,
+                             ctypes.c_void_p(dst.data_ptr()), ctypes.c_size_t(nbytes), int(blocks),
+                             ctypes.c_void_p(st)))
 
 
 def _dev_ptr(t, torch, shape=None):
@@ -233,9 +247,23 @@ class Simulation:
         self._c(self.lib.lbpf_set_tile(self._h, int(index)))
         return self
 
+    def autotune(self, trial_steps=20):
+        """Time every strip shape on this grid, keep the fastest; the state is restored."""
+        n = self.lib.lbpf_tile_count()
+        ms = (ctypes.c_float * n)()
+        best = ctypes.c_int32()
+        scratch = self.torch.empty(self.state_size(), dtype=self.torch.uint8, device=self.device)
+        self._c(self.lib.lbpf_autotune(self._h, int(trial_steps), ctypes.c_void_p(scratch.data_ptr()),
+                                       ms, ctypes.byref(best)))
+        return best.value, list(ms)
+
     def set_stream(self, stream):
         self._c(self.lib.lbpf_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
         return self
+
+    @property
+    def tile(self):
+        return int(self.lib.lbpf_get_tile(self._h))
 
     @property
     def step_count(self):

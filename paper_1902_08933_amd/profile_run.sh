@@ -1,0 +1,35 @@
+#!/bin/bash
+# Profile the fused step on one workload and write the summaries under profiles/:
+#   profiles/fused_step_<workload>_trace.txt  (rocprofv3 --kernel-trace --stats)
+#   profiles/fused_step_<workload>_pmc.txt    (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, each
+#                                              scaled by the counter's reading for the bandwidth probe)
+# Usage (from the repository root): bash paper_1902_08933_amd/profile_run.sh spinodal1024
+# Raw rocprofv3 output goes to gpurun_out/prof_<workload>/; PROFILE_OUT overrides profiles/.
+set -o pipefail
+W=${1:-spinodal1024}
+N=${W#spinodal}
+CELLS=$((N * N))
+OUT=gpurun_out/prof_$W
+PROF=${PROFILE_OUT:-profiles}
+mkdir -p "$OUT" "$PROF"
+export TMPDIR=/tmp
+STEP="python3 -m paper_1902_08933_amd.profile_step --workload $W"
+PROBE="python3 -m paper_1902_08933_amd.profile_step --copy-mib 1024 --steps 2 --probe-blocks 4096"
+echo "profile: kernel trace $W" && \
+timeout -k 10 180 rocprofv3 --kernel-trace --stats -d "$OUT/trace" -o run -- $STEP --steps 100 --warmup 10 > "$OUT/trace.log" 2>&1 && \
+echo "profile: FETCH_SIZE $W" && \
+timeout -s KILL 90 rocprofv3 --pmc FETCH_SIZE -d "$OUT/fetch" -o run -- $STEP --steps 5 --warmup 1 > "$OUT/fetch.log" 2>&1 && \
+echo "profile: WRITE_SIZE $W" && \
+timeout -s KILL 90 rocprofv3 --pmc WRITE_SIZE -d "$OUT/write" -o run -- $STEP --steps 5 --warmup 1 > "$OUT/write.log" 2>&1 && \
+echo "profile: probe FETCH_SIZE" && \
+timeout -s KILL 90 rocprofv3 --pmc FETCH_SIZE -d "$OUT/cfetch" -o run -- $PROBE > "$OUT/cfetch.log" 2>&1 && \
+echo "profile: probe WRITE_SIZE" && \
+timeout -s KILL 90 rocprofv3 --pmc WRITE_SIZE -d "$OUT/cwrite" -o run -- $PROBE > "$OUT/cwrite.log" 2>&1 && \
+python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --cells $CELLS \
+    --command "bash paper_1902_08933_amd/profile_run.sh $W  (trace: rocprofv3 --kernel-trace --stats -- $STEP --steps 100 --warmup 10)" \
+    --out "$PROF/fused_step_${W}_trace.txt" && \
+python3 -m paper_1902_08933_amd.rocprof_summary --fetch "$OUT/fetch/run_results.db" --write "$OUT/write/run_results.db" \
+    --calib-fetch "$OUT/cfetch/run_results.db" --calib-write "$OUT/cwrite/run_results.db" --calib-bytes 1073741824 \
+    --cells $CELLS \
+    --command "bash paper_1902_08933_amd/profile_run.sh $W  (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE -- $STEP --steps 5 --warmup 1; calibration: same counters on $PROBE)" \
+    --out "$PROF/fused_step_${W}_pmc.txt"

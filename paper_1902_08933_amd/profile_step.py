@@ -1,0 +1,87 @@
+"""Profiling driver for the fused step (run it under rocprofv3, or alone for a tile sweep).
+
+python -m paper_1902_08933_amd.profile_step --workload spinodal4096 --steps 20
+python -m paper_1902_08933_amd.profile_step --workload spinodal1024 --sweep
+python -m paper_1902_08933_amd.profile_step --copy-mib 2048 --steps 10   (bandwidth probe:
+    copy / read / write of a known byte count, the reference for the HBM roofline and for
+    scaling the FETCH_SIZE / WRITE_SIZE counters)
+"""
+import argparse
+import sys
+
+from . import lbpf, workloads
+
+BYTES_PER_CELL = 168
+
+
+def make(name, variant):
+    if name.startswith("spinodal"):
+        n = int(name[len("spinodal"):])
+        return workloads.spinodal(n=n, variant=variant, seed=0)
+    if name == "bubble512x2048":
+        return workloads.rising_bubble(nx=512, ny=2048, R=64.0, rho_ratio=10.0, variant=variant)
+    if name == "poiseuille256x128":
+        return workloads.layered_poiseuille(nx=256, ny=128, variant=variant)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def run_steps(torch, cfg, phi, steps, warmup, tile):
+    sim = lbpf.Simulation(cfg)
+    if tile is not None:
+        sim.set_tile(tile)
+    sim.init(torch.from_numpy(phi.astype("float32")).cuda())
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def main():
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="spinodal1024")
+    ap.add_argument("--variant", default="qim")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--tile", type=int, default=None, help="strip shape (default: library default)")
+    ap.add_argument("--sweep", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0)
+    ap.add_argument("--probe-blocks", type=int, default=0)
+    a = ap.parse_args()
+    if a.copy_mib:
+        nbytes = a.copy_mib * (1 << 20)
+        x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for mode, name, moved in ((0, "copy", 2), (1, "read", 1), (2, "write", 1)):
+            for blocks in ((a.probe_blocks,) if a.probe_blocks else (1024, 4096, 16384)):
+                dst = y if mode != 1 else torch.empty(blocks, dtype=torch.float32, device="cuda")
+                lbpf.bw_probe(mode, x, dst, nbytes, blocks)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(a.steps):
+                    lbpf.bw_probe(mode, x, dst, nbytes, blocks)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / a.steps
+                print(f"probe {name} {a.copy_mib} MiB, {blocks} workgroups: {ms:.4f} ms, "
+                      f"{moved * nbytes / ms / 1e6:.1f} GB/s", flush=True)
+        return
+    cfg, phi = make(a.workload, a.variant)
+    cells = cfg["nx"] * cfg["ny"]
+    tiles = range(len(lbpf.tile_shapes())) if a.sweep else [a.tile]
+    for t in tiles:
+        ms = run_steps(torch, cfg, phi, a.steps, a.warmup, t)
+        gbs = BYTES_PER_CELL * cells / (ms * 1e-3) / 1e9
+        shape = lbpf.tile_shapes()[t] if t is not None else "default"
+        print(f"{a.workload} {a.variant} tile {t} {shape}: {ms:.4f} ms/step, "
+              f"{cells / (ms * 1e-3) / 1e6:.0f} MLUPS, {gbs:.0f} GB/s ({gbs / 80:.1f}% of 8 TB/s)",
+              flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,115 @@
+"""Short text summaries of rocprofv3 results (SQLite .db output) for profiles/.
+
+python -m paper_1902_08933_amd.rocprof_summary --trace T.db [--fetch F.db --write W.db
+    --calib-fetch CF.db --calib-write CW.db --calib-bytes N --kernel strip_kernel --cells C]
+    --command "..." --out profiles/NAME.txt
+
+--trace: kernel-trace run: calls, total and average duration per kernel.
+--fetch/--write: one --pmc FETCH_SIZE run and one --pmc WRITE_SIZE run of the same program;
+each counter is scaled by what it reads for the bandwidth probe (probe_read_kernel /
+probe_write_kernel of --calib-bytes bytes), giving HBM bytes per dispatch of --kernel.
+"""
+import argparse
+import hashlib
+import os
+import sqlite3
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_FILES = [os.path.join(HERE, "csrc", n) for n in ("lbpf_kernels.hip", "lbpf_cell.hpp",
+                                                        "lbpf_model.hpp")]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_FILES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def trace_stats(db):
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, end - start from kernels").fetchall()
+    out = {}
+    for name, d in rows:
+        out.setdefault(name, []).append(d)
+    return {k: (len(v), sum(v), statistics.mean(v), statistics.median(v)) for k, v in out.items()}
+
+
+def pmc_values(db, counter):
+    c = sqlite3.connect(db)
+    rows = c.execute("select kernel_name, value from counters_collection where counter_name = ?",
+                     (counter,)).fetchall()
+    out = {}
+    for name, v in rows:
+        out.setdefault(name, []).append(v)
+    return out
+
+
+def pick(d, key):
+    ks = [k for k in d if key in k]
+    if not ks:
+        raise SystemExit(f"no kernel matching {key!r} in {list(d)[:5]}")
+    return ks[0], d[ks[0]]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--calib-fetch")
+    ap.add_argument("--calib-write")
+    ap.add_argument("--calib-bytes", type=int, default=0)
+    ap.add_argument("--kernel", default="strip_kernel")
+    ap.add_argument("--cells", type=int, default=0)
+    ap.add_argument("--alg-bytes-per-cell", type=float, default=168.0)
+    ap.add_argument("--command", default="")
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args()
+    lines = [f"# rocprofv3 summary", f"command: {a.command}",
+             f"kernel_source_sha256_16: {kernel_source_hash()}"]
+    if a.cells:
+        lines.append(f"cells: {a.cells}")
+    if a.trace:
+        lines.append("")
+        lines.append("## kernel trace (durations in microseconds)")
+        lines.append(f"{'calls':>6} {'total_us':>12} {'avg_us':>10} {'median_us':>10}  kernel")
+        for k, (n, tot, avg, med) in sorted(trace_stats(a.trace).items(), key=lambda kv: -kv[1][1]):
+            lines.append(f"{n:6d} {tot / 1e3:12.1f} {avg / 1e3:10.3f} {med / 1e3:10.3f}  {k[:110]}")
+        if a.cells:
+            name, (n, tot, avg, med) = pick(trace_stats(a.trace), a.kernel)
+            gbs = a.alg_bytes_per_cell * a.cells / (avg * 1e-9) / 1e9
+            lines.append(f"avg_duration_us_{a.kernel}: {avg / 1e3:.3f}")
+            lines.append(f"algorithmic_GBs_at_avg_duration: {gbs:.1f}")
+    if a.fetch and a.write:
+        fk, fv = pick(pmc_values(a.fetch, "FETCH_SIZE"), a.kernel)
+        wk, wv = pick(pmc_values(a.write, "WRITE_SIZE"), a.kernel)
+        f_kib, w_kib = statistics.median(fv), statistics.median(wv)
+        fs = ws = 1.0
+        if a.calib_fetch and a.calib_write and a.calib_bytes:
+            _, cf = pick(pmc_values(a.calib_fetch, "FETCH_SIZE"), "probe_read_kernel")
+            _, cw = pick(pmc_values(a.calib_write, "WRITE_SIZE"), "probe_write_kernel")
+            fs = a.calib_bytes / (statistics.median(cf) * 1024)
+            ws = a.calib_bytes / (statistics.median(cw) * 1024)
+        hbm = f_kib * 1024 * fs + w_kib * 1024 * ws
+        lines += ["", "## HBM traffic per dispatch (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE)",
+                  f"kernel: {fk[:110]}",
+                  f"FETCH_SIZE_KiB_median: {f_kib:.0f} (dispatches: {len(fv)})",
+                  f"WRITE_SIZE_KiB_median: {w_kib:.0f} (dispatches: {len(wv)})",
+                  f"calibration_probe_bytes: {a.calib_bytes}",
+                  f"fetch_scale: {fs:.4f}", f"write_scale: {ws:.4f}",
+                  f"hbm_bytes_per_launch: {hbm:.6e}"]
+        if a.cells:
+            lines.append(f"hbm_bytes_per_cell: {hbm / a.cells:.2f} "
+                         f"(read {f_kib * 1024 * fs / a.cells:.2f}, write {w_kib * 1024 * ws / a.cells:.2f}; "
+                         f"algorithmic {a.alg_bytes_per_cell:.0f})")
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+    with open(a.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()

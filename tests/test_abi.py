@@ -45,8 +45,9 @@ def test_workspace_size_scales_with_grid(lib):
     cfg, _ = workloads.static_droplet(n=64)
     a = lbpf.workspace_size(cfg)
     b = lbpf.workspace_size(dict(cfg, nx=128, ny=128))
-    assert b > 3 * (a - 4096 * 8 * 9) // 1  # planes dominate
-    assert a % 256 == 0 or a > 0
+    # 48 FP32 planes per node (two population copies, histories, field scratch); the layout pad
+    # and the reduction area do not depend on the grid size
+    assert b - a == 48 * 4 * (128 * 128 - 64 * 64)
 
 
 @pytest.mark.parametrize("bad,why", [
@@ -86,5 +87,5 @@ def test_create_rejects_null_workspace(lib):
 def test_tile_shapes_listed(lib):
     shapes = lbpf.tile_shapes()
     assert len(shapes) >= 4
-    for tx, ty, nt in shapes:
-        assert nt % tx == 0 and ty % (nt // tx) == 0
+    for tx, rows, nt in shapes:
+        assert nt % tx == 0 and nt // tx >= 2 and rows % (nt // tx) == 0
