@@ -95,6 +95,38 @@ def probe_copy_gbs(mib=2048, reps=10):
     return best
 
 
+def batch_bench(steps, count=256, seed=0):
+    """256 independent instances (sides 64..512): one graph-replayed persistent launch per step
+    vs one single-simulation launch per instance per step. Instances the method cannot hold
+    stable are frozen after the warm-up; MLUPS counts the active instances' nodes."""
+    import numpy as np
+    import torch
+    from paper_1902_08933_amd import lbpf
+    from paper_1902_08933_amd import workloads as W
+    insts = W.batch_instances(count, seed=seed)
+    b = lbpf.Batch([c for c, _ in insts])
+    for k, (_, phi) in enumerate(insts):
+        b.init(k, torch.from_numpy(np.ascontiguousarray(phi, dtype=np.float32)).cuda())
+    del insts
+    b.step(16)
+    flags, _ = b.status()
+    active = sum(c["nx"] * c["ny"] for c, f in zip(b.cfgs, flags) if not f)
+    out = {"instances": count, "frozen": int(sum(flags)), "active_nodes": active,
+           "strip": list(lbpf.tile_shapes()[b.tile])}
+    for name, fn in (("graph_persistent", b.step), ("launch_per_instance", b.step_each)):
+        fn(8)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[name] = {"ms_per_step": round(ms, 4), "MLUPS": round(active / (ms * 1e-3) / 1e6, 1)}
+    out["speedup"] = round(out["launch_per_instance"]["ms_per_step"] / out["graph_persistent"]["ms_per_step"], 2)
+    return out
+
+
 def cpu_baseline(cfg, phi, steps):
     import numpy as np
     import oracle
@@ -116,6 +148,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=80)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -172,6 +206,8 @@ def main():
             "frac": round(BYTES_PER_CELL * lcells / (lper * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic("spinodal4096", lcells)}
     out["roofline"]["copy_probe_GBs"] = round(probe_copy_gbs(), 1)
+    if not args.no_batch:
+        out["batched"] = batch_bench(args.batch_steps)
     if not args.no_cpu_baseline:
         v, dt = cpu_baseline(cfg, phi, args.cpu_steps)
         out["cpu_baseline"] = {"value": round(v, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",

@@ -181,6 +181,52 @@ const char* lbpf_last_error(const lbpf_ctx* ctx);
 /* Message of the last failed lbpf_create / lbpf_workspace_size on this thread. */
 const char* lbpf_create_error(void);
 
+/* ------------------------------------------------------------------------------------------
+ * Batch: many independent simulations (own grid size and parameters each) advanced together by
+ * one persistent kernel per time step, replayed from HIP graphs of 8 steps. Each instance
+ * evolves bit-identically to a single simulation with the same parameters and initial fields.
+ * Instances are addressed by index 0..n-1; lbpf_batch_instance() returns the per-instance
+ * handle for lbpf_read, lbpf_diagnostics, lbpf_laplace_dp and checkpointing (not for lbpf_step
+ * or lbpf_init: use the batch calls). The batch owns those handles.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct lbpf_batch lbpf_batch;
+
+/* Device workspace bytes for n instances with parameters params[0..n-1]. */
+lbpf_status lbpf_batch_workspace_size(int32_t n, const lbpf_params* params, size_t* bytes);
+/* Bind a batch to a caller-owned workspace (256-byte aligned) and stream; builds the work
+ * list of (instance, strip chunk) items and the step graphs. Errors as lbpf_create. */
+lbpf_status lbpf_batch_create(int32_t n, const lbpf_params* params, void* workspace,
+                              size_t workspace_bytes, void* hip_stream, lbpf_batch** out);
+/* Initial state of instance idx, as lbpf_init; also clears a frozen flag. */
+lbpf_status lbpf_batch_init(lbpf_batch* b, int32_t idx, const float* phi, const float* ux,
+                            const float* uy, const float* p);
+/* Advance every instance nsteps steps: graph replays of 8 steps, then single launches. Every
+ * instance must be initialized. Asynchronous. */
+lbpf_status lbpf_batch_step(lbpf_batch* b, int64_t nsteps);
+/* Reference path: the same steps with one single-simulation launch per instance per step (a
+ * frozen instance's state is copied instead), for comparison with lbpf_batch_step. */
+lbpf_status lbpf_batch_step_each(lbpf_batch* b, int64_t nsteps);
+/* Per-instance FP64 diagnostics (flags[k] = 1 for a frozen instance). An instance whose state
+ * holds a non-finite value is frozen: later steps hold its state fixed while the others go on.
+ * flags (n int32) and diags (n lbpf_diag) may be NULL. Synchronizes the stream. */
+lbpf_status lbpf_batch_status(lbpf_batch* b, int32_t* flags, lbpf_diag* diags);
+lbpf_ctx* lbpf_batch_instance(lbpf_batch* b, int32_t idx);
+int32_t lbpf_batch_count(const lbpf_batch* b);
+/* Strip shape of the batched kernel (rebuilds the work list and graphs); results are
+ * bit-identical for every shape. */
+lbpf_status lbpf_batch_set_tile(lbpf_batch* b, int32_t tile_index);
+int32_t lbpf_batch_get_tile(const lbpf_batch* b);
+/* Bytes of a buffer holding every instance state (for lbpf_batch_autotune). */
+lbpf_status lbpf_batch_state_size(const lbpf_batch* b, size_t* bytes);
+/* Autotuner for the batch: times every strip shape over trial_steps steps, keeps the fastest
+ * (ms_out as in lbpf_autotune), and restores every instance state from scratch_state
+ * (lbpf_batch_state_size() bytes of device memory). Synchronizes the stream. */
+lbpf_status lbpf_batch_autotune(lbpf_batch* b, int32_t trial_steps, void* scratch_state,
+                                float* ms_out, int32_t* best_out);
+int64_t lbpf_batch_step_count(const lbpf_batch* b);
+lbpf_status lbpf_batch_destroy(lbpf_batch* b);
+const char* lbpf_batch_last_error(const lbpf_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,13 +2,16 @@
 // the model coefficients, carving of the caller's device workspace and kernel sequencing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "lbpf.h"
 #include "lbpf_model.hpp"
@@ -28,6 +31,9 @@ hipError_t launch_laplace(const Model& m, const float* h, const float* fields, d
                           double xc, double yc, double r_in, double r_out, double* red,
                           hipStream_t st);
 hipError_t launch_probe(int mode, const void* src, void* dst, size_t bytes, int blocks, hipStream_t st);
+hipError_t batch_kernel_info(int tile, void** fn, int* nt, int* tx, int* ch, int* per_cu);
+hipError_t launch_batch(int tile, const BatchInst* insts, const BatchItem* items, int nitems,
+                        int grid, int parity, hipStream_t st);
 }  // namespace lbpf
 
 using namespace lbpf;
@@ -189,16 +195,21 @@ lbpf_status lbpf_create(const lbpf_params* params, void* workspace, size_t works
     return LBPF_OK;
 }
 
-lbpf_status lbpf_init(lbpf_ctx* c, const float* phi, const float* ux, const float* uy, const float* p) {
+static lbpf_status init_copy(lbpf_ctx* c, int copy, const float* phi, const float* ux,
+                             const float* uy, const float* p) {
     if (lbpf_status s = check_ctx(c, false)) return s;
     if (!phi) return fail(c, LBPF_E_INVALID, "phi is NULL");
-    c->cur = 0;
+    c->cur = copy;
     hipError_t e = launch_init(c->m, phi, ux, uy, p, fcur(c), hcur(c), pcur(c), plane(c, kPlanePhiU),
                                c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "init kernel");
     c->initialized = 1;
     c->step = 0;
     return LBPF_OK;
+}
+
+lbpf_status lbpf_init(lbpf_ctx* c, const float* phi, const float* ux, const float* uy, const float* p) {
+    return init_copy(c, 0, phi, ux, uy, p);
 }
 
 lbpf_status lbpf_step(lbpf_ctx* c, int64_t nsteps) {
@@ -425,5 +436,403 @@ const char* lbpf_status_string(lbpf_status s) {
 const char* lbpf_last_error(const lbpf_ctx* c) { return c ? c->err.c_str() : "NULL handle"; }
 
 const char* lbpf_create_error(void) { return g_create_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// Batch of independent simulations
+// ---------------------------------------------------------------------------------------------
+struct lbpf_batch {
+    int n;
+    std::vector<lbpf_ctx*> inst;
+    std::vector<size_t> inst_off;     // byte offset of each instance workspace
+    std::vector<int> frozen;
+    char* ws;
+    size_t ws_bytes;
+    BatchInst* d_insts;               // device arrays at the start of the workspace
+    BatchItem* d_items;
+    size_t max_items;
+    int nitems;
+    int tile;
+    int grid;
+    int parity;                       // population copy holding the current state
+    int64_t step;
+    hipStream_t stream;
+    hipGraph_t graph[2];
+    hipGraphExec_t exec[2];
+    int graph_steps;
+    std::string err;
+};
+
+static const int kBatchGraphSteps = 8;
+
+static lbpf_status bfail(lbpf_batch* b, lbpf_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (b) b->err = buf;
+    else g_create_err = buf;
+    return s;
+}
+
+static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+static size_t batch_max_items(int n, const lbpf_params* params) {
+    size_t best = 0;
+    for (int t = 0; t < tile_count(); ++t) {
+        int tx, ch, nt;
+        tile_shape(t, &tx, &ch, &nt);
+        size_t items = 0;
+        for (int k = 0; k < n; ++k)
+            items += (size_t)((params[k].nx + tx - 1) / tx) * ((params[k].ny + ch - 1) / ch);
+        if (items > best) best = items;
+    }
+    return best;
+}
+
+static size_t batch_header_bytes(int n, const lbpf_params* params) {
+    return align256(sizeof(BatchInst) * n) + align256(sizeof(BatchItem) * batch_max_items(n, params));
+}
+
+static void destroy_graphs(lbpf_batch* b) {
+    for (int i = 0; i < 2; ++i) {
+        if (b->exec[i]) hipGraphExecDestroy(b->exec[i]);
+        if (b->graph[i]) hipGraphDestroy(b->graph[i]);
+        b->exec[i] = nullptr;
+        b->graph[i] = nullptr;
+    }
+}
+
+// Work list and persistent grid for the current strip shape, and the two step graphs (starting
+// from either population copy), built node by node so that any stream can replay them.
+static lbpf_status batch_setup(lbpf_batch* b) {
+    void* fn;
+    int nt, tx, ch, per;
+    hipError_t e = batch_kernel_info(b->tile, &fn, &nt, &tx, &ch, &per);
+    if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "batch kernel info: %s", hipGetErrorString(e));
+    std::vector<BatchInst> hi(b->n);
+    std::vector<BatchItem> items;
+    for (int k = 0; k < b->n; ++k) {
+        const Model& m = b->inst[k]->m;
+        hi[k].m = m;
+        hi[k].ws = b->inst[k]->ws;
+        hi[k].nsx = (m.nx + tx - 1) / tx;
+        hi[k].nsy = (m.ny + ch - 1) / ch;
+        hi[k].frozen = b->frozen[k];
+        hi[k].pad = 0;
+        for (int c = 0; c < hi[k].nsx * hi[k].nsy; ++c) items.push_back(BatchItem{k, c});
+    }
+    if (items.size() > b->max_items) return bfail(b, LBPF_E_NOMEM, "work list overflow");
+    b->nitems = (int)items.size();
+    int dev = 0, cus = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "device query: %s", hipGetErrorString(e));
+    b->grid = std::max(1, std::min(b->nitems, cus * per));
+    e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = hipMemcpy(b->d_insts, hi.data(), sizeof(BatchInst) * b->n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "work list upload: %s", hipGetErrorString(e));
+    destroy_graphs(b);
+    for (int start = 0; start < 2; ++start) {
+        e = hipGraphCreate(&b->graph[start], 0);
+        hipGraphNode_t prev = nullptr;
+        int parities[kBatchGraphSteps];
+        for (int sidx = 0; sidx < kBatchGraphSteps && e == hipSuccess; ++sidx) {
+            parities[sidx] = (start + sidx) & 1;
+            const BatchInst* di = b->d_insts;
+            const BatchItem* dt = b->d_items;
+            int ni = b->nitems;
+            void* args[] = {(void*)&di, (void*)&dt, (void*)&ni, (void*)&parities[sidx]};
+            hipKernelNodeParams kp{};
+            kp.func = fn;
+            kp.gridDim = dim3(b->grid);
+            kp.blockDim = dim3(nt);
+            kp.sharedMemBytes = 0;
+            kp.kernelParams = args;
+            kp.extra = nullptr;
+            hipGraphNode_t node;
+            e = hipGraphAddKernelNode(&node, b->graph[start], prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+            prev = node;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec[start], b->graph[start], nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            destroy_graphs(b);
+            return bfail(b, LBPF_E_HIP, "step graph: %s", hipGetErrorString(e));
+        }
+    }
+    b->graph_steps = kBatchGraphSteps;
+    return LBPF_OK;
+}
+
+extern "C" {
+
+lbpf_status lbpf_batch_workspace_size(int32_t n, const lbpf_params* params, size_t* bytes) {
+    if (n < 1 || !params || !bytes) return bfail(nullptr, LBPF_E_INVALID, "n >= 1, params and bytes required");
+    size_t total = batch_header_bytes(n, params);
+    for (int k = 0; k < n; ++k) {
+        if (const char* why = validate(&params[k])) return bfail(nullptr, LBPF_E_INVALID, "instance %d: %s", k, why);
+        total += align256(ws_bytes(&params[k]));
+    }
+    *bytes = total;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_batch_create(int32_t n, const lbpf_params* params, void* workspace,
+                              size_t workspace_bytes, void* hip_stream, lbpf_batch** out) {
+    if (!out) return bfail(nullptr, LBPF_E_INVALID, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    if (lbpf_status s = lbpf_batch_workspace_size(n, params, &need)) return s;
+    if (!workspace || ((uintptr_t)workspace) % 256 != 0)
+        return bfail(nullptr, LBPF_E_INVALID, "workspace must be non-NULL and 256-byte aligned");
+    if (workspace_bytes < need)
+        return bfail(nullptr, LBPF_E_NOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    lbpf_batch* b = new (std::nothrow) lbpf_batch();
+    if (!b) return bfail(nullptr, LBPF_E_NOMEM, "host allocation failed");
+    b->n = n;
+    b->ws = (char*)workspace;
+    b->ws_bytes = workspace_bytes;
+    b->stream = (hipStream_t)hip_stream;
+    b->d_insts = (BatchInst*)b->ws;
+    b->max_items = batch_max_items(n, params);
+    b->d_items = (BatchItem*)(b->ws + align256(sizeof(BatchInst) * n));
+    b->tile = kDefaultTile;
+    b->parity = 0;
+    b->step = 0;
+    b->graph[0] = b->graph[1] = nullptr;
+    b->exec[0] = b->exec[1] = nullptr;
+    b->frozen.assign(n, 0);
+    size_t off = batch_header_bytes(n, params);
+    for (int k = 0; k < n; ++k) {
+        lbpf_ctx* c = nullptr;
+        const size_t sz = align256(ws_bytes(&params[k]));
+        lbpf_status s = lbpf_create(&params[k], b->ws + off, sz, hip_stream, &c);
+        if (s != LBPF_OK) {
+            for (lbpf_ctx* x : b->inst) lbpf_destroy(x);
+            delete b;
+            return s;
+        }
+        b->inst.push_back(c);
+        b->inst_off.push_back(off);
+        off += sz;
+    }
+    if (lbpf_status s = batch_setup(b)) {
+        g_create_err = b->err;
+        for (lbpf_ctx* x : b->inst) lbpf_destroy(x);
+        destroy_graphs(b);
+        delete b;
+        return s;
+    }
+    *out = b;
+    return LBPF_OK;
+}
+
+lbpf_ctx* lbpf_batch_instance(lbpf_batch* b, int32_t idx) {
+    if (!b || idx < 0 || idx >= b->n) return nullptr;
+    return b->inst[idx];
+}
+
+int32_t lbpf_batch_count(const lbpf_batch* b) { return b ? b->n : -1; }
+
+lbpf_status lbpf_batch_init(lbpf_batch* b, int32_t idx, const float* phi, const float* ux,
+                            const float* uy, const float* p) {
+    if (!b) return LBPF_E_INVALID;
+    b->err.clear();
+    if (idx < 0 || idx >= b->n) return bfail(b, LBPF_E_INVALID, "instance %d out of range", idx);
+    lbpf_status s = init_copy(b->inst[idx], b->parity, phi, ux, uy, p);
+    if (s != LBPF_OK) return bfail(b, s, "instance %d: %s", idx, b->inst[idx]->err.c_str());
+    if (b->frozen[idx]) {
+        b->frozen[idx] = 0;
+        const int zero = 0;
+        hipError_t e = hipMemcpyAsync((char*)b->d_insts + sizeof(BatchInst) * idx + offsetof(BatchInst, frozen),
+                                      &zero, sizeof(int), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "unfreeze: %s", hipGetErrorString(e));
+    }
+    return LBPF_OK;
+}
+
+static lbpf_status batch_check(lbpf_batch* b) {
+    if (!b) return LBPF_E_INVALID;
+    b->err.clear();
+    for (int k = 0; k < b->n; ++k)
+        if (!b->inst[k]->initialized) return bfail(b, LBPF_E_STATE, "instance %d is not initialized", k);
+    return LBPF_OK;
+}
+
+static void batch_advance(lbpf_batch* b, int64_t nsteps) {
+    b->parity = (int)((b->parity + nsteps) & 1);
+    b->step += nsteps;
+    for (int k = 0; k < b->n; ++k) {
+        b->inst[k]->cur = b->parity;
+        if (!b->frozen[k]) b->inst[k]->step += nsteps;
+    }
+}
+
+lbpf_status lbpf_batch_step(lbpf_batch* b, int64_t nsteps) {
+    if (lbpf_status s = batch_check(b)) return s;
+    if (nsteps < 0) return bfail(b, LBPF_E_INVALID, "nsteps must be >= 0");
+    int64_t done = 0;
+    while (nsteps - done >= b->graph_steps) {
+        hipError_t e = hipGraphLaunch(b->exec[b->parity], b->stream);
+        if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "graph launch: %s", hipGetErrorString(e));
+        batch_advance(b, b->graph_steps);
+        done += b->graph_steps;
+    }
+    for (; done < nsteps; ++done) {
+        hipError_t e = launch_batch(b->tile, b->d_insts, b->d_items, b->nitems, b->grid, b->parity, b->stream);
+        if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "batch kernel: %s", hipGetErrorString(e));
+        batch_advance(b, 1);
+    }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_batch_step_each(lbpf_batch* b, int64_t nsteps) {
+    if (lbpf_status s = batch_check(b)) return s;
+    if (nsteps < 0) return bfail(b, LBPF_E_INVALID, "nsteps must be >= 0");
+    for (int64_t t = 0; t < nsteps; ++t) {
+        for (int k = 0; k < b->n; ++k) {
+            lbpf_ctx* c = b->inst[k];
+            if (b->frozen[k]) {  // held fixed: copy the state into the other population copy
+                const int a = c->cur, o = 1 - a;
+                const size_t pb = (size_t)c->m.plane * sizeof(float);
+                hipError_t e = hipMemcpyAsync(plane(c, o ? kPlaneFB : kPlaneFA), plane(c, a ? kPlaneFB : kPlaneFA),
+                                              kFPlanes * pb, hipMemcpyDeviceToDevice, b->stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(plane(c, o ? kPlaneHB : kPlaneHA), plane(c, a ? kPlaneHB : kPlaneHA),
+                                       kHPlanes * pb, hipMemcpyDeviceToDevice, b->stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(plane(c, o ? kPlanePB : kPlanePA), plane(c, a ? kPlanePB : kPlanePA),
+                                       pb, hipMemcpyDeviceToDevice, b->stream);
+                if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "frozen copy: %s", hipGetErrorString(e));
+                c->cur = o;
+                continue;
+            }
+            const int tile = c->tile;
+            c->tile = b->tile;
+            lbpf_status s = lbpf_step(c, 1);
+            c->tile = tile;
+            if (s != LBPF_OK) return bfail(b, s, "instance %d: %s", k, c->err.c_str());
+        }
+        b->parity ^= 1;
+        b->step += 1;
+    }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_batch_status(lbpf_batch* b, int32_t* flags, lbpf_diag* diags) {
+    if (lbpf_status s = batch_check(b)) return s;
+    bool changed = false;
+    for (int k = 0; k < b->n; ++k) {
+        lbpf_diag d{};
+        lbpf_status s = lbpf_diagnostics(b->inst[k], &d);
+        if (s == LBPF_E_UNSTABLE && !b->frozen[k]) {
+            b->frozen[k] = 1;
+            changed = true;
+        } else if (s != LBPF_OK && s != LBPF_E_UNSTABLE) {
+            return bfail(b, s, "instance %d: %s", k, b->inst[k]->err.c_str());
+        }
+        if (diags) diags[k] = d;
+        if (flags) flags[k] = b->frozen[k];
+    }
+    if (changed) {
+        for (int k = 0; k < b->n; ++k) {
+            hipError_t e = hipMemcpy((char*)b->d_insts + sizeof(BatchInst) * k + offsetof(BatchInst, frozen),
+                                     &b->frozen[k], sizeof(int), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "freeze flags: %s", hipGetErrorString(e));
+        }
+    }
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_batch_set_tile(lbpf_batch* b, int32_t tile) {
+    if (!b) return LBPF_E_INVALID;
+    b->err.clear();
+    if (tile < 0 || tile >= tile_count()) return bfail(b, LBPF_E_INVALID, "tile index %d out of range", tile);
+    b->tile = tile;
+    return batch_setup(b);
+}
+
+int32_t lbpf_batch_get_tile(const lbpf_batch* b) { return b ? b->tile : -1; }
+
+lbpf_status lbpf_batch_state_size(const lbpf_batch* b, size_t* bytes) {
+    if (!b || !bytes) return LBPF_E_INVALID;
+    size_t total = 0;
+    for (int k = 0; k < b->n; ++k) {
+        size_t s = 0;
+        lbpf_state_size(b->inst[k], &s);
+        total += align256(s);
+    }
+    *bytes = total;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_batch_autotune(lbpf_batch* b, int32_t trial_steps, void* scratch_state,
+                                float* ms_out, int32_t* best_out) {
+    if (lbpf_status s = batch_check(b)) return s;
+    if (trial_steps < 1 || !scratch_state) return bfail(b, LBPF_E_INVALID, "trial_steps >= 1 and a state buffer are required");
+    std::vector<size_t> off(b->n);
+    size_t o = 0;
+    for (int k = 0; k < b->n; ++k) {
+        size_t sz = 0;
+        lbpf_state_size(b->inst[k], &sz);
+        off[k] = o;
+        o += align256(sz);
+        if (lbpf_status s = lbpf_save_state(b->inst[k], (char*)scratch_state + off[k])) return bfail(b, s, "save %d", k);
+    }
+    const int64_t keep_step = b->step;
+    std::vector<int64_t> keep_inst_step(b->n);
+    for (int k = 0; k < b->n; ++k) keep_inst_step[k] = b->inst[k]->step;
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "autotune events: %s", hipGetErrorString(e));
+    int best = b->tile;
+    float best_ms = 0.0f;
+    lbpf_status st = LBPF_OK;
+    for (int t = 0; t < tile_count() && st == LBPF_OK; ++t) {
+        if ((st = lbpf_batch_set_tile(b, t)) != LBPF_OK) break;
+        if ((st = lbpf_batch_step(b, 1)) != LBPF_OK) break;
+        e = hipEventRecord(e0, b->stream);
+        if (e == hipSuccess && (st = lbpf_batch_step(b, trial_steps)) == LBPF_OK) e = hipEventRecord(e1, b->stream);
+        float ms = 0.0f;
+        if (e == hipSuccess && st == LBPF_OK) e = hipEventSynchronize(e1);
+        if (e == hipSuccess && st == LBPF_OK) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { st = bfail(b, LBPF_E_HIP, "autotune timing: %s", hipGetErrorString(e)); break; }
+        ms /= (float)trial_steps;
+        if (ms_out) ms_out[t] = ms;
+        if (t == 0 || ms < best_ms) { best_ms = ms; best = t; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != LBPF_OK) return st;
+    // restore: every instance state back into copy A, then the batch continues from parity 0
+    for (int k = 0; k < b->n; ++k)
+        if (lbpf_status s = lbpf_load_state(b->inst[k], (char*)scratch_state + off[k])) return bfail(b, s, "load %d", k);
+    b->parity = 0;
+    b->step = keep_step;
+    for (int k = 0; k < b->n; ++k) {
+        b->inst[k]->cur = 0;
+        b->inst[k]->step = keep_inst_step[k];
+    }
+    if (lbpf_status s = lbpf_batch_set_tile(b, best)) return s;
+    if (best_out) *best_out = best;
+    return LBPF_OK;
+}
+
+int64_t lbpf_batch_step_count(const lbpf_batch* b) { return b ? b->step : -1; }
+
+lbpf_status lbpf_batch_destroy(lbpf_batch* b) {
+    if (!b) return LBPF_OK;
+    destroy_graphs(b);
+    for (lbpf_ctx* c : b->inst) lbpf_destroy(c);
+    delete b;
+    return LBPF_OK;
+}
+
+const char* lbpf_batch_last_error(const lbpf_batch* b) { return b ? b->err.c_str() : "NULL handle"; }
 
 }  // extern "C"

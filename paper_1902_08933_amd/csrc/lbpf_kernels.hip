@@ -119,32 +119,42 @@ __device__ __forceinline__ void march_load(const Model& m, const float* __restri
     }
 }
 
-template <int TX, int NT, int CH, bool PF, bool COLLIDE>
-__global__ __launch_bounds__(NT) void strip_kernel(Model m, const float* __restrict__ fin,
-                                                   float* __restrict__ fout,
-                                                   const float* __restrict__ hin,
-                                                   float* __restrict__ hout,
-                                                   const float* __restrict__ pin,
-                                                   float* __restrict__ pout,
-                                                   float* __restrict__ phiu,
-                                                   float* __restrict__ fields, int nsx, int nsy) {
-    constexpr int TY = NT / TX;              // rows per step of the march
-    constexpr int PX = TX + 4, MX = TX + 2;  // phi ring columns, mu/p ring columns
+// LDS of one marching workgroup
+template <int TX, int NT>
+struct MarchLds {
+    static constexpr int TY = NT / TX;              // rows per step of the march
+    static constexpr int PX = TX + 4, MX = TX + 2;  // phi ring columns, mu/p ring columns
     // ring rows: at least 2 TY + 4 (phi) and 2 TY + 2 (mu, p) so that the rows written by one
-    // step of the march never alias rows another thread may still read from the previous step;
-    // a power of two so that a row's slot is (row & (R - 1)), also for the ghost rows -1, -2
-    constexpr int RP = ring_rows(2 * TY + 4);
-    constexpr int RM = ring_rows(2 * TY + 2);
+    // step of the march never alias rows another thread may still read from the previous
+    // step; a power of two so that a row's slot is (row & (R - 1)), also for rows -1, -2
+    static constexpr int RP = ring_rows(2 * TY + 4);
+    static constexpr int RM = ring_rows(2 * TY + 2);
+    float phh[RP * PX];
+    float phl[RP * PX];
+    float mu[RM * MX];
+    float p[RM * MX];
+};
+
+// One workgroup marches the chunk of a strip starting at column x0, rows ys .. ys+CH-1
+// (clipped to the grid), of one simulation.
+template <int TX, int NT, int CH, bool PF, bool COLLIDE>
+__device__ __forceinline__ void march_chunk(const Model& m, const float* __restrict__ fin,
+                                            float* __restrict__ fout,
+                                            const float* __restrict__ hin,
+                                            float* __restrict__ hout,
+                                            const float* __restrict__ pin,
+                                            float* __restrict__ pout, float* __restrict__ phiu,
+                                            float* __restrict__ fields, int x0, int ys,
+                                            MarchLds<TX, NT>& S) {
+    using L_ = MarchLds<TX, NT>;
+    constexpr int TY = L_::TY, PX = L_::PX, MX = L_::MX, RP = L_::RP, RM = L_::RM;
     static_assert(NT % TX == 0 && TY >= 2 && CH % TY == 0 && TX >= 6, "strip/thread mapping");
-    __shared__ float s_phh[RP * PX];
-    __shared__ float s_phl[RP * PX];
-    __shared__ float s_mu[RM * MX];
-    __shared__ float s_p[RM * MX];
+    float* s_phh = S.phh;
+    float* s_phl = S.phl;
+    float* s_mu = S.mu;
+    float* s_p = S.p;
     auto prow = [](int r) { return (r & (RP - 1)) * PX; };
     auto mrow = [](int r) { return (r & (RM - 1)) * MX; };
-
-    const int blk = xcd_tile(blockIdx.x, nsx * nsy);
-    const int x0 = (blk % nsx) * TX, ys = (blk / nsx) * CH;
     const int nx = m.nx, ny = m.ny, pitch = m.pitch;
     const int ye = min(ys + CH, ny);
     const long long P = m.plane;
@@ -222,6 +232,21 @@ __global__ __launch_bounds__(NT) void strip_kernel(Model m, const float* __restr
         }
         if (!PF && Y + TY < ye) march_load<TX, TY>(m, fin, hin, pin, phiu, x0, Y + TY, ye, tid, L);
     }
+}
+
+template <int TX, int NT, int CH, bool PF, bool COLLIDE>
+__global__ __launch_bounds__(NT) void strip_kernel(Model m, const float* __restrict__ fin,
+                                                   float* __restrict__ fout,
+                                                   const float* __restrict__ hin,
+                                                   float* __restrict__ hout,
+                                                   const float* __restrict__ pin,
+                                                   float* __restrict__ pout,
+                                                   float* __restrict__ phiu,
+                                                   float* __restrict__ fields, int nsx, int nsy) {
+    __shared__ MarchLds<TX, NT> S;
+    const int blk = xcd_tile(blockIdx.x, nsx * nsy);
+    march_chunk<TX, NT, CH, PF, COLLIDE>(m, fin, fout, hin, hout, pin, pout, phiu, fields,
+                                         (blk % nsx) * TX, (blk / nsx) * CH, S);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -446,6 +471,95 @@ static hipError_t launch_fused(int tile, const Model& m, const float* fin, float
         LBPF_STRIP_CASES(C)
         default: return hipErrorInvalidValue;
     }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Batched persistent step: every workgroup loops over the work list of (instance, chunk)
+// items of all simulations of a batch, with a stride of the grid size; each item is one
+// march_chunk of that instance with its own model constants, so each instance evolves
+// bit-identically to a single-simulation launch. `parity` selects the population copy read.
+// A frozen instance's chunk is copied through unchanged so that all instances share parity.
+// ---------------------------------------------------------------------------------------------
+template <int TX, int NT>
+__device__ __forceinline__ void copy_chunk(const Model& m, const float* fin, float* fout,
+                                           const float* hin, float* hout, const float* pin,
+                                           float* pout, int x0, int ys, int ch) {
+    const int w = min(TX, m.nx - x0), h = min(ch, m.ny - ys);
+    for (int i = threadIdx.x; i < w * h; i += NT) {
+        const long long c = (long long)(ys + i / w) * m.pitch + x0 + i % w;
+        for (int q = 0; q < kFPlanes; ++q) fout[q * m.plane + c] = fin[q * m.plane + c];
+        for (int q = 0; q < kHPlanes; ++q) hout[q * m.plane + c] = hin[q * m.plane + c];
+        pout[c] = pin[c];
+    }
+}
+
+template <int TX, int NT, int CH, bool PF>
+__global__ __launch_bounds__(NT) void batch_kernel(const BatchInst* __restrict__ insts,
+                                                   const BatchItem* __restrict__ items,
+                                                   int nitems, int parity) {
+    __shared__ MarchLds<TX, NT> S;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const BatchItem w = items[it];
+        const BatchInst& I = insts[w.inst];
+        const Model m = I.m;
+        float* ws = I.ws;
+        const long long P = m.plane;
+        const int a = parity, b = 1 - parity;
+        const float* fin = ws + (a ? kPlaneFB : kPlaneFA) * P;
+        float* fout = ws + (b ? kPlaneFB : kPlaneFA) * P;
+        const float* hin = ws + (a ? kPlaneHB : kPlaneHA) * P;
+        float* hout = ws + (b ? kPlaneHB : kPlaneHA) * P;
+        const float* pin = ws + (a ? kPlanePB : kPlanePA) * P;
+        float* pout = ws + (b ? kPlanePB : kPlanePA) * P;
+        float* phiu = ws + kPlanePhiU * P;
+        const int x0 = (w.chunk % I.nsx) * TX, ys = (w.chunk / I.nsx) * CH;
+        if (I.frozen)
+            copy_chunk<TX, NT>(m, fin, fout, hin, hout, pin, pout, x0, ys, CH);
+        else
+            march_chunk<TX, NT, CH, PF, true>(m, fin, fout, hin, hout, pin, pout, phiu, nullptr,
+                                              x0, ys, S);
+        __syncthreads();  // LDS is reused by the next item
+    }
+}
+
+template <int TX, int NT, int CH, bool PF>
+static void* batch_fn() { return reinterpret_cast<void*>(&batch_kernel<TX, NT, CH, PF>); }
+
+// Kernel entry, workgroup size, strip width and chunk rows of the batched kernel for a strip
+// shape; occupancy (resident workgroups per CU) for sizing the persistent grid.
+hipError_t batch_kernel_info(int tile, void** fn, int* nt, int* tx, int* ch, int* per_cu) {
+    switch (tile) {
+        case 0: *fn = batch_fn<64, 256, 4, false>(); break;
+        case 1: *fn = batch_fn<64, 256, 16, false>(); break;
+        case 2: *fn = batch_fn<64, 256, 64, false>(); break;
+        case 3: *fn = batch_fn<128, 256, 64, false>(); break;
+        case 4: *fn = batch_fn<128, 256, 16, false>(); break;
+        case 5: *fn = batch_fn<64, 256, 16, true>(); break;
+        case 6: *fn = batch_fn<64, 256, 64, true>(); break;
+        case 7: *fn = batch_fn<128, 256, 64, true>(); break;
+        case 8: *fn = batch_fn<64, 512, 64, true>(); break;
+        case 9: *fn = batch_fn<32, 128, 32, false>(); break;
+        case 10: *fn = batch_fn<64, 128, 32, false>(); break;
+        case 11: *fn = batch_fn<256, 512, 64, false>(); break;
+        default: return hipErrorInvalidValue;
+    }
+    *tx = kStrips[tile].tx;
+    *nt = kStrips[tile].nt;
+    *ch = kStrips[tile].ch;
+    int blocks = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void*)*fn, *nt, 0);
+    *per_cu = (e == hipSuccess && blocks > 0) ? blocks : 1;
+    return e;
+}
+
+hipError_t launch_batch(int tile, const BatchInst* insts, const BatchItem* items, int nitems,
+                        int grid, int parity, hipStream_t st) {
+    void* fn;
+    int nt, tx, ch, per;
+    hipError_t e = batch_kernel_info(tile, &fn, &nt, &tx, &ch, &per);
+    if (e != hipSuccess) return e;
+    void* args[] = {(void*)&insts, (void*)&items, (void*)&nitems, (void*)&parity};
+    return hipLaunchKernel(fn, dim3(grid), dim3(nt), args, 0, st);
 }
 
 hipError_t launch_step(int tile, const Model& m, const float* fin, float* fout, const float* hin,

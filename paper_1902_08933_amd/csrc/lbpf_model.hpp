@@ -63,6 +63,19 @@ struct Model {
     double d_beta, d_kappa, d_rhoA, d_rhoB;
 };
 
+// One simulation of a batch, as the batched kernel sees it (device memory).
+struct BatchInst {
+    Model m;
+    float* ws;        // base of the instance's workspace (planes as above)
+    int nsx, nsy;     // strips and chunks of the batch's strip shape
+    int frozen;       // nonzero: a non-finite state was detected; the instance is held fixed
+    int pad;
+};
+// One unit of work of the batched kernel: chunk `chunk` (row-major over nsx x nsy) of `inst`.
+struct BatchItem {
+    int inst, chunk;
+};
+
 // Deterministic reduction results (FP64).
 struct DiagOut {
     double sum_phi, sum_rho, max_u, nonfinite;

@@ -69,6 +69,23 @@ SIGNATURES = {
     "lbpf_step_count": (ctypes.c_int64, [_V]),
     "lbpf_bw_probe": (_S, [ctypes.c_int32, _V, _V, ctypes.c_size_t, ctypes.c_int32, _V]),
     "lbpf_destroy": (_S, [_V]),
+    "lbpf_batch_workspace_size": (_S, [ctypes.c_int32, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]),
+    "lbpf_batch_create": (_S, [ctypes.c_int32, ctypes.POINTER(Params), _V, ctypes.c_size_t, _V,
+                               ctypes.POINTER(_V)]),
+    "lbpf_batch_init": (_S, [_V, ctypes.c_int32, _V, _V, _V, _V]),
+    "lbpf_batch_step": (_S, [_V, ctypes.c_int64]),
+    "lbpf_batch_step_each": (_S, [_V, ctypes.c_int64]),
+    "lbpf_batch_status": (_S, [_V, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Diag)]),
+    "lbpf_batch_instance": (_V, [_V, ctypes.c_int32]),
+    "lbpf_batch_count": (ctypes.c_int32, [_V]),
+    "lbpf_batch_set_tile": (_S, [_V, ctypes.c_int32]),
+    "lbpf_batch_get_tile": (ctypes.c_int32, [_V]),
+    "lbpf_batch_state_size": (_S, [_V, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbpf_batch_autotune": (_S, [_V, ctypes.c_int32, _V, ctypes.POINTER(ctypes.c_float),
+                                 ctypes.POINTER(ctypes.c_int32)]),
+    "lbpf_batch_step_count": (ctypes.c_int64, [_V]),
+    "lbpf_batch_destroy": (_S, [_V]),
+    "lbpf_batch_last_error": (ctypes.c_char_p, [_V]),
     "lbpf_status_string": (ctypes.c_char_p, [_S]),
     "lbpf_last_error": (ctypes.c_char_p, [_V]),
     "lbpf_create_error": (ctypes.c_char_p, []),
@@ -268,3 +285,119 @@ class Simulation:
     @property
     def step_count(self):
         return int(self.lib.lbpf_step_count(self._h))
+
+
+class _InstanceView(Simulation):
+    """A batch instance seen through the single-simulation calls (read, diagnostics, ...)."""
+
+    def __init__(self, batch, idx):  # noqa: D107 - no workspace of its own
+        self.torch = batch.torch
+        self.lib = batch.lib
+        self.device = batch.device
+        self.cfg = batch.cfgs[idx]
+        self.params = make_params(self.cfg)
+        self.nx, self.ny = self.params.nx, self.params.ny
+        self._h = ctypes.c_void_p(self.lib.lbpf_batch_instance(batch._h, idx))
+        self._batch = batch  # keeps the owner alive
+
+    def __del__(self):
+        pass  # the batch owns the handle
+
+    def init(self, *a, **k):
+        raise RuntimeError("initialize batch instances with Batch.init")
+
+    def step(self, n=1):
+        raise RuntimeError("step batch instances with Batch.step")
+
+
+class Batch:
+    """Many independent simulations advanced by one persistent launch per step."""
+
+    def __init__(self, cfgs, device="cuda"):
+        import torch
+        self.torch = torch
+        self.lib = library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lbpf solver runs only on the GPU")
+        self.device = torch.device(device)
+        self.cfgs = [dict(c) for c in cfgs]
+        n = len(self.cfgs)
+        self._params = (Params * n)(*[make_params(c) for c in self.cfgs])
+        nb = ctypes.c_size_t()
+        _check(self.lib.lbpf_batch_workspace_size(n, self._params, ctypes.byref(nb)))
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        h = ctypes.c_void_p()
+        _check(self.lib.lbpf_batch_create(n, self._params, ctypes.c_void_p(self.workspace.data_ptr()),
+                                          ctypes.c_size_t(nb.value), ctypes.c_void_p(stream),
+                                          ctypes.byref(h)))
+        self._h = h
+        self.n = n
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.lib.lbpf_batch_destroy(h)
+            self._h = None
+
+    def _c(self, status):
+        if status != 0:
+            raise LbpfError(status, (self.lib.lbpf_batch_last_error(self._h) or b"").decode())
+
+    def init(self, idx, phi, ux=None, uy=None, p=None):
+        c = self.cfgs[idx]
+        shape = (int(c["ny"]), int(c["nx"]))
+        ts = []
+        for a in (phi, ux, uy, p):
+            if a is None:
+                ts.append(None)
+                continue
+            t = self.torch.as_tensor(a, dtype=self.torch.float32, device=self.device).contiguous()
+            if tuple(t.shape) != shape:
+                raise ValueError(f"instance {idx}: field shape {tuple(t.shape)} != {shape}")
+            ts.append(t)
+        ptrs = [None if t is None else ctypes.c_void_p(t.data_ptr()) for t in ts]
+        self._c(self.lib.lbpf_batch_init(self._h, int(idx), *ptrs))
+        self.torch.cuda.current_stream(self.device).synchronize()
+        return self
+
+    def step(self, n=1):
+        self._c(self.lib.lbpf_batch_step(self._h, int(n)))
+        return self
+
+    def step_each(self, n=1):
+        self._c(self.lib.lbpf_batch_step_each(self._h, int(n)))
+        return self
+
+    def status(self):
+        flags = (ctypes.c_int32 * self.n)()
+        diags = (Diag * self.n)()
+        self._c(self.lib.lbpf_batch_status(self._h, flags, diags))
+        return list(flags), [dict(sum_phi=d.sum_phi, sum_rho=d.sum_rho, max_u=d.max_u,
+                                  nonfinite=d.nonfinite, step=d.step) for d in diags]
+
+    def instance(self, idx):
+        return _InstanceView(self, idx)
+
+    def set_tile(self, index):
+        self._c(self.lib.lbpf_batch_set_tile(self._h, int(index)))
+        return self
+
+    @property
+    def tile(self):
+        return int(self.lib.lbpf_batch_get_tile(self._h))
+
+    @property
+    def step_count(self):
+        return int(self.lib.lbpf_batch_step_count(self._h))
+
+    def autotune(self, trial_steps=10):
+        nb = ctypes.c_size_t()
+        self._c(self.lib.lbpf_batch_state_size(self._h, ctypes.byref(nb)))
+        scratch = self.torch.empty(nb.value, dtype=self.torch.uint8, device=self.device)
+        n = self.lib.lbpf_tile_count()
+        ms = (ctypes.c_float * n)()
+        best = ctypes.c_int32()
+        self._c(self.lib.lbpf_batch_autotune(self._h, int(trial_steps), ctypes.c_void_p(scratch.data_ptr()),
+                                             ms, ctypes.byref(best)))
+        return best.value, list(ms)
