@@ -227,6 +227,64 @@ int64_t lbpf_batch_step_count(const lbpf_batch* b);
 lbpf_status lbpf_batch_destroy(lbpf_batch* b);
 const char* lbpf_batch_last_error(const lbpf_batch* b);
 
+/* ------------------------------------------------------------------------------------------
+ * Learned surrogate: a 4-level convolutional U-Net (level widths base_ch << l, l = 0..3; 3x3
+ * convolutions with circular padding, 2x2 average pooling, nearest upsampling, skip
+ * concatenation, 1x1 head) mapping the fields (phi, u_x, u_y, p) of the solver at time t to
+ * time t + K. It adds a predicted change to its input. BF16 weights and activations, FP32
+ * accumulation on MFMA, FP32 master weights and Adam moments. Fields are FP32 NHWC
+ * [n][h][w][in_ch] device arrays; h and w multiples of 8. Errors via lbpf_unet_last_error().
+ * ------------------------------------------------------------------------------------------ */
+typedef struct lbpf_unet lbpf_unet;
+typedef struct lbpf_unet_cfg {
+    int32_t in_ch;        /* field channels, 1..16 (4: phi, u_x, u_y, p) */
+    int32_t base_ch;      /* width of level 0 (16, 32, ... 128); 32 gives ~0.97 M parameters */
+    int32_t max_batch;    /* largest n * h * w the workspace holds is max_batch*max_h*max_w */
+    int32_t max_h, max_w; /* multiples of 8 */
+    int32_t train;        /* nonzero: workspace includes gradients and Adam moments */
+    int32_t wgrad_chunks; /* pixel chunks of the weight-gradient reduction (0: 64) */
+    int32_t pad;
+    uint64_t seed;        /* He-normal initial weights; the head starts at zero */
+} lbpf_unet_cfg;
+
+lbpf_status lbpf_unet_workspace_size(const lbpf_unet_cfg* cfg, size_t* bytes);
+lbpf_status lbpf_unet_create(const lbpf_unet_cfg* cfg, void* workspace, size_t workspace_bytes,
+                             void* hip_stream, lbpf_unet** out);
+int64_t lbpf_unet_param_count(const lbpf_unet* u);
+/* Layer i (0..7: encoder 0..3, decoder 2, 1, 0, head): offsets of its weights
+ * [cout][ks*ks][cin] and bias [cout] in the flat FP32 parameter vector. */
+lbpf_status lbpf_unet_layer(const lbpf_unet* u, int32_t i, int64_t* woff, int64_t* boff,
+                            int32_t* cout, int32_t* ks, int32_t* cin);
+/* Copy the FP32 master parameters out of / into the network (device arrays of
+ * lbpf_unet_param_count() floats); setting also resets the Adam moments. */
+lbpf_status lbpf_unet_get_params(lbpf_unet* u, float* dst_device);
+lbpf_status lbpf_unet_set_params(lbpf_unet* u, const float* src_device);
+/* Per-channel weights of the squared-error loss (16 host floats; channels >= in_ch ignored). */
+lbpf_status lbpf_unet_set_loss_weights(lbpf_unet* u, const float* host_weights);
+/* Inference: out = in + net(in). Asynchronous. */
+lbpf_status lbpf_unet_forward(lbpf_unet* u, const float* in, float* out, int32_t n, int32_t h,
+                              int32_t w);
+/* Loss (mean over pixels and in_ch channels of w_c (out - target)^2) and its gradient with
+ * respect to the flat parameters (grad_device may be NULL). Synchronizes the stream. */
+lbpf_status lbpf_unet_loss_grad(lbpf_unet* u, const float* in, const float* target, int32_t n,
+                                int32_t h, int32_t w, double* loss_host, float* grad_device);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8) on the loss above; *loss_host before the update. */
+lbpf_status lbpf_unet_train_step(lbpf_unet* u, const float* in, const float* target, int32_t n,
+                                 int32_t h, int32_t w, float lr, double* loss_host);
+lbpf_status lbpf_unet_destroy(lbpf_unet* u);
+const char* lbpf_unet_last_error(const lbpf_unet* u);
+/* One 16x16x16 BF16 matrix product on MFMA (row-major A, B bf16; D FP32, device arrays):
+ * the operand-layout check of the surrogate kernels. */
+lbpf_status lbpf_mfma_probe(const void* A, const void* B, float* D, void* hip_stream);
+
+/* Hand-over between the solver and the surrogate: the current fields of a simulation as
+ * normalized NHWC [ny][nx][4] FP32, (field - shift[c]) / scale[c] for c = phi, u_x, u_y, p
+ * (host arrays of 4); and a new state from such fields (equilibria as in lbpf_init, the step
+ * count is kept). Asynchronous. */
+lbpf_status lbpf_fields_to_nhwc(lbpf_ctx* ctx, float* dst, const float* shift, const float* scale);
+lbpf_status lbpf_init_from_nhwc(lbpf_ctx* ctx, const float* src, const float* shift,
+                                const float* scale);
+
 #ifdef __cplusplus
 }
 #endif

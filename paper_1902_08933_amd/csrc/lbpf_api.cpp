@@ -32,6 +32,10 @@ hipError_t launch_laplace(const Model& m, const float* h, const float* fields, d
                           hipStream_t st);
 hipError_t launch_probe(int mode, const void* src, void* dst, size_t bytes, int blocks, hipStream_t st);
 hipError_t batch_kernel_info(int tile, void** fn, int* nt, int* tx, int* ch, int* per_cu);
+hipError_t launch_fields_to_nhwc(const Model& m, const float* fields, float* dst, const float* shift,
+                                 const float* scale, hipStream_t st);
+hipError_t launch_nhwc_to_dense(const Model& m, const float* src, float* phi, float* ux, float* uy,
+                                float* p, const float* shift, const float* scale, hipStream_t st);
 hipError_t launch_batch(int tile, const BatchInst* insts, const BatchItem* items, int nitems,
                         int grid, int parity, hipStream_t st);
 }  // namespace lbpf
@@ -382,6 +386,34 @@ lbpf_status lbpf_autotune(lbpf_ctx* c, int32_t trial_steps, void* scratch_state,
     c->step = step0;
     c->tile = best;
     if (best_out) *best_out = best;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_fields_to_nhwc(lbpf_ctx* c, float* dst, const float* shift, const float* scale) {
+    if (lbpf_status s = check_ctx(c, true)) return s;
+    if (!dst || !shift || !scale) return fail(c, LBPF_E_INVALID, "NULL argument");
+    for (int k = 0; k < 4; ++k)
+        if (!(scale[k] != 0.0f) || !std::isfinite(scale[k]) || !std::isfinite(shift[k]))
+            return fail(c, LBPF_E_INVALID, "scale must be finite and nonzero, shift finite");
+    if (((uintptr_t)dst) % 16) return fail(c, LBPF_E_INVALID, "dst must be 16-byte aligned");
+    if (lbpf_status s = run_fields(c)) return s;
+    hipError_t e = launch_fields_to_nhwc(c->m, plane(c, kPlaneFields), dst, shift, scale, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "fields to NHWC");
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_init_from_nhwc(lbpf_ctx* c, const float* src, const float* shift, const float* scale) {
+    if (lbpf_status s = check_ctx(c, false)) return s;
+    if (!src || !shift || !scale) return fail(c, LBPF_E_INVALID, "NULL argument");
+    if (((uintptr_t)src) % 16) return fail(c, LBPF_E_INVALID, "src must be 16-byte aligned");
+    // dense fields in the field scratch planes (each plane holds at least nx*ny floats)
+    float* d[4];
+    for (int k = 0; k < 4; ++k) d[k] = plane(c, kPlaneFields + k);
+    hipError_t e = launch_nhwc_to_dense(c->m, src, d[0], d[1], d[2], d[3], shift, scale, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "NHWC to fields");
+    const int64_t step = c->step;
+    if (lbpf_status s = init_copy(c, c->cur, d[0], d[1], d[2], d[3])) return s;
+    c->step = step;
     return LBPF_OK;
 }
 

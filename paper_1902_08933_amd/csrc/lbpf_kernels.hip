@@ -651,4 +651,49 @@ hipError_t launch_probe(int mode, const void* src, void* dst, size_t bytes, int 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------------
+// Hand-over between the solver and the surrogate: normalized NHWC [ny][nx][4] fields
+// ---------------------------------------------------------------------------------------------
+__global__ void fields_to_nhwc_kernel(Model m, const float* __restrict__ fields, float* __restrict__ dst,
+                                      float4 shift, float4 inv_scale) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= m.nx || y >= m.ny) return;
+    const long long cell = (long long)y * m.pitch + x, P = m.plane;
+    float4 v;
+    v.x = (fields[cell] - shift.x) * inv_scale.x;          // phi
+    v.y = (fields[2 * P + cell] - shift.y) * inv_scale.y;  // u_x
+    v.z = (fields[3 * P + cell] - shift.z) * inv_scale.z;  // u_y
+    v.w = (fields[4 * P + cell] - shift.w) * inv_scale.w;  // p
+    reinterpret_cast<float4*>(dst)[(long long)y * m.nx + x] = v;
+}
+
+__global__ void nhwc_to_dense_kernel(Model m, const float* __restrict__ src, float* __restrict__ phi,
+                                     float* __restrict__ ux, float* __restrict__ uy,
+                                     float* __restrict__ p, float4 shift, float4 scale) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= m.nx || y >= m.ny) return;
+    const long long i = (long long)y * m.nx + x;
+    const float4 v = reinterpret_cast<const float4*>(src)[i];
+    phi[i] = v.x * scale.x + shift.x;
+    ux[i] = v.y * scale.y + shift.y;
+    uy[i] = v.z * scale.z + shift.z;
+    p[i] = v.w * scale.w + shift.w;
+}
+
+hipError_t launch_fields_to_nhwc(const Model& m, const float* fields, float* dst, const float* shift,
+                                 const float* scale, hipStream_t st) {
+    const float4 sh = make_float4(shift[0], shift[1], shift[2], shift[3]);
+    const float4 is = make_float4(1.0f / scale[0], 1.0f / scale[1], 1.0f / scale[2], 1.0f / scale[3]);
+    hipLaunchKernelGGL(fields_to_nhwc_kernel, dim3((m.nx + 255) / 256, m.ny), dim3(256), 0, st, m, fields, dst, sh, is);
+    return hipGetLastError();
+}
+
+hipError_t launch_nhwc_to_dense(const Model& m, const float* src, float* phi, float* ux, float* uy,
+                                float* p, const float* shift, const float* scale, hipStream_t st) {
+    const float4 sh = make_float4(shift[0], shift[1], shift[2], shift[3]);
+    const float4 sc = make_float4(scale[0], scale[1], scale[2], scale[3]);
+    hipLaunchKernelGGL(nhwc_to_dense_kernel, dim3((m.nx + 255) / 256, m.ny), dim3(256), 0, st, m, src, phi, ux, uy, p, sh, sc);
+    return hipGetLastError();
+}
+
 }  // namespace lbpf

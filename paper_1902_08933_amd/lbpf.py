@@ -401,3 +401,156 @@ class Batch:
         self._c(self.lib.lbpf_batch_autotune(self._h, int(trial_steps), ctypes.c_void_p(scratch.data_ptr()),
                                              ms, ctypes.byref(best)))
         return best.value, list(ms)
+
+
+class UNetCfg(ctypes.Structure):
+    _fields_ = [("in_ch", ctypes.c_int32), ("base_ch", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("max_h", ctypes.c_int32),
+                ("max_w", ctypes.c_int32), ("train", ctypes.c_int32),
+                ("wgrad_chunks", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+_PF = ctypes.POINTER(ctypes.c_float)
+_PD = ctypes.POINTER(ctypes.c_double)
+SIGNATURES.update({
+    "lbpf_unet_workspace_size": (_S, [ctypes.POINTER(UNetCfg), ctypes.POINTER(ctypes.c_size_t)]),
+    "lbpf_unet_create": (_S, [ctypes.POINTER(UNetCfg), _V, ctypes.c_size_t, _V, ctypes.POINTER(_V)]),
+    "lbpf_unet_param_count": (ctypes.c_int64, [_V]),
+    "lbpf_unet_layer": (_S, [_V, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "lbpf_unet_get_params": (_S, [_V, _V]),
+    "lbpf_unet_set_params": (_S, [_V, _V]),
+    "lbpf_unet_set_loss_weights": (_S, [_V, _PF]),
+    "lbpf_unet_forward": (_S, [_V, _V, _V, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "lbpf_unet_loss_grad": (_S, [_V, _V, _V, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _PD, _V]),
+    "lbpf_unet_train_step": (_S, [_V, _V, _V, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_float, _PD]),
+    "lbpf_unet_destroy": (_S, [_V]),
+    "lbpf_unet_last_error": (ctypes.c_char_p, [_V]),
+    "lbpf_mfma_probe": (_S, [_V, _V, _V, _V]),
+    "lbpf_fields_to_nhwc": (_S, [_V, _V, _PF, _PF]),
+    "lbpf_init_from_nhwc": (_S, [_V, _V, _PF, _PF]),
+})
+
+
+def _f4(v):
+    return (ctypes.c_float * 4)(*[float(a) for a in v])
+
+
+def fields_to_nhwc(sim, shift, scale, out=None):
+    """Current fields (phi, u_x, u_y, p) of a simulation as normalized NHWC [ny, nx, 4]."""
+    torch = sim.torch
+    t = out if out is not None else torch.empty((sim.ny, sim.nx, 4), dtype=torch.float32, device=sim.device)
+    sim._c(sim.lib.lbpf_fields_to_nhwc(sim._h, ctypes.c_void_p(t.data_ptr()), _f4(shift), _f4(scale)))
+    return t
+
+
+def init_from_nhwc(sim, src, shift, scale):
+    """Replace the state of a simulation by equilibria of normalized NHWC fields."""
+    sim._c(sim.lib.lbpf_init_from_nhwc(sim._h, ctypes.c_void_p(src.data_ptr()), _f4(shift), _f4(scale)))
+    return sim
+
+
+def mfma_probe(A_bf16_bits, B_bf16_bits, D):
+    """One 16x16x16 MFMA product; A, B int16 tensors holding BF16 bits, D float32 16x16."""
+    import torch
+    lib = library()
+    st = lib.lbpf_mfma_probe(ctypes.c_void_p(A_bf16_bits.data_ptr()), ctypes.c_void_p(B_bf16_bits.data_ptr()),
+                             ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != 0:
+        raise LbpfError(st, "mfma probe")
+    return D
+
+
+class UNet:
+    """The learned surrogate (see include/lbpf.h): forward, loss/gradient, Adam step."""
+
+    def __init__(self, in_ch=4, base_ch=32, max_batch=1, max_h=256, max_w=256, train=True,
+                 wgrad_chunks=0, seed=0, device="cuda"):
+        import torch
+        self.torch = torch
+        self.lib = library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the surrogate runs only on the GPU")
+        self.device = torch.device(device)
+        self.cfg = UNetCfg(in_ch, base_ch, max_batch, max_h, max_w, int(bool(train)), wgrad_chunks, 0, seed)
+        nb = ctypes.c_size_t()
+        st = self.lib.lbpf_unet_workspace_size(ctypes.byref(self.cfg), ctypes.byref(nb))
+        if st != 0:
+            raise LbpfError(st, self.lib.lbpf_unet_last_error(None).decode())
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        st = self.lib.lbpf_unet_create(ctypes.byref(self.cfg), ctypes.c_void_p(self.workspace.data_ptr()),
+                                       nb, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream),
+                                       ctypes.byref(h))
+        if st != 0:
+            raise LbpfError(st, self.lib.lbpf_unet_last_error(None).decode())
+        self._h = h
+        self.in_ch = in_ch
+        self.nparam = int(self.lib.lbpf_unet_param_count(h))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.lib.lbpf_unet_destroy(h)
+            self._h = None
+
+    def _c(self, st):
+        if st != 0:
+            raise LbpfError(st, (self.lib.lbpf_unet_last_error(self._h) or b"").decode())
+
+    def layers(self):
+        out = []
+        for i in range(8):
+            wo, bo = ctypes.c_int64(), ctypes.c_int64()
+            co, ks, ci = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            self._c(self.lib.lbpf_unet_layer(self._h, i, ctypes.byref(wo), ctypes.byref(bo), ctypes.byref(co),
+                                             ctypes.byref(ks), ctypes.byref(ci)))
+            out.append(dict(woff=wo.value, boff=bo.value, cout=co.value, ks=ks.value, cin=ci.value))
+        return out
+
+    def get_params(self):
+        t = self.torch.empty(self.nparam, dtype=self.torch.float32, device=self.device)
+        self._c(self.lib.lbpf_unet_get_params(self._h, ctypes.c_void_p(t.data_ptr())))
+        return t
+
+    def set_params(self, t):
+        t = t.to(self.device, self.torch.float32).contiguous()
+        self._c(self.lib.lbpf_unet_set_params(self._h, ctypes.c_void_p(t.data_ptr())))
+
+    def set_loss_weights(self, w):
+        arr = (ctypes.c_float * 16)(*([float(v) for v in w] + [0.0] * (16 - len(w))))
+        self._c(self.lib.lbpf_unet_set_loss_weights(self._h, arr))
+
+    def _chk(self, x):
+        if not (x.is_cuda and x.dtype == self.torch.float32 and x.is_contiguous() and x.dim() == 4
+                and x.shape[3] == self.in_ch):
+            raise ValueError("expected a contiguous float32 NHWC tensor on the GPU")
+        return x.shape[0], x.shape[1], x.shape[2]
+
+    def forward(self, x, out=None):
+        n, h, w = self._chk(x)
+        y = out if out is not None else self.torch.empty_like(x)
+        self._c(self.lib.lbpf_unet_forward(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                           n, h, w))
+        return y
+
+    def loss_grad(self, x, target):
+        n, h, w = self._chk(x)
+        self._chk(target)
+        g = self.torch.empty(self.nparam, dtype=self.torch.float32, device=self.device)
+        loss = ctypes.c_double()
+        self._c(self.lib.lbpf_unet_loss_grad(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+                                             n, h, w, ctypes.byref(loss), ctypes.c_void_p(g.data_ptr())))
+        return loss.value, g
+
+    def train_step(self, x, target, lr):
+        n, h, w = self._chk(x)
+        self._chk(target)
+        loss = ctypes.c_double()
+        self._c(self.lib.lbpf_unet_train_step(self._h, ctypes.c_void_p(x.data_ptr()),
+                                              ctypes.c_void_p(target.data_ptr()), n, h, w, float(lr),
+                                              ctypes.byref(loss)))
+        return loss.value
