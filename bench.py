@@ -127,6 +127,86 @@ def batch_bench(steps, count=256, seed=0):
     return out
 
 
+def unet_flops(net, h, w):
+    """multiply-add FLOPs of one forward pass (2 per MAC) at h x w from the layer table"""
+    f = 0
+    for i, l in enumerate(net.layers()):
+        level = {0: 0, 1: 1, 2: 2, 3: 3, 4: 2, 5: 1, 6: 0, 7: 0}[i]
+        pix = (h >> level) * (w >> level)
+        f += 2 * pix * l["cout"] * l["ks"] ** 2 * l["cin"]
+    return f
+
+
+def surrogate_bench(train_steps=2000, cycles=3):
+    """Train the surrogate on solver trajectories (256^2), then compare the hybrid cycle (9
+    network strides of 50 steps + one 50-step LB stride with fallback) with 500 plain LB steps
+    on the 1024^2 spinodal from t = 1000."""
+    import numpy as np
+    import torch
+    from paper_1902_08933_amd import lbpf, surrogate as S, workloads as W
+    t0 = time.perf_counter()
+    xs, ys = S.generate_pairs(n=256, n_spinodal=28, n_merger=4, t0=1000, snapshots=24, seed=0)
+    perm = torch.from_numpy(np.random.default_rng(0).permutation(xs.shape[0])).cuda()
+    xs, ys = xs[perm].contiguous(), ys[perm].contiguous()
+    ntr = int(xs.shape[0] * 0.9)
+    net = lbpf.UNet(max_batch=8, max_h=256, max_w=256, train=True, seed=1)
+    losses = S.train(net, xs[:ntr], ys[:ntr], steps=train_steps, batch=8, lr=5e-4, log_every=0,
+                     loss_weights=[400.0, 1.0, 1.0, 1.0])
+    t_train = time.perf_counter() - t0
+    e_all, p_all = S.eval_one_stride(net, xs[ntr:], ys[ntr:])
+    k = min(8, xs.shape[0] - ntr)
+    e_phi = float(((net.forward(xs[ntr:ntr + k].contiguous())[..., 0] - ys[ntr:ntr + k, ..., 0]) ** 2).mean())
+    p_phi = float(((xs[ntr:ntr + k, ..., 0] - ys[ntr:ntr + k, ..., 0]) ** 2).mean())
+    del xs, ys
+    big = lbpf.UNet(max_batch=1, max_h=1024, max_w=1024, train=False, seed=1)
+    big.set_params(net.get_params())
+    x = torch.zeros(1, 1024, 1024, 4, device="cuda")
+    y = torch.empty_like(x)
+    big.forward(x, out=y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        big.forward(x, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 10
+    flops = unet_flops(big, 1024, 1024)
+    cfg, phi = W.spinodal(n=1024, seed=99)
+    lb = lbpf.Simulation(cfg).init(torch.from_numpy(phi.astype(np.float32)).cuda())
+    hy = lbpf.Simulation(cfg).init(torch.from_numpy(phi.astype(np.float32)).cuda())
+    lb.step(1000)
+    hy.step(1000)
+    bufs = S.hybrid_buffers(hy)
+    ckpt = torch.empty(hy.state_size(), dtype=torch.uint8, device="cuda")
+    rows = []
+    for c in range(cycles):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lb.step(500)
+        torch.cuda.synchronize()
+        t_lb = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        kept = S.hybrid_cycle(hy, big, bufs, ckpt=ckpt)
+        torch.cuda.synchronize()
+        t_hy = time.perf_counter() - t1
+        a = hy.read("phi").double().cpu().numpy()
+        b = lb.read("phi").double().cpu().numpy()
+        rows.append({"cycle": c, "lb_ms": round(t_lb * 1e3, 2), "hybrid_ms": round(t_hy * 1e3, 2),
+                     "network_kept": bool(kept), "phi_rel_l2": float(f"{S.phi_rel_l2(a, b):.4g}"),
+                     "domain_length_ratio": round(S.domain_length(a) / S.domain_length(b), 4)})
+    return {"net": "U-Net 32-256 ch, %d params, BF16 weights/activations, FP32 accumulate" % big.nparam,
+            "train": {"pairs": ntr, "steps": train_steps, "seconds": round(t_train, 1),
+                      "final_loss": float(f"{losses[-1]:.4g}")},
+            "one_stride_mse": {"network_phi": float(f"{e_phi:.4g}"), "persistence_phi": float(f"{p_phi:.4g}"),
+                               "network_all": float(f"{e_all:.4g}"), "persistence_all": float(f"{p_all:.4g}")},
+            "forward_1024": {"ms": round(fwd_ms, 3), "flop": flops,
+                             "TFLOPs": round(flops / (fwd_ms * 1e-3) / 1e12, 1),
+                             "frac_of_bf16_peak": round(flops / (fwd_ms * 1e-3) / 2.5e15, 4)},
+            "hybrid_vs_lb_1024": rows,
+            "speedup": round(sum(r["lb_ms"] for r in rows) / sum(r["hybrid_ms"] for r in rows), 2)}
+
+
 def cpu_baseline(cfg, phi, steps):
     import numpy as np
     import oracle
@@ -149,6 +229,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=80)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -208,6 +289,8 @@ def main():
     out["roofline"]["copy_probe_GBs"] = round(probe_copy_gbs(), 1)
     if not args.no_batch:
         out["batched"] = batch_bench(args.batch_steps)
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_bench()
     if not args.no_cpu_baseline:
         v, dt = cpu_baseline(cfg, phi, args.cpu_steps)
         out["cpu_baseline"] = {"value": round(v, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",

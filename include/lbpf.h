@@ -273,17 +273,17 @@ lbpf_status lbpf_unet_train_step(lbpf_unet* u, const float* in, const float* tar
                                  int32_t h, int32_t w, float lr, double* loss_host);
 lbpf_status lbpf_unet_destroy(lbpf_unet* u);
 const char* lbpf_unet_last_error(const lbpf_unet* u);
-/* One 16x16x16 BF16 matrix product on MFMA (row-major A, B bf16; D FP32, device arrays):
- * the operand-layout check of the surrogate kernels. */
-lbpf_status lbpf_mfma_probe(const void* A, const void* B, float* D, void* hip_stream);
+/* One 16 x 16 x k BF16 matrix product on MFMA, k = 16 or 32 (row-major A 16 x k and B k x 16
+ * bf16, D 16 x 16 FP32, device arrays): the operand-layout check of the surrogate kernels. */
+lbpf_status lbpf_mfma_probe(int32_t k, const void* A, const void* B, float* D, void* hip_stream);
 
 /* Hand-over between the solver and the surrogate: the current fields of a simulation as
  * normalized NHWC [ny][nx][4] FP32, (field - shift[c]) / scale[c] for c = phi, u_x, u_y, p
- * (host arrays of 4); and a new state from such fields (equilibria as in lbpf_init, the step
- * count is kept). Asynchronous. */
+ * (host arrays of 4; dst 16-byte aligned); and a new state from such fields at time level
+ * `step` (equilibria as in lbpf_init; the histories start from the given fields). Async. */
 lbpf_status lbpf_fields_to_nhwc(lbpf_ctx* ctx, float* dst, const float* shift, const float* scale);
 lbpf_status lbpf_init_from_nhwc(lbpf_ctx* ctx, const float* src, const float* shift,
-                                const float* scale);
+                                const float* scale, int64_t step);
 
 #ifdef __cplusplus
 }

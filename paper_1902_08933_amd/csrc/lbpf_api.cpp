@@ -402,7 +402,8 @@ lbpf_status lbpf_fields_to_nhwc(lbpf_ctx* c, float* dst, const float* shift, con
     return LBPF_OK;
 }
 
-lbpf_status lbpf_init_from_nhwc(lbpf_ctx* c, const float* src, const float* shift, const float* scale) {
+lbpf_status lbpf_init_from_nhwc(lbpf_ctx* c, const float* src, const float* shift, const float* scale,
+                                int64_t step) {
     if (lbpf_status s = check_ctx(c, false)) return s;
     if (!src || !shift || !scale) return fail(c, LBPF_E_INVALID, "NULL argument");
     if (((uintptr_t)src) % 16) return fail(c, LBPF_E_INVALID, "src must be 16-byte aligned");
@@ -411,7 +412,7 @@ lbpf_status lbpf_init_from_nhwc(lbpf_ctx* c, const float* src, const float* shif
     for (int k = 0; k < 4; ++k) d[k] = plane(c, kPlaneFields + k);
     hipError_t e = launch_nhwc_to_dense(c->m, src, d[0], d[1], d[2], d[3], shift, scale, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "NHWC to fields");
-    const int64_t step = c->step;
+    if (step < 0) return fail(c, LBPF_E_INVALID, "step must be >= 0");
     if (lbpf_status s = init_copy(c, c->cur, d[0], d[1], d[2], d[3])) return s;
     c->step = step;
     return LBPF_OK;

@@ -28,7 +28,7 @@
 
 namespace lbpf {
 typedef uint16_t bf16;
-hipError_t unet_mfma_probe(const bf16* A, const bf16* B, float* D, hipStream_t st);
+hipError_t unet_mfma_probe(int k32, const bf16* A, const bf16* B, float* D, hipStream_t st);
 hipError_t unet_conv_fwd(int ks, bool relu, const bf16* x, int xs, int xo, int Cin, const bf16* w,
                          const float* bias, bf16* y, int ys, int yo, int Cout, float* yf, int N,
                          int H, int W, hipStream_t st);
@@ -482,9 +482,9 @@ lbpf_status lbpf_unet_destroy(lbpf_unet* u) {
 
 const char* lbpf_unet_last_error(const lbpf_unet* u) { return u ? u->err.c_str() : g_unet_err.c_str(); }
 
-lbpf_status lbpf_mfma_probe(const void* A, const void* B, float* D, void* hip_stream) {
-    if (!A || !B || !D) return LBPF_E_INVALID;
-    hipError_t e = unet_mfma_probe((const bf16*)A, (const bf16*)B, D, (hipStream_t)hip_stream);
+lbpf_status lbpf_mfma_probe(int32_t k, const void* A, const void* B, float* D, void* hip_stream) {
+    if (!A || !B || !D || (k != 16 && k != 32)) return LBPF_E_INVALID;
+    hipError_t e = unet_mfma_probe(k == 32, (const bf16*)A, (const bf16*)B, D, (hipStream_t)hip_stream);
     return e == hipSuccess ? LBPF_OK : LBPF_E_HIP;
 }
 

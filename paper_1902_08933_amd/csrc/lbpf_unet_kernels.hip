@@ -30,6 +30,14 @@ __device__ __forceinline__ float4_t mfma16(short4_t a, short4_t b, float4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+typedef short short8_t __attribute__((ext_vector_type(8)));
+
+// gfx950 double-K form: A 16 x 32, B 32 x 16; lane i + 16 * (k / 8) holds A[i][k] in element
+// k % 8 (B likewise with the column), D as for the 16 x 16 x 16 form
+__device__ __forceinline__ float4_t mfma32(short8_t a, short8_t b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
 __device__ __forceinline__ short4_t load4(const bf16* p) {
     return *reinterpret_cast<const short4_t*>(p);
 }
@@ -45,6 +53,20 @@ __global__ void mfma_probe_kernel(const bf16* __restrict__ A, const bf16* __rest
     }
     float4_t d = {0.f, 0.f, 0.f, 0.f};
     d = mfma16(a, b, d);
+    for (int e = 0; e < 4; ++e) D[(4 * (l / 16) + e) * 16 + l % 16] = d[e];
+}
+
+// One 16x16x32 product (row-major A 16x32, B 32x16 bf16) into D (16x16 FP32).
+__global__ void mfma32_probe_kernel(const bf16* __restrict__ A, const bf16* __restrict__ B,
+                                    float* __restrict__ D) {
+    const int l = threadIdx.x;
+    short8_t a, b;
+    for (int e = 0; e < 8; ++e) {
+        a[e] = (short)A[(l % 16) * 32 + 8 * (l / 16) + e];
+        b[e] = (short)B[(8 * (l / 16) + e) * 16 + l % 16];
+    }
+    float4_t d = {0.f, 0.f, 0.f, 0.f};
+    d = mfma32(a, b, d);
     for (int e = 0; e < 4; ++e) D[(4 * (l / 16) + e) * 16 + l % 16] = d[e];
 }
 
@@ -104,6 +126,128 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const bf16* __restrict__ 
         for (int e = 0; e < 4; ++e) {
             const long long p = p0 + 4 * (lane >> 4) + e;
             if (p >= npix) continue;
+            float v = acc[j][e] + bb;
+            if (RELU) v = fmaxf(v, 0.0f);
+            y[p * ys + yo + co] = f2bf(v);
+            if (yf) yf[p * Cout + co] = v;
+        }
+    }
+}
+
+// LDS-tiled convolution (same contract as conv_fwd_kernel): a workgroup of 4 waves computes a
+// tile of 4 rows x 16 columns of one image (wave w: row w) for COT output channels. Per chunk
+// of 32 input channels it stages the input patch (with its KS-1 halo, circular) and the
+// weights of the COT channels in LDS, then every tap is one 16x16x32 MFMA per 16 output
+// channels with the A fragment shared across them. The next chunk is loaded into registers
+// while the current one is multiplied. Pixels beyond the image (a ragged tile) are computed
+// from wrapped data and not stored.
+template <int KS, bool RELU, int COT>
+__global__ __launch_bounds__(256) void conv_lds_kernel(const bf16* __restrict__ x, int xs, int xo,
+                                                       int Cin, const bf16* __restrict__ w,
+                                                       const float* __restrict__ bias,
+                                                       bf16* __restrict__ y, int ys, int yo,
+                                                       int Cout, float* __restrict__ yf, int N,
+                                                       int H, int W) {
+    constexpr int TR = 4, TC = 16, CK = 32, CKP = 40;  // CKP: padded LDS row (bank spread)
+    constexpr int HALO = KS - 1, PR = TR + HALO, PC = TC + HALO, T = KS * KS;
+    constexpr int NPATCH = PR * PC * (CK / 8);           // 16-byte pieces of the patch
+    constexpr int NWT = COT * T * (CK / 8);              // 16-byte pieces of the weights
+    constexpr int PP = (NPATCH + 255) / 256, PW = (NWT + 255) / 256;
+    __shared__ __attribute__((aligned(16))) bf16 s_x[PR * PC * CKP];
+    __shared__ __attribute__((aligned(16))) bf16 s_w[COT * T * CKP];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_x = (W + TC - 1) / TC, tiles_y = (H + TR - 1) / TR;
+    const int tile = blockIdx.x;
+    const int tx0 = (tile % tiles_x) * TC, ty0 = ((tile / tiles_x) % tiles_y) * TR;
+    const long long n = tile / (tiles_x * tiles_y);
+    const int co0 = blockIdx.y * COT;
+    const int K = T * Cin;
+    const int h0 = HALO / 2;
+
+    short8_t rp[PP], rw[PW];
+    auto fetch = [&](int kc) {
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int piece = tid + 256 * i;
+            short8_t v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (piece < NPATCH) {
+                const int q = piece % (CK / 8), pix = piece / (CK / 8);
+                const int pr = pix / PC, pc = pix % PC;
+                int sy = ty0 + pr - h0, sx = tx0 + pc - h0;
+                sy = ((sy % H) + H) % H;
+                sx = ((sx % W) + W) % W;
+                const int ci = kc + 8 * q;
+                if (ci < Cin) v = *reinterpret_cast<const short8_t*>(x + ((n * H + sy) * W + sx) * xs + xo + ci);
+            }
+            rp[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < PW; ++i) {
+            const int piece = tid + 256 * i;
+            short8_t v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (piece < NWT) {
+                const int q = piece % (CK / 8), r = piece / (CK / 8);
+                const int tap = r % T, col = r / T;
+                const int co = co0 + col, ci = kc + 8 * q;
+                if (co < Cout && ci < Cin) v = *reinterpret_cast<const short8_t*>(w + (long long)co * K + tap * Cin + ci);
+            }
+            rw[i] = v;
+        }
+    };
+    auto publish = [&]() {
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int piece = tid + 256 * i;
+            if (piece < NPATCH) {
+                const int q = piece % (CK / 8), pix = piece / (CK / 8);
+                *reinterpret_cast<short8_t*>(s_x + pix * CKP + 8 * q) = rp[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PW; ++i) {
+            const int piece = tid + 256 * i;
+            if (piece < NWT) {
+                const int q = piece % (CK / 8), r = piece / (CK / 8);
+                *reinterpret_cast<short8_t*>(s_w + r * CKP + 8 * q) = rw[i];
+            }
+        }
+    };
+
+    float4_t acc[COT / 16];
+#pragma unroll
+    for (int j = 0; j < COT / 16; ++j) acc[j] = {0.f, 0.f, 0.f, 0.f};
+    const int m = lane & 15, kq = 8 * (lane >> 4);
+    fetch(0);
+    for (int kc = 0; kc < Cin; kc += CK) {
+        __syncthreads();
+        publish();
+        __syncthreads();
+        if (kc + CK < Cin) fetch(kc + CK);
+#pragma unroll
+        for (int tap = 0; tap < T; ++tap) {
+            const int dy = KS == 3 ? tap / 3 - 1 : 0, dx = KS == 3 ? tap % 3 - 1 : 0;
+            const short8_t a = *reinterpret_cast<const short8_t*>(
+                s_x + ((wave + dy + h0) * PC + (m + dx + h0)) * CKP + kq);
+#pragma unroll
+            for (int j = 0; j < COT / 16; ++j) {
+                const short8_t b = *reinterpret_cast<const short8_t*>(s_w + ((16 * j + m) * T + tap) * CKP + kq);
+                acc[j] = mfma32(a, b, acc[j]);
+            }
+        }
+    }
+    // D: lane (j, i/4): column = output channel, rows = 4 consecutive pixels of this wave's row
+#pragma unroll
+    for (int j = 0; j < COT / 16; ++j) {
+        const int co = co0 + 16 * j + m;
+        if (co >= Cout) continue;
+        const float bb = bias ? bias[co] : 0.0f;
+        const int yy = ty0 + wave;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int xx = tx0 + 4 * (lane >> 4) + e;
+            if (yy >= H || xx >= W) continue;
+            const long long p = (n * H + yy) * W + xx;
             float v = acc[j][e] + bb;
             if (RELU) v = fmaxf(v, 0.0f);
             y[p * ys + yo + co] = f2bf(v);
@@ -362,14 +506,35 @@ static dim3 ew_grid(long long n) {
     return dim3((unsigned)b);
 }
 
-hipError_t unet_mfma_probe(const bf16* A, const bf16* B, float* D, hipStream_t st) {
-    hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, st, A, B, D);
+hipError_t unet_mfma_probe(int k32, const bf16* A, const bf16* B, float* D, hipStream_t st) {
+    if (k32)
+        hipLaunchKernelGGL(mfma32_probe_kernel, dim3(1), dim3(64), 0, st, A, B, D);
+    else
+        hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, st, A, B, D);
     return hipGetLastError();
 }
 
 hipError_t unet_conv_fwd(int ks, bool relu, const bf16* x, int xs, int xo, int Cin, const bf16* w,
                          const float* bias, bf16* y, int ys, int yo, int Cout, float* yf, int N,
                          int H, int W, hipStream_t st) {
+    // LDS-tiled MFMA kernel whenever the 16-byte pieces stay aligned, else the plain one
+    const bool tiled = (Cin % 8 == 0) && (xs % 8 == 0) && (xo % 8 == 0);
+    if (tiled) {
+        const long long tiles = (long long)N * ((H + 3) / 4) * ((W + 15) / 16);
+        const int cot = Cout <= 32 ? 32 : 64;
+        dim3 grid((unsigned)tiles, (unsigned)((Cout + cot - 1) / cot));
+#define LBPF_CONV(KS_, R_, C_) hipLaunchKernelGGL((conv_lds_kernel<KS_, R_, C_>), grid, dim3(256), 0, st, \
+                                                  x, xs, xo, Cin, w, bias, y, ys, yo, Cout, yf, N, H, W)
+        if (ks == 3) {
+            if (relu) { if (cot == 32) LBPF_CONV(3, true, 32); else LBPF_CONV(3, true, 64); }
+            else { if (cot == 32) LBPF_CONV(3, false, 32); else LBPF_CONV(3, false, 64); }
+        } else {
+            if (relu) { if (cot == 32) LBPF_CONV(1, true, 32); else LBPF_CONV(1, true, 64); }
+            else { if (cot == 32) LBPF_CONV(1, false, 32); else LBPF_CONV(1, false, 64); }
+        }
+#undef LBPF_CONV
+        return hipGetLastError();
+    }
     const long long npix = (long long)N * H * W;
     dim3 grid((unsigned)((npix + 63) / 64), (unsigned)((Cout + 63) / 64));
     if (ks == 3 && relu)

@@ -249,8 +249,9 @@ class Simulation:
         self._c(self.lib.lbpf_state_size(self._h, ctypes.byref(n)))
         return n.value
 
-    def save_state(self):
-        buf = self.torch.empty(self.state_size(), dtype=self.torch.uint8, device=self.device)
+    def save_state(self, out=None):
+        buf = out if out is not None else self.torch.empty(self.state_size(), dtype=self.torch.uint8,
+                                                           device=self.device)
         self._c(self.lib.lbpf_save_state(self._h, ctypes.c_void_p(buf.data_ptr())))
         return buf
 
@@ -429,9 +430,9 @@ SIGNATURES.update({
                                   ctypes.c_float, _PD]),
     "lbpf_unet_destroy": (_S, [_V]),
     "lbpf_unet_last_error": (ctypes.c_char_p, [_V]),
-    "lbpf_mfma_probe": (_S, [_V, _V, _V, _V]),
+    "lbpf_mfma_probe": (_S, [ctypes.c_int32, _V, _V, _V, _V]),
     "lbpf_fields_to_nhwc": (_S, [_V, _V, _PF, _PF]),
-    "lbpf_init_from_nhwc": (_S, [_V, _V, _PF, _PF]),
+    "lbpf_init_from_nhwc": (_S, [_V, _V, _PF, _PF, ctypes.c_int64]),
 })
 
 
@@ -447,17 +448,19 @@ def fields_to_nhwc(sim, shift, scale, out=None):
     return t
 
 
-def init_from_nhwc(sim, src, shift, scale):
-    """Replace the state of a simulation by equilibria of normalized NHWC fields."""
-    sim._c(sim.lib.lbpf_init_from_nhwc(sim._h, ctypes.c_void_p(src.data_ptr()), _f4(shift), _f4(scale)))
+def init_from_nhwc(sim, src, shift, scale, step=None):
+    """Replace the state of a simulation by equilibria of normalized NHWC fields at time level
+    `step` (default: the current step count)."""
+    st = sim.step_count if step is None else int(step)
+    sim._c(sim.lib.lbpf_init_from_nhwc(sim._h, ctypes.c_void_p(src.data_ptr()), _f4(shift), _f4(scale), st))
     return sim
 
 
-def mfma_probe(A_bf16_bits, B_bf16_bits, D):
-    """One 16x16x16 MFMA product; A, B int16 tensors holding BF16 bits, D float32 16x16."""
+def mfma_probe(A_bf16_bits, B_bf16_bits, D, k=16):
+    """One 16x16xk MFMA product (k = 16 or 32); A, B int16 tensors holding BF16 bits."""
     import torch
     lib = library()
-    st = lib.lbpf_mfma_probe(ctypes.c_void_p(A_bf16_bits.data_ptr()), ctypes.c_void_p(B_bf16_bits.data_ptr()),
+    st = lib.lbpf_mfma_probe(int(k), ctypes.c_void_p(A_bf16_bits.data_ptr()), ctypes.c_void_p(B_bf16_bits.data_ptr()),
                              ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     if st != 0:
         raise LbpfError(st, "mfma probe")
