@@ -25,9 +25,9 @@ def traffic_summary_path(workload):
     return os.path.join(ROOT, "profiles", f"fused_step_{workload}_pmc.txt")
 
 
-def measured_traffic(workload, cells):
+def measured_traffic(workload, cells, tile):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken on the
-    current kernel source; otherwise None."""
+    current kernel source with the same strip shape; otherwise None."""
     from paper_1902_08933_amd.rocprof_summary import kernel_source_hash
     path = traffic_summary_path(workload)
     if not os.path.exists(path):
@@ -36,7 +36,10 @@ def measured_traffic(workload, cells):
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     c = re.search(r"cells:\s*([0-9]+)", text)
-    if not (m and t and c) or m.group(1) != kernel_source_hash() or int(c.group(1)) != cells:
+    k = re.search(r"--tile (\d+)", text)
+    if not (m and t and c and k) or m.group(1) != kernel_source_hash() or int(c.group(1)) != cells:
+        return None
+    if int(k.group(1)) != tile:
         return None
     return float(t.group(1))
 
@@ -51,12 +54,16 @@ def workload(name, variant):
 
 
 def time_gpu(cfg, phi, steps, warmup, tile=None):
+    """Time `steps` steps after `warmup`; the strip shape is `tile`, else the one the library's
+    autotuner picks on this grid (it restores the state it ran on)."""
     import torch
     from paper_1902_08933_amd import lbpf
     sim = lbpf.Simulation(cfg)
+    sim.init(torch.from_numpy(phi.astype("float32")).cuda())
     if tile is not None:
         sim.set_tile(tile)
-    sim.init(torch.from_numpy(phi.astype("float32")).cuda())
+    else:
+        sim.autotune(trial_steps=20)
     sim.step(warmup)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
@@ -70,7 +77,7 @@ def time_gpu(cfg, phi, steps, warmup, tile=None):
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     diag = sim.diagnostics()
-    return ms, wall, diag, lbpf.tile_shapes()[sim.tile]
+    return ms, wall, diag, lbpf.tile_shapes()[sim.tile], sim.tile
 
 
 def probe_copy_gbs(mib=2048, reps=10):
@@ -109,6 +116,7 @@ def batch_bench(steps, count=256, seed=0):
         b.init(k, torch.from_numpy(np.ascontiguousarray(phi, dtype=np.float32)).cuda())
     del insts
     b.step(16)
+    b.autotune(trial_steps=5)
     flags, _ = b.status()
     active = sum(c["nx"] * c["ny"] for c, f in zip(b.cfgs, flags) if not f)
     out = {"instances": count, "frozen": int(sum(flags)), "active_nodes": active,
@@ -241,11 +249,11 @@ def main():
     cells = cfg["nx"] * cfg["ny"]
     print(f"# workload {args.workload} {cfg['nx']}x{cfg['ny']} {args.variant}: "
           f"{args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
-    ms, wall, diag, shape = time_gpu(cfg, phi, args.steps, args.warmup, args.tile)
+    ms, wall, diag, shape, tile = time_gpu(cfg, phi, args.steps, args.warmup, args.tile)
     ms_per_step = ms / args.steps
     mlups = cells * args.steps / (ms * 1e-3) / 1e6
     achieved = BYTES_PER_CELL * cells / (ms_per_step * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, cells)
+    traffic = measured_traffic(args.workload, cells, tile)
     out = {
         "metric": "D2Q9 two-phase MLUPS, % of HBM roofline; surrogate speedup at fixed error",
         "value": round(mlups, 1),
@@ -263,7 +271,8 @@ def main():
                                f"{args.variant.upper()}, rho ratio 3, nu ratio 0.1, sigma 0.03, "
                                "W 4, M_phi 0.1, tau_h 1",
                    "nx": cfg["nx"], "ny": cfg["ny"], "variant": args.variant,
-                   "strip": {"tx": shape[0], "rows": shape[1], "threads": shape[2]},
+                   "strip": {"tx": shape[0], "rows": shape[1], "threads": shape[2], "index": tile,
+                             "chosen_by": "set" if args.tile is not None else "autotuner"},
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -277,15 +286,16 @@ def main():
         # footprint far above the 256 MB Infinity Cache: 4096^2 cells, ~2.8 GB of state
         lcfg, lphi = workload("spinodal4096", args.variant)
         lsteps = max(50, args.steps // 16)
-        lms, _, _, _ = time_gpu(lcfg, lphi, lsteps, 20, args.tile)
+        lms, _, _, lshape, ltile = time_gpu(lcfg, lphi, lsteps, 20, args.tile)
         lcells = lcfg["nx"] * lcfg["ny"]
         lper = lms / lsteps
         out["large_footprint"] = {
             "workload": "spinodal 4096x4096", "steps": lsteps, "ms_per_step": lper,
+            "strip": {"tx": lshape[0], "rows": lshape[1], "threads": lshape[2], "index": ltile},
             "MLUPS": round(lcells / (lper * 1e-3) / 1e6, 1),
             "achieved_GBs": round(BYTES_PER_CELL * lcells / (lper * 1e-3) / 1e9, 1),
             "frac": round(BYTES_PER_CELL * lcells / (lper * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("spinodal4096", lcells)}
+            "traffic": measured_traffic("spinodal4096", lcells, ltile)}
     out["roofline"]["copy_probe_GBs"] = round(probe_copy_gbs(), 1)
     if not args.no_batch:
         out["batched"] = batch_bench(args.batch_steps)

@@ -73,7 +73,8 @@ typedef enum {
 
 /* Physical parameters of one simulation (lattice units). */
 typedef struct lbpf_params {
-    int32_t nx, ny;          /* grid size, each >= 3 */
+    int32_t nx, ny;          /* grid size: 3 <= nx, ny < 2^24 and ny * pitch(nx) + pad < 2^30,
+                              * pitch(nx) = nx rounded up to a multiple of 64 */
     int32_t variant;         /* lbpf_variant */
     int32_t pscheme;         /* lbpf_pscheme */
     int32_t fsurf;           /* lbpf_fsurf */
@@ -146,7 +147,8 @@ lbpf_status lbpf_set_stream(lbpf_ctx* ctx, void* hip_stream);
 
 /* Work shape of the fused step: index into the list of strip shapes. A workgroup of `threads`
  * threads owns a strip `tx` nodes wide and `rows` rows tall and marches up it. Results are
- * bit-identical for every shape. */
+ * bit-identical for every shape. A new simulation starts with shape 12 (64 x 32, 512 threads),
+ * a new batch with shape 1 (64 x 16, 256 threads); the autotuners below pick per workload. */
 lbpf_status lbpf_set_tile(lbpf_ctx* ctx, int32_t tile_index);
 /* Autotuner: times every strip shape over trial_steps steps (after one warm-up launch each)
  * on this simulation's own grid and parameters, writes the mean milliseconds per step of shape i

@@ -57,7 +57,12 @@ struct lbpf_ctx {
 };
 
 static thread_local std::string g_create_err;
-static const int kDefaultTile = 1;  // strip 64 wide, 16 rows, 256 threads
+// Default strip shapes (indices into the table of lbpf_tile_shape): for one simulation the
+// shape that measured fastest on a 1024^2 grid (64 wide, 32 rows, 512 threads, loads of the
+// next step of the march issued before the update); for a batch of small grids 64 wide,
+// 16 rows, 256 threads. lbpf_autotune / lbpf_batch_autotune choose per workload.
+static const int kDefaultTile = 12;
+static const int kDefaultBatchTile = 1;
 
 static lbpf_status fail(lbpf_ctx* c, lbpf_status s, const char* fmt, ...) {
     char buf[512];
@@ -74,10 +79,15 @@ static lbpf_status hip_fail(lbpf_ctx* c, hipError_t e, const char* what) {
     return fail(c, LBPF_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+static size_t plane_pad();
+
 static const char* validate(const lbpf_params* p) {
     if (!p) return "params is NULL";
     if (p->nx < 3 || p->ny < 3) return "nx and ny must be >= 3";
-    if ((long long)p->nx * p->ny > (1LL << 31)) return "grid too large (nx*ny > 2^31)";
+    if (p->nx >= (1 << 24) || p->ny >= (1 << 24)) return "nx and ny must be below 2^24";
+    // kernels address a node inside a plane with a 32-bit byte offset
+    if ((long long)p->ny * pitch_of(p->nx) + plane_pad() >= (1LL << 30))
+        return "grid too large (a plane of ny * pitch nodes must hold fewer than 2^30 floats)";
     if (p->variant != LBPF_QIM && p->variant != LBPF_IM) return "variant must be LBPF_QIM or LBPF_IM";
     if (p->pscheme < 0 || p->pscheme > 2) return "pscheme out of range";
     if (p->fsurf != 0 && p->fsurf != 1) return "fsurf out of range";
@@ -632,7 +642,7 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_params* params, void* worksp
     b->d_insts = (BatchInst*)b->ws;
     b->max_items = batch_max_items(n, params);
     b->d_items = (BatchItem*)(b->ws + align256(sizeof(BatchInst) * n));
-    b->tile = kDefaultTile;
+    b->tile = kDefaultBatchTile;
     b->parity = 0;
     b->step = 0;
     b->graph[0] = b->graph[1] = nullptr;

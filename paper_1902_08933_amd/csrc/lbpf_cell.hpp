@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbpf_model.hpp"
 
 namespace lbpf {
@@ -24,6 +26,19 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
     e = (a - (s - bb)) + (b - bb);
 }
 
+// Element `off` of plane `q` of a plane array. The plane base is the same for every lane
+// (scalar registers) and the per-lane part is a 32-bit byte offset (a plane holds fewer than
+// 2^30 floats), so loads and stores use the scalar-base addressing form with no 64-bit
+// address arithmetic per lane.
+template <typename T>
+__device__ __forceinline__ T* pl(T* base, long long plane, int q, unsigned off) {
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T*>(reinterpret_cast<B*>(base + q * plane) + (off << 2));
+}
+
+// 1/x with the hardware reciprocal (relative error within 1 ulp)
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 __device__ __forceinline__ int wrap(int v, int n) {
     if ((unsigned)v < (unsigned)n) return v;
     if (v < 0 && v >= -n) return v + n;
@@ -32,10 +47,18 @@ __device__ __forceinline__ int wrap(int v, int n) {
     return r < 0 ? r + n : r;
 }
 
+// Offset of node (x, y) in a plane, y * pitch + x, with the full-rate 24-bit multiply (grid
+// sides are below 2^24 and a plane holds fewer than 2^30 nodes).
+__device__ __forceinline__ unsigned node_off(int y, int pitch, int x) {
+    return (unsigned)__umul24(y, pitch) + (unsigned)x;
+}
+
 // Row read for a stencil ghost: periodic wrap, or the mirror image about a wall half a cell
 // outside the first/last fluid row (clamped for rows that no active node reads).
-__device__ __forceinline__ int src_row(int y, int ny, int bc) {
-    if (bc == 0) return wrap(y, ny);
+// BC: 0 periodic in y, 1 walls at y = -1/2 and y = ny - 1/2.
+template <int BC>
+__device__ __forceinline__ int src_row(int y, int ny) {
+    if (BC == 0) return wrap(y, ny);
     if (y < 0) y = -1 - y;
     else if (y >= ny) y = 2 * ny - 1 - y;
     return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
@@ -111,8 +134,8 @@ __device__ __forceinline__ Stencil gather(const float* phh, const float* phl, in
 // or both BGK collisions (eq. 24, eq. 10 with eqs. 33, 34, 11, 14) with push-streaming into
 // fout / hout, the new pressure into pout and (phi u) into phiu. f holds f_1..f_8, h the ten h
 // planes, pu the previous (phi u). `cell` is the node's offset in a plane.
-template <bool COLLIDE>
-__device__ __forceinline__ void cell_update(const Model& m, int x, int y, long long cell,
+template <bool COLLIDE, int BC>
+__device__ __forceinline__ void cell_update(const Model& m, int x, int y, unsigned cell,
                                             const float (&f8)[kFPlanes], const float (&h10)[kHPlanes],
                                             const float (&pu)[2], const Stencil& st,
                                             float* __restrict__ fout, float* __restrict__ hout,
@@ -142,7 +165,8 @@ __device__ __forceinline__ void cell_update(const Model& m, int x, int y, long l
     // eq. (27a): u = (sum_i c_i g_i + F/2) / rho
     const float mx = ((f[1] - f[3]) + (f[5] - f[7])) + (f[8] - f[6]);
     const float my = ((f[2] - f[4]) + (f[5] - f[7])) + (f[6] - f[8]);
-    const float ux = (mx + 0.5f * Fx) / rho, uy = (my + 0.5f * Fy) / rho;
+    const float irho = rcp(rho);
+    const float ux = (mx + 0.5f * Fx) * irho, uy = (my + 0.5f * Fy) * irho;
     // mass source: S1 = -gamma M lap(mu) (quasi-incompressible) or 0; S = u.grad(rho) + rho S1
     const float S1 = (m.variant == 0) ? -m.gammaM * st.lapmu : 0.0f;
     const float grx = m.drho * gphix, gry = m.drho * gphiy;
@@ -153,8 +177,8 @@ __device__ __forceinline__ void cell_update(const Model& m, int x, int y, long l
     const float uFt = ux * Ftx + uy * Fty;
     // tau_g from nu(phi): nu = c_s^2 (tau_g - 1/2)
     float nu;
-    if (m.visc == 0) nu = 1.0f / (phic * (m.inv_nuA - m.inv_nuB) + m.inv_nuB);
-    else nu = ((phi >= 0.5f) ? m.muA : m.muB) / rho;
+    if (m.visc == 0) nu = rcp(phic * (m.inv_nuA - m.inv_nuB) + m.inv_nuB);
+    else nu = ((phi >= 0.5f) ? m.muA : m.muB) * irho;
     const float tau_g = 3.0f * nu + 0.5f;
     // eq. (28): p = 3/5 [ sum_{i!=0} g_i + S/2 + rho s_0(u) + (tau_g - 1/2) G_0 ]
     const float u2 = ux * ux + uy * uy;
@@ -171,45 +195,57 @@ __device__ __forceinline__ void cell_update(const Model& m, int x, int y, long l
     const float phiux = phi * ux, phiuy = phi * uy;
 
     if constexpr (!COLLIDE) {
-        float* o = fields + cell;
-        o[0] = phi;
-        o[P] = rho;
-        o[2 * P] = ux;
-        o[3 * P] = uy;
-        o[4 * P] = p;
-        o[5 * P] = mu;
+        *pl(fields, P, 0, cell) = phi;
+        *pl(fields, P, 1, cell) = rho;
+        *pl(fields, P, 2, cell) = ux;
+        *pl(fields, P, 3, cell) = uy;
+        *pl(fields, P, 4, cell) = p;
+        *pl(fields, P, 5, cell) = mu;
     } else {
         const int nx = m.nx, ny = m.ny, pitch = m.pitch;
-        const float omega = 1.0f / tau_g;
+        const float omega = rcp(tau_g), om1 = 1.0f - omega;
         const float fgain = 1.0f - 0.5f * omega;
         const float emu = m.eta * mu;
         const float dpx = phiux - pu[0], dpy = phiuy - pu[1];
         const float rcoef = 3.0f * m.src_coef;
-        const float ith = m.inv_tau_h;
+        const float ith = m.inv_tau_h, ith1 = 1.0f - ith;
+        // Both collisions, eq. (24) and eq. (10), written as g* = (1 - omega) g + omega g^eq
+        // + (1 - omega/2) G and h* = (1 - 1/tau_h) h + h^eq/tau_h + R, and taken by pairs of
+        // opposite directions (c_j = -c_i): the parts of G_i (eq. 34 expanded for d = 2),
+        // g_i^eq (eq. 33, i != 0) and h_i^eq (eq. 11, i != 0) that are even in c_i are shared by
+        // the pair, the odd parts (and R_i of eq. 14) change sign.
+        //   G_i even: w_i [S - 3 u.F~ + rho S1 (1.5 |c_i|^2 - 1) + 9 (c_i.u)(c_i.F~)], odd: 3 w_i c_i.F
+        //   g_i^eq even: w_i [3 p - 1.5 rho u^2 + 4.5 rho (c_i.u)^2],              odd: 3 w_i rho c_i.u
+        //   h_i^eq even: w_i eta mu,                                   odd: 3 w_i c_i.(phi u)
+        //   R_i: 3 (1 - 1/(2 tau_h)) w_i c_i.((phi u) - (phi u)_prev)
+        const float T0 = S - 3.0f * uFt;
+        const float Kax = T0 + 0.5f * rS1, Kdg = T0 + 2.0f * rS1;
+        const float Eb = 3.0f * p - 1.5f * rho * u2;
+        const float r45 = 4.5f * rho, wr = omega * rho;
+        const float hem = ith * emu, ith3 = 3.0f * ith;
+        float fs[9], hst[9];
+        auto pair = [&](int qa, int qb, float w, float K, float cu, float cF, float cFt, float cpu,
+                        float cd) {
+            const float ev = w * (omega * fmaf(r45, cu * cu, Eb) + fgain * fmaf(9.0f * cu, cFt, K));
+            const float od = (3.0f * w) * fmaf(wr, cu, fgain * cF);
+            fs[qa] = fmaf(f[qa], om1, ev) + od;
+            fs[qb] = fmaf(f[qb], om1, ev) - od;
+            const float hev = w * hem;
+            const float hod = w * fmaf(ith3, cpu, rcoef * cd);
+            hst[qa] = fmaf(h[qa], ith1, hev) + hod;
+            hst[qb] = fmaf(h[qb], ith1, hev) - hod;
+        };
+        pair(1, 3, kWA, Kax, ux, Fx, Ftx, phiux, dpx);
+        pair(2, 4, kWA, Kax, uy, Fy, Fty, phiuy, dpy);
+        pair(5, 7, kWD, Kdg, ux + uy, Fx + Fy, Ftx + Fty, phiux + phiuy, dpx + dpy);
+        pair(6, 8, kWD, Kdg, uy - ux, Fy - Fx, Fty - Ftx, phiuy - phiux, dpy - dpx);
         const int xp = (x + 1 == nx) ? 0 : x + 1, xm = (x == 0) ? nx - 1 : x - 1;
-        const bool walls = (m.bc == 1);
+        constexpr bool walls = (BC == 1);
         const int yp = (y + 1 == ny) ? 0 : y + 1, ym = (y == 0) ? ny - 1 : y - 1;
         const bool wall_top = walls && (y == ny - 1), wall_bot = walls && (y == 0);
 #pragma unroll
         for (int q = 1; q <= 8; ++q) {
-            const float w = wgt(q);
             const int cx = kCX[q], cy = kCY[q];
-            const float cu = cx * ux + cy * uy;
-            const float cF = cx * Fx + cy * Fy;
-            const float cFt = cx * Ftx + cy * Fty;
-            const float c2 = (float)(cx * cx + cy * cy);
-            // eq. (34) expanded for d = 2:
-            // G_i = w_i [S + c.F/c_s^2 + ((c.u)(c.F~) - c_s^2 u.F~)/c_s^4 + rho S1 (|c|^2 - 2 c_s^2)/(2 c_s^2)]
-            const float G = w * (S + 3.0f * cF + 9.0f * cu * cFt - 3.0f * uFt + rS1 * (1.5f * c2 - 1.0f));
-            // eq. (33), i != 0: g_i^eq = w_i p / c_s^2 + rho s_i(u)
-            const float geq = w * (3.0f * p + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * u2));
-            // eq. (24)
-            const float fst = f[q] - (f[q] - geq) * omega + fgain * G;
-            // eq. (11), i != 0, and eq. (14)
-            const float heq = w * (emu + 3.0f * (cx * phiux + cy * phiuy));
-            const float R = rcoef * w * (cx * dpx + cy * dpy);
-            // eq. (10)
-            const float hst = h[q] - (h[q] - heq) * ith + R;
             // streaming to x + c_i, or back into this node across a wall
             int dx = cx > 0 ? xp : (cx < 0 ? xm : x);
             int dy = cy > 0 ? yp : (cy < 0 ? ym : y);
@@ -219,9 +255,9 @@ __device__ __forceinline__ void cell_update(const Model& m, int x, int y, long l
                 dy = y;
                 dq = kOpp[q];
             }
-            const long long dst = (long long)dy * pitch + dx;
-            fout[(dq - 1) * P + dst] = fst;
-            hout[dq * P + dst] = hst;
+            const unsigned dst = node_off(dy, pitch, dx);
+            *pl(fout, P, dq - 1, dst) = fs[q];
+            *pl(hout, P, dq, dst) = hst[q];
         }
         // rest population of h: h_0* = h_0 - (h_0 - h_0^eq)/tau_h with h_0 - h_0^eq
         // = -sum_{i!=0} h_i - (w_0 - 1) eta mu; added to the hi/lo pair without rounding h_0
@@ -231,11 +267,11 @@ __device__ __forceinline__ void cell_update(const Model& m, int x, int y, long l
         const float nl = h10[kH0Lo] + e;
         float hi2, lo2;
         two_sum(nh, nl, hi2, lo2);
-        hout[cell] = hi2;
-        hout[kH0Lo * P + cell] = lo2;
-        pout[cell] = p;
-        phiu[cell] = phiux;
-        phiu[P + cell] = phiuy;
+        *pl(hout, P, 0, cell) = hi2;
+        *pl(hout, P, kH0Lo, cell) = lo2;
+        *pl(pout, P, 0, cell) = p;
+        *pl(phiu, P, 0, cell) = phiux;
+        *pl(phiu, P, 1, cell) = phiuy;
     }
 }
 

@@ -37,12 +37,13 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
 }
 
 // phi pair of the node at global (x, y) (sources wrapped or mirrored) into LDS
+template <int BC>
 __device__ __forceinline__ void load_phi(const Model& m, const float* __restrict__ hin, int x,
                                          int y, float* phh, float* phl, int slot) {
-    const long long c = (long long)src_row(y, m.ny, m.bc) * m.pitch + wrap(x, m.nx);
+    const unsigned c = node_off(src_row<BC>(y, m.ny), m.pitch, wrap(x, m.nx));
     float h[kHPlanes];
 #pragma unroll
-    for (int q = 0; q < kHPlanes; ++q) h[q] = hin[q * m.plane + c];
+    for (int q = 0; q < kHPlanes; ++q) h[q] = *pl(hin, m.plane, q, c);
     phi_pair(h, phh[slot], phl[slot]);
 }
 
@@ -51,11 +52,11 @@ __device__ __forceinline__ void load_phi(const Model& m, const float* __restrict
 // arithmetic. Rows whose stencil is not in the ring [lo, hi) are never read: 0.
 constexpr int ring_rows(int n) { return n <= 8 ? 8 : (n <= 16 ? 16 : (n <= 32 ? 32 : 64)); }
 
-template <int RP, int PX>
+template <int RP, int PX, int BC>
 __device__ __forceinline__ float ring_mu(const Model& m, const float* phh, const float* phl,
                                          int row, int px, int lo, int hi) {
     int cy = row;
-    if (m.bc == 1) {
+    if (BC == 1) {
         if (row < 0) cy = -1 - row;
         else if (row >= m.ny) cy = 2 * m.ny - 1 - row;
     }
@@ -76,7 +77,7 @@ struct MarchLoads {
     float pg;            // ghost pressure column node (4 TY <= tid < 6 TY)
 };
 
-template <int TX, int TY>
+template <int TX, int TY, int BC>
 __device__ __forceinline__ void march_load(const Model& m, const float* __restrict__ fin,
                                            const float* __restrict__ hin,
                                            const float* __restrict__ pin,
@@ -94,28 +95,28 @@ __device__ __forceinline__ void march_load(const Model& m, const float* __restri
     L.pu[0] = L.pu[1] = 0.0f;
     L.pg = 0.0f;
     {
-        const long long c = (long long)src_row(rowL, ny, m.bc) * pitch + wrap(x0 + tx, nx);
+        const unsigned c = node_off(src_row<BC>(rowL, ny), pitch, wrap(x0 + tx, nx));
 #pragma unroll
-        for (int q = 0; q < kHPlanes; ++q) L.hn[q] = hin[q * P + c];
+        for (int q = 0; q < kHPlanes; ++q) L.hn[q] = *pl(hin, P, q, c);
     }
     const int rowO = (r < TY - 2) ? rowL : Y + r - (TY - 2);
     if (x0 + tx < nx && rowO < ye) {
-        const long long cell = (long long)rowO * pitch + x0 + tx;
+        const unsigned cell = node_off(rowO, pitch, x0 + tx);
 #pragma unroll
-        for (int q = 0; q < kFPlanes; ++q) L.f[q] = fin[q * P + cell];
-        L.pu[0] = phiu[cell];
-        L.pu[1] = phiu[P + cell];
+        for (int q = 0; q < kFPlanes; ++q) L.f[q] = *pl(fin, P, q, cell);
+        L.pu[0] = *pl(phiu, P, 0, cell);
+        L.pu[1] = *pl(phiu, P, 1, cell);
     }
-    L.p = pin[(long long)src_row(Y + 1 + r, ny, m.bc) * pitch + wrap(x0 + tx, nx)];
+    L.p = *pl(pin, P, 0, node_off(src_row<BC>(Y + 1 + r, ny), pitch, wrap(x0 + tx, nx)));
     if (tid < 4 * TY) {
         const int cidx = tid / TY, row = Y + 2 + tid % TY;
         const int lx = cidx < 2 ? cidx : TX + cidx;
-        const long long c = (long long)src_row(row, ny, m.bc) * pitch + wrap(x0 + lx - 2, nx);
+        const unsigned c = node_off(src_row<BC>(row, ny), pitch, wrap(x0 + lx - 2, nx));
 #pragma unroll
-        for (int q = 0; q < kHPlanes; ++q) L.hg[q] = hin[q * P + c];
+        for (int q = 0; q < kHPlanes; ++q) L.hg[q] = *pl(hin, P, q, c);
     } else if (tid < 6 * TY) {
         const int j = tid - 4 * TY, lx = (j / TY) ? TX + 1 : 0, rw = Y + 1 + j % TY;
-        L.pg = pin[(long long)src_row(rw, ny, m.bc) * pitch + wrap(x0 + lx - 1, nx)];
+        L.pg = *pl(pin, P, 0, node_off(src_row<BC>(rw, ny), pitch, wrap(x0 + lx - 1, nx)));
     }
 }
 
@@ -137,7 +138,7 @@ struct MarchLds {
 
 // One workgroup marches the chunk of a strip starting at column x0, rows ys .. ys+CH-1
 // (clipped to the grid), of one simulation.
-template <int TX, int NT, int CH, bool PF, bool COLLIDE>
+template <int TX, int NT, int CH, bool PF, bool COLLIDE, int BC>
 __device__ __forceinline__ void march_chunk(const Model& m, const float* __restrict__ fin,
                                             float* __restrict__ fout,
                                             const float* __restrict__ hin,
@@ -162,28 +163,28 @@ __device__ __forceinline__ void march_chunk(const Model& m, const float* __restr
 
     // loads of the first step are issued before the prologue so that both are in flight together
     MarchLoads<TX, TY> L;
-    march_load<TX, TY>(m, fin, hin, pin, phiu, x0, ys, ye, tid, L);
+    march_load<TX, TY, BC>(m, fin, hin, pin, phiu, x0, ys, ye, tid, L);
 
     // ---- prologue: phi rows ys-2 .. ys+1, pressure and mu rows ys-1, ys --------------------
     for (int j = tid; j < 4 * PX; j += NT) {
         const int row = ys - 2 + j / PX, lx = j % PX;
-        load_phi(m, hin, x0 + lx - 2, row, s_phh, s_phl, prow(row) + lx);
+        load_phi<BC>(m, hin, x0 + lx - 2, row, s_phh, s_phl, prow(row) + lx);
     }
     for (int j = tid; j < 2 * MX; j += NT) {
         const int row = ys - 1 + j / MX, lx = j % MX;
-        s_p[mrow(row) + lx] = pin[(long long)src_row(row, ny, m.bc) * pitch + wrap(x0 + lx - 1, nx)];
+        s_p[mrow(row) + lx] = *pl(pin, P, 0, node_off(src_row<BC>(row, ny), pitch, wrap(x0 + lx - 1, nx)));
     }
     // threads r >= TY-2 own rows ys + r - (TY-2) in the first step: their h from the registers
     float hq[kHPlanes];
     if (r >= TY - 2) {
-        const long long c = (long long)src_row(ys + r - (TY - 2), ny, m.bc) * pitch + wrap(x0 + tx, nx);
+        const unsigned c = node_off(src_row<BC>(ys + r - (TY - 2), ny), pitch, wrap(x0 + tx, nx));
 #pragma unroll
-        for (int q = 0; q < kHPlanes; ++q) hq[q] = hin[q * P + c];
+        for (int q = 0; q < kHPlanes; ++q) hq[q] = *pl(hin, P, q, c);
     }
     __syncthreads();
     for (int j = tid; j < 2 * MX; j += NT) {
         const int row = ys - 1 + j / MX, lx = j % MX;
-        s_mu[mrow(row) + lx] = ring_mu<RP, PX>(m, s_phh, s_phl, row, lx + 1, ys - 2, ys + 2);
+        s_mu[mrow(row) + lx] = ring_mu<RP, PX, BC>(m, s_phh, s_phl, row, lx + 1, ys - 2, ys + 2);
     }
 
     // ---- march ------------------------------------------------------------------------------
@@ -205,7 +206,7 @@ __device__ __forceinline__ void march_chunk(const Model& m, const float* __restr
         const int rowO = own_new ? rowL : Y + r - (TY - 2);
         const int xo = x0 + tx;
         const bool active = xo < nx && rowO < ye;
-        const long long cell = (long long)rowO * pitch + xo;
+        const unsigned cell = node_off(rowO, pitch, xo);
         float hc[kHPlanes], f[kFPlanes], pu[2];
 #pragma unroll
         for (int q = 0; q < kHPlanes; ++q) hc[q] = own_new ? L.hn[q] : hq[q];
@@ -217,24 +218,24 @@ __device__ __forceinline__ void march_chunk(const Model& m, const float* __restr
         pu[1] = L.pu[1];
         __syncthreads();
         // (2) mu on rows Y+1 .. Y+TY, ghost columns included
-        s_mu[mrow(Y + 1 + r) + tx + 1] = ring_mu<RP, PX>(m, s_phh, s_phl, Y + 1 + r, tx + 2, Y - 2, Y + TY + 2);
+        s_mu[mrow(Y + 1 + r) + tx + 1] = ring_mu<RP, PX, BC>(m, s_phh, s_phl, Y + 1 + r, tx + 2, Y - 2, Y + TY + 2);
         if (tid < 2 * TY) {
             const int lx = (tid / TY) ? MX - 1 : 0, row = Y + 1 + tid % TY;
-            s_mu[mrow(row) + lx] = ring_mu<RP, PX>(m, s_phh, s_phl, row, lx + 1, Y - 2, Y + TY + 2);
+            s_mu[mrow(row) + lx] = ring_mu<RP, PX, BC>(m, s_phh, s_phl, row, lx + 1, Y - 2, Y + TY + 2);
         }
         __syncthreads();
         // (3) with PF, issue the loads of the next step first; then update the owned node
-        if (PF && Y + TY < ye) march_load<TX, TY>(m, fin, hin, pin, phiu, x0, Y + TY, ye, tid, L);
+        if (PF && Y + TY < ye) march_load<TX, TY, BC>(m, fin, hin, pin, phiu, x0, Y + TY, ye, tid, L);
         if (active) {
             const Stencil st = gather(s_phh, s_phl, prow(rowO - 1), prow(rowO), prow(rowO + 1), tx + 2,
                                       s_mu, s_p, mrow(rowO - 1), mrow(rowO), mrow(rowO + 1), tx + 1);
-            cell_update<COLLIDE>(m, xo, rowO, cell, f, hc, pu, st, fout, hout, pout, phiu, fields);
+            cell_update<COLLIDE, BC>(m, xo, rowO, cell, f, hc, pu, st, fout, hout, pout, phiu, fields);
         }
-        if (!PF && Y + TY < ye) march_load<TX, TY>(m, fin, hin, pin, phiu, x0, Y + TY, ye, tid, L);
+        if (!PF && Y + TY < ye) march_load<TX, TY, BC>(m, fin, hin, pin, phiu, x0, Y + TY, ye, tid, L);
     }
 }
 
-template <int TX, int NT, int CH, bool PF, bool COLLIDE>
+template <int TX, int NT, int CH, bool PF, bool COLLIDE, int BC>
 __global__ __launch_bounds__(NT) void strip_kernel(Model m, const float* __restrict__ fin,
                                                    float* __restrict__ fout,
                                                    const float* __restrict__ hin,
@@ -245,8 +246,8 @@ __global__ __launch_bounds__(NT) void strip_kernel(Model m, const float* __restr
                                                    float* __restrict__ fields, int nsx, int nsy) {
     __shared__ MarchLds<TX, NT> S;
     const int blk = xcd_tile(blockIdx.x, nsx * nsy);
-    march_chunk<TX, NT, CH, PF, COLLIDE>(m, fin, fout, hin, hout, pin, pout, phiu, fields,
-                                         (blk % nsx) * TX, (blk / nsx) * CH, S);
+    march_chunk<TX, NT, CH, PF, COLLIDE, BC>(m, fin, fout, hin, hout, pin, pout, phiu, fields,
+                                             (blk % nsx) * TX, (blk / nsx) * CH, S);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -260,7 +261,8 @@ __global__ void init_kernel(Model m, const float* __restrict__ phi0, const float
     if (x >= m.nx || y >= m.ny) return;
     const int nx = m.nx, ny = m.ny;
     auto at = [&](int dx, int dy) {
-        return phi0[(long long)src_row(y + dy, ny, m.bc) * nx + wrap(x + dx, nx)];
+        const int sy = m.bc ? src_row<1>(y + dy, ny) : src_row<0>(y + dy, ny);
+        return phi0[(long long)sy * nx + wrap(x + dx, nx)];
     };
     const float c = at(0, 0);
     const float axes = ((at(1, 0) - c) + (at(-1, 0) - c)) + ((at(0, 1) - c) + (at(0, -1) - c));
@@ -392,7 +394,8 @@ __global__ __launch_bounds__(256) void laplace_partial_kernel(Model m, const dou
     for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
         const int x = (int)(k % m.nx), y = (int)(k / m.nx);
         auto at = [&](int dx, int dy) {
-            return phi64[(long long)src_row(y + dy, m.ny, m.bc) * m.pitch + wrap(x + dx, m.nx)];
+            const int sy = m.bc ? src_row<1>(y + dy, m.ny) : src_row<0>(y + dy, m.ny);
+            return phi64[(long long)sy * m.pitch + wrap(x + dx, m.nx)];
         };
         const double c = at(0, 0);
         const double gx = (at(1, 0) - at(-1, 0)) / 3.0 + ((at(1, 1) - at(-1, 1)) + (at(1, -1) - at(-1, -1))) / 12.0;
@@ -430,7 +433,8 @@ struct StripShape { int tx, nt, ch, pf; };
 static const StripShape kStrips[] = {
     {64, 256, 4, 0},   {64, 256, 16, 0},  {64, 256, 64, 0},  {128, 256, 64, 0}, {128, 256, 16, 0},
     {64, 256, 16, 1},  {64, 256, 64, 1},  {128, 256, 64, 1}, {64, 512, 64, 1},  {32, 128, 32, 0},
-    {64, 128, 32, 0},  {256, 512, 64, 0}};
+    {64, 128, 32, 0},  {256, 512, 64, 0}, {64, 512, 32, 1},  {64, 512, 16, 1},  {128, 512, 32, 1},
+    {256, 512, 32, 1}, {256, 512, 16, 1}, {128, 256, 32, 1}};
 constexpr int kNumStrips = sizeof(kStrips) / sizeof(kStrips[0]);
 
 int tile_count() { return kNumStrips; }
@@ -443,8 +447,12 @@ static hipError_t launch_strip_t(const Model& m, const float* fin, float* fout, 
                                  float* hout, const float* pin, float* pout, float* phiu,
                                  float* fields, hipStream_t st) {
     const int nsx = (m.nx + TX - 1) / TX, nsy = (m.ny + CH - 1) / CH;
-    hipLaunchKernelGGL((strip_kernel<TX, NT, CH, PF, C>), dim3(nsx * nsy), dim3(NT), 0, st, m, fin,
-                       fout, hin, hout, pin, pout, phiu, fields, nsx, nsy);
+    if (m.bc == 1)
+        hipLaunchKernelGGL((strip_kernel<TX, NT, CH, PF, C, 1>), dim3(nsx * nsy), dim3(NT), 0, st,
+                           m, fin, fout, hin, hout, pin, pout, phiu, fields, nsx, nsy);
+    else
+        hipLaunchKernelGGL((strip_kernel<TX, NT, CH, PF, C, 0>), dim3(nsx * nsy), dim3(NT), 0, st,
+                           m, fin, fout, hin, hout, pin, pout, phiu, fields, nsx, nsy);
     return hipGetLastError();
 }
 
@@ -461,7 +469,13 @@ static hipError_t launch_strip_t(const Model& m, const float* fin, float* fout, 
     case 8: return launch_strip_t<64, 512, 64, true, C>(LBPF_ARGS);         \
     case 9: return launch_strip_t<32, 128, 32, false, C>(LBPF_ARGS);        \
     case 10: return launch_strip_t<64, 128, 32, false, C>(LBPF_ARGS);       \
-    case 11: return launch_strip_t<256, 512, 64, false, C>(LBPF_ARGS);
+    case 11: return launch_strip_t<256, 512, 64, false, C>(LBPF_ARGS);      \
+    case 12: return launch_strip_t<64, 512, 32, true, C>(LBPF_ARGS);        \
+    case 13: return launch_strip_t<64, 512, 16, true, C>(LBPF_ARGS);        \
+    case 14: return launch_strip_t<128, 512, 32, true, C>(LBPF_ARGS);       \
+    case 15: return launch_strip_t<256, 512, 32, true, C>(LBPF_ARGS);       \
+    case 16: return launch_strip_t<256, 512, 16, true, C>(LBPF_ARGS);       \
+    case 17: return launch_strip_t<128, 256, 32, true, C>(LBPF_ARGS);
 
 template <bool C>
 static hipError_t launch_fused(int tile, const Model& m, const float* fin, float* fout,
@@ -515,9 +529,12 @@ __global__ __launch_bounds__(NT) void batch_kernel(const BatchInst* __restrict__
         const int x0 = (w.chunk % I.nsx) * TX, ys = (w.chunk / I.nsx) * CH;
         if (I.frozen)
             copy_chunk<TX, NT>(m, fin, fout, hin, hout, pin, pout, x0, ys, CH);
+        else if (m.bc == 1)
+            march_chunk<TX, NT, CH, PF, true, 1>(m, fin, fout, hin, hout, pin, pout, phiu, nullptr,
+                                                 x0, ys, S);
         else
-            march_chunk<TX, NT, CH, PF, true>(m, fin, fout, hin, hout, pin, pout, phiu, nullptr,
-                                              x0, ys, S);
+            march_chunk<TX, NT, CH, PF, true, 0>(m, fin, fout, hin, hout, pin, pout, phiu, nullptr,
+                                                 x0, ys, S);
         __syncthreads();  // LDS is reused by the next item
     }
 }
@@ -541,6 +558,12 @@ hipError_t batch_kernel_info(int tile, void** fn, int* nt, int* tx, int* ch, int
         case 9: *fn = batch_fn<32, 128, 32, false>(); break;
         case 10: *fn = batch_fn<64, 128, 32, false>(); break;
         case 11: *fn = batch_fn<256, 512, 64, false>(); break;
+        case 12: *fn = batch_fn<64, 512, 32, true>(); break;
+        case 13: *fn = batch_fn<64, 512, 16, true>(); break;
+        case 14: *fn = batch_fn<128, 512, 32, true>(); break;
+        case 15: *fn = batch_fn<256, 512, 32, true>(); break;
+        case 16: *fn = batch_fn<256, 512, 16, true>(); break;
+        case 17: *fn = batch_fn<128, 256, 32, true>(); break;
         default: return hipErrorInvalidValue;
     }
     *tx = kStrips[tile].tx;

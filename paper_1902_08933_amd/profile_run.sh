@@ -13,7 +13,10 @@ OUT=gpurun_out/prof_$W
 PROF=${PROFILE_OUT:-profiles}
 mkdir -p "$OUT" "$PROF"
 export TMPDIR=/tmp
-STEP="python3 -m paper_1902_08933_amd.profile_step --workload $W"
+# the strip shape the autotuner picks (an unprofiled run), then every profiled run uses it
+TILE=$(timeout -k 10 120 python3 -m paper_1902_08933_amd.profile_step --workload $W --autotune | tail -1) || exit 1
+echo "profile: autotuned strip shape $TILE"
+STEP="python3 -m paper_1902_08933_amd.profile_step --workload $W --tile $TILE"
 PROBE="python3 -m paper_1902_08933_amd.profile_step --copy-mib 1024 --steps 2 --probe-blocks 4096"
 echo "profile: kernel trace $W" && \
 timeout -k 10 180 rocprofv3 --kernel-trace --stats -d "$OUT/trace" -o run -- $STEP --steps 100 --warmup 10 > "$OUT/trace.log" 2>&1 && \

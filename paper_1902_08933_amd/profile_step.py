@@ -49,6 +49,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tile", type=int, default=None, help="strip shape (default: library default)")
     ap.add_argument("--sweep", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="print the strip shape the library's autotuner picks for the workload and exit")
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--probe-blocks", type=int, default=0)
     a = ap.parse_args()
@@ -73,6 +75,11 @@ def main():
         return
     cfg, phi = make(a.workload, a.variant)
     cells = cfg["nx"] * cfg["ny"]
+    if a.autotune:
+        sim = lbpf.Simulation(cfg).init(torch.from_numpy(phi.astype("float32")).cuda())
+        best, _ = sim.autotune(trial_steps=20)
+        print(best, flush=True)
+        return 0
     tiles = range(len(lbpf.tile_shapes())) if a.sweep else [a.tile]
     for t in tiles:
         ms = run_steps(torch, cfg, phi, a.steps, a.warmup, t)

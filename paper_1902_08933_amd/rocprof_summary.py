@@ -48,10 +48,12 @@ def pmc_values(db, counter):
 
 
 def pick(d, key):
+    """the kernel whose name contains `key` with the most dispatches"""
     ks = [k for k in d if key in k]
     if not ks:
         raise SystemExit(f"no kernel matching {key!r} in {list(d)[:5]}")
-    return ks[0], d[ks[0]]
+    k = max(ks, key=lambda n: d[n][0] if isinstance(d[n], tuple) else len(d[n]))
+    return k, d[k]
 
 
 def main():

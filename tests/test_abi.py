@@ -59,6 +59,9 @@ def test_workspace_size_scales_with_grid(lib):
     (dict(W=0.0), "W must"),
     (dict(sigma=-0.1), "sigma"),
     (dict(variant="qim", force_x=float("nan")), "finite"),
+    # in-plane offsets are 32-bit byte offsets and row offsets use a 24-bit multiply
+    (dict(nx=1 << 24, ny=3), "below 2^24"),
+    (dict(nx=32768, ny=32768), "2^30"),
 ])
 def test_invalid_parameters_rejected(lib, bad, why):
     cfg, _ = workloads.static_droplet(n=16, R=4)
@@ -67,6 +70,12 @@ def test_invalid_parameters_rejected(lib, bad, why):
         lbpf.workspace_size(cfg)
     assert ei.value.status == -1
     assert why in str(ei.value)
+
+
+def test_largest_plane_accepted(lib):
+    # 32768 x 32704 nodes (plus the layout pad) stays below 2^30 floats per plane
+    cfg, _ = workloads.static_droplet(n=16, R=4)
+    assert lbpf.workspace_size(dict(cfg, nx=32768, ny=32704)) > 48 * 4 * 32768 * 32704
 
 
 def test_status_strings(lib):
