@@ -26,28 +26,7 @@
 
 #include "lbpf.h"
 
-namespace lbpf {
-typedef uint16_t bf16;
-hipError_t unet_mfma_probe(int k32, const bf16* A, const bf16* B, float* D, hipStream_t st);
-hipError_t unet_conv_fwd(int ks, bool relu, const bf16* x, int xs, int xo, int Cin, const bf16* w,
-                         const float* bias, bf16* y, int ys, int yo, int Cout, float* yf, int N,
-                         int H, int W, hipStream_t st);
-hipError_t unet_flip_weights(const bf16* w, bf16* wt, int Cout, int Cin, int taps, hipStream_t st);
-hipError_t unet_conv_wgrad(int ks, const bf16* dy, int dys, int dyo, int Cout, const bf16* x, int xs,
-                           int xo, int Cin, int N, int H, int W, int nchunks, float* part,
-                           float* bpart, float* dw, float* db, hipStream_t st);
-hipError_t unet_avgpool(const bf16* x, int xs, int xo, bf16* y, int ys, int yo, int C, int N, int H, int W, hipStream_t st);
-hipError_t unet_avgpool_bwd_add(const bf16* dy, int dys, int dyo, bf16* dx, int dxs, int dxo, int C, int N, int H, int W, hipStream_t st);
-hipError_t unet_upsample(const bf16* x, int xs, int xo, bf16* y, int ys, int yo, int C, int N, int H, int W, hipStream_t st);
-hipError_t unet_upsample_bwd(const bf16* dy, int dys, int dyo, bf16* dx, int dxs, int dxo, int C, int N, int H, int W, hipStream_t st);
-hipError_t unet_relu_bwd(bf16* g, int gs, int go, const bf16* a, int as, int ao, int C, long long npix, hipStream_t st);
-hipError_t unet_pack_input(const float* in, int cin, bf16* x0, long long npix, hipStream_t st);
-hipError_t unet_predict_loss(const float* in, const float* head, int cout, float* pred, const float* target,
-                             const float* wch, bf16* dy, long long npix, double* part, int nblk, hipStream_t st);
-hipError_t unet_adam(float* w, bf16* wb, const float* g, float* m, float* v, long long n, float lr, float b1,
-                     float b2, float eps, float c1, float c2, hipStream_t st);
-hipError_t unet_to_bf16(const float* a, bf16* b, long long n, hipStream_t st);
-}  // namespace lbpf
+#include "lbpf_unet_ops.hpp"
 
 using namespace lbpf;
 
@@ -226,33 +205,67 @@ static lbpf_status check_dims(lbpf_unet* u, int n, int h, int w) {
     return LBPF_OK;
 }
 
-// forward pass; leaves every activation in place for the backward pass
-static lbpf_status forward(lbpf_unet* u, const float* in, int n, int h, int w) {
+// Forward pass. The decoder convolutions read the upsampled half of their input straight from
+// the lower level (the concat is never formed). With `pred` (inference) the 1x1 head writes the
+// prediction input + Y[:, :in_ch] and nothing else; without it (loss and gradients) the head's
+// outputs are kept for the loss, and the upsampled halves of the concat buffers are written
+// out as well, since the weight gradients read them.
+static lbpf_status forward(lbpf_unet* u, const float* in, int n, int h, int w, float* pred) {
     const Geometry& g = u->g;
     hipStream_t st = u->stream;
     const long long np0 = (long long)n * h * w;
     const int* c = g.c;
     const int su0 = c[1] + c[0], su1 = c[2] + c[1], su2 = c[3] + c[2];
     const Layer* L = g.layer;
+    const bool keep = pred == nullptr;
     auto W = [&](int i) { return u->wbf + L[i].woff; };
     auto B = [&](int i) { return u->w32 + L[i].boff; };
     UCHK(unet_pack_input(in, u->cfg.in_ch, u->act[X0], np0, st));
-    // encoder
-    UCHK(unet_conv_fwd(3, true, u->act[X0], 16, 0, 16, W(0), B(0), u->act[U0], su0, c[1], c[0], nullptr, n, h, w, st));
-    UCHK(unet_avgpool(u->act[U0], su0, c[1], u->act[P1], c[0], 0, c[0], n, h, w, st));
-    UCHK(unet_conv_fwd(3, true, u->act[P1], c[0], 0, c[0], W(1), B(1), u->act[U1], su1, c[2], c[1], nullptr, n, h / 2, w / 2, st));
-    UCHK(unet_avgpool(u->act[U1], su1, c[2], u->act[P2], c[1], 0, c[1], n, h / 2, w / 2, st));
-    UCHK(unet_conv_fwd(3, true, u->act[P2], c[1], 0, c[1], W(2), B(2), u->act[U2], su2, c[3], c[2], nullptr, n, h / 4, w / 4, st));
-    UCHK(unet_avgpool(u->act[U2], su2, c[3], u->act[P3], c[2], 0, c[2], n, h / 4, w / 4, st));
-    UCHK(unet_conv_fwd(3, true, u->act[P3], c[2], 0, c[2], W(3), B(3), u->act[E3], c[3], 0, c[3], nullptr, n, h / 8, w / 8, st));
-    // decoder
-    UCHK(unet_upsample(u->act[E3], c[3], 0, u->act[U2], su2, 0, c[3], n, h / 4, w / 4, st));
-    UCHK(unet_conv_fwd(3, true, u->act[U2], su2, 0, su2, W(4), B(4), u->act[D2], c[2], 0, c[2], nullptr, n, h / 4, w / 4, st));
-    UCHK(unet_upsample(u->act[D2], c[2], 0, u->act[U1], su1, 0, c[2], n, h / 2, w / 2, st));
-    UCHK(unet_conv_fwd(3, true, u->act[U1], su1, 0, su1, W(5), B(5), u->act[D1], c[1], 0, c[1], nullptr, n, h / 2, w / 2, st));
-    UCHK(unet_upsample(u->act[D1], c[1], 0, u->act[U0], su0, 0, c[1], n, h, w, st));
-    UCHK(unet_conv_fwd(3, true, u->act[U0], su0, 0, su0, W(6), B(6), u->act[D0], c[0], 0, c[0], nullptr, n, h, w, st));
-    UCHK(unet_conv_fwd(1, false, u->act[D0], c[0], 0, c[0], W(7), B(7), u->act[YH], 16, 0, 16, u->head32, n, h, w, st));
+    // encoder: E_l goes into the second part of the concat buffer of its level, and its 2x2
+    // average pool P_{l+1} (the next layer's input) is written by the same kernel
+    auto enc = [&](int i, Buf xin, int cin, int sx, Buf out, int so, int oo, Buf pool, int cout,
+                   int lev) -> lbpf_status {
+        ConvArgs a{};
+        a.x = u->act[xin]; a.xs = sx; a.xo = 0;
+        a.Cin = cin; a.w = W(i); a.bias = B(i);
+        a.y = u->act[out]; a.ys = so; a.yo = oo;
+        if (pool != kNumBufs) { a.yp = u->act[pool]; a.yps = cout; a.ypo = 0; }
+        a.Cout = cout; a.N = n; a.H = h >> lev; a.W = w >> lev;
+        UCHK(unet_conv(3, true, a, st));
+        return LBPF_OK;
+    };
+    lbpf_status s;
+    if ((s = enc(0, X0, 16, 16, U0, su0, c[1], P1, c[0], 0))) return s;
+    if ((s = enc(1, P1, c[0], c[0], U1, su1, c[2], P2, c[1], 1))) return s;
+    if ((s = enc(2, P2, c[1], c[1], U2, su2, c[3], P3, c[2], 2))) return s;
+    if ((s = enc(3, P3, c[2], c[2], E3, c[3], 0, kNumBufs, c[3], 3))) return s;
+    // decoder: layer i reads [up(low), skip] with low = (buffer, channels), skip at offset cl of
+    // the concat buffer cat (stride scat), at level lev
+    auto dec = [&](int i, Buf low, int cl, Buf cat, int scat, Buf out, int cout, int lev) -> lbpf_status {
+        if (keep) UCHK(unet_upsample(u->act[low], cl, 0, u->act[cat], scat, 0, cl, n, h >> lev, w >> lev, st));
+        ConvArgs a{};
+        a.x = u->act[cat]; a.xs = scat; a.xo = cl;
+        a.xl = u->act[low]; a.xls = cl; a.xlo = 0; a.Cl = cl;
+        a.Cin = scat; a.w = W(i); a.bias = B(i);
+        a.y = u->act[out]; a.ys = cout; a.yo = 0;
+        a.Cout = cout; a.N = n; a.H = h >> lev; a.W = w >> lev;
+        UCHK(unet_conv(3, true, a, st));
+        return LBPF_OK;
+    };
+    if ((s = dec(4, E3, c[3], U2, su2, D2, c[2], 2))) return s;
+    if ((s = dec(5, D2, c[2], U1, su1, D1, c[1], 1))) return s;
+    if ((s = dec(6, D1, c[1], U0, su0, D0, c[0], 0))) return s;
+    ConvArgs a{};
+    a.x = u->act[D0]; a.xs = c[0]; a.xo = 0;
+    a.Cin = c[0]; a.w = W(7); a.bias = B(7);
+    a.Cout = 16; a.N = n; a.H = h; a.W = w;
+    if (keep) {
+        a.y = u->act[YH]; a.ys = 16; a.yo = 0;
+        a.yf = u->head32;
+    } else {
+        a.res = in; a.pred = pred; a.rc = u->cfg.in_ch;
+    }
+    UCHK(unet_conv(1, false, a, st));
     return LBPF_OK;
 }
 
@@ -444,10 +457,7 @@ lbpf_status lbpf_unet_forward(lbpf_unet* u, const float* in, float* out, int32_t
     if (!u || !in || !out) return u ? ufail(u, LBPF_E_INVALID, "NULL buffer") : LBPF_E_INVALID;
     u->err.clear();
     if (lbpf_status s = check_dims(u, n, h, w)) return s;
-    if (lbpf_status s = forward(u, in, n, h, w)) return s;
-    UCHK(unet_predict_loss(in, u->head32, u->cfg.in_ch, out, nullptr, nullptr, nullptr,
-                           (long long)n * h * w, nullptr, kLossBlocks, u->stream));
-    return LBPF_OK;
+    return forward(u, in, n, h, w, out);
 }
 
 lbpf_status lbpf_unet_loss_grad(lbpf_unet* u, const float* in, const float* target, int32_t n,
@@ -456,7 +466,7 @@ lbpf_status lbpf_unet_loss_grad(lbpf_unet* u, const float* in, const float* targ
     u->err.clear();
     if (!u->grad) return ufail(u, LBPF_E_STATE, "created without training buffers (cfg.train = 0)");
     if (lbpf_status s = check_dims(u, n, h, w)) return s;
-    if (lbpf_status s = forward(u, in, n, h, w)) return s;
+    if (lbpf_status s = forward(u, in, n, h, w, nullptr)) return s;
     UCHK(unet_predict_loss(in, u->head32, u->cfg.in_ch, nullptr, target, u->wch, u->gact[YH],
                            (long long)n * h * w, u->loss_part, kLossBlocks, u->stream));
     if (lbpf_status s = backward(u, n, h, w)) return s;

@@ -11,9 +11,10 @@
 
 #include <cstdint>
 
+#include "lbpf_unet_ops.hpp"
+
 namespace lbpf {
 
-typedef uint16_t bf16;
 typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
@@ -70,100 +71,55 @@ __global__ void mfma32_probe_kernel(const bf16* __restrict__ A, const bf16* __re
     for (int e = 0; e < 4; ++e) D[(4 * (l / 16) + e) * 16 + l % 16] = d[e];
 }
 
-// Convolution with a KS x KS kernel (KS = 1 or 3), stride 1, circular padding:
-//   y[p, co] = act( bias[co] + sum_{tap, ci} x[p + off(tap), ci] w[co, tap, ci] )
-// as an implicit GEMM: M = pixels, N = output channels, K = KS*KS*Cin.
-// x: NHWC bf16 with channel stride xs and offset xo (Cin channels used, Cin % 16 == 0)
-// w: [Cout][KS*KS][Cin] bf16; bias: Cout floats (may be NULL)
-// y: NHWC bf16 with channel stride ys and offset yo (Cout % 64 == 0 or the tail masked);
-// yf: optional FP32 copy, NHWC with channel stride Cout.
-// Workgroup: 4 waves; a wave computes 16 consecutive pixels x 64 output channels.
-template <int KS, bool RELU>
-__global__ __launch_bounds__(256) void conv_fwd_kernel(const bf16* __restrict__ x, int xs, int xo,
-                                                       int Cin, const bf16* __restrict__ w,
-                                                       const float* __restrict__ bias,
-                                                       bf16* __restrict__ y, int ys, int yo,
-                                                       int Cout, float* __restrict__ yf, int N,
-                                                       int H, int W) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long long npix = (long long)N * H * W;
-    const long long p0 = ((long long)blockIdx.x * 4 + wave) * 16;
-    const int co0 = blockIdx.y * 64;
-    if (p0 >= npix) return;
-    // pixel of this lane's A row
-    const long long pa = p0 + (lane & 15);
-    const bool pa_ok = pa < npix;
-    const long long pac = pa_ok ? pa : npix - 1;
-    const int xa = (int)(pac % W), ya = (int)((pac / W) % H);
-    const long long na = pac / ((long long)W * H);
-    const int kq = 4 * (lane >> 4);  // first of this lane's four k within a 16-chunk
-    float4_t acc[4];
-    for (int j = 0; j < 4; ++j) acc[j] = {0.f, 0.f, 0.f, 0.f};
-    const int K = KS * KS * Cin;
-    for (int tap = 0; tap < KS * KS; ++tap) {
-        const int dy = KS == 3 ? tap / 3 - 1 : 0, dx = KS == 3 ? tap % 3 - 1 : 0;
-        int sy = ya + dy, sx = xa + dx;
-        sy = sy < 0 ? sy + H : (sy >= H ? sy - H : sy);
-        sx = sx < 0 ? sx + W : (sx >= W ? sx - W : sx);
-        const bf16* xp = x + ((na * H + sy) * W + sx) * xs + xo + kq;
-        for (int kc = 0; kc < Cin; kc += 16) {
-            const short4_t a = load4(xp + kc);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int co = co0 + 16 * j + (lane & 15);
-                const short4_t b = co < Cout ? load4(w + (long long)co * K + tap * Cin + kc + kq)
-                                             : short4_t{0, 0, 0, 0};
-                acc[j] = mfma16(a, b, acc[j]);
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int co = co0 + 16 * j + (lane & 15);
-        if (co >= Cout) continue;
-        const float bb = bias ? bias[co] : 0.0f;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const long long p = p0 + 4 * (lane >> 4) + e;
-            if (p >= npix) continue;
-            float v = acc[j][e] + bb;
-            if (RELU) v = fmaxf(v, 0.0f);
-            y[p * ys + yo + co] = f2bf(v);
-            if (yf) yf[p * Cout + co] = v;
-        }
-    }
+// Convolution (contract in lbpf_unet_ops.hpp) as an implicit GEMM on MFMA: M = pixels,
+// N = output channels, K = KS*KS*Cin. A workgroup of 4 waves computes a tile of TR x TC
+// pixels of one image for COT output channels; wave w owns rows 4w .. 4w+3 of the tile, i.e.
+// four 16-pixel A fragments, so every B fragment read from LDS feeds four MFMAs. Per chunk of
+// 32 input channels the input patch (with its KS-1 halo, circular) and the weights of the COT
+// channels are staged in LDS (rows padded to 40 bf16 so that the 16 lanes of a fragment read hit
+// 16 different bank groups); each tap is then a 16x16x32 MFMA per (row fragment, 16 channels).
+// The next chunk is fetched into registers while the current one is multiplied. Channels below
+// Cl are read from the half-resolution tensor at (y/2, x/2): the nearest 2x upsampling fused
+// into the load. Pixels beyond a ragged image edge are computed from wrapped data and not
+// stored. The bf16 output leaves through LDS as 16-byte stores, and so does its 2x2 average
+// pool when asked for (tiles start at even coordinates, so every pool window is inside one).
+constexpr int kConvTR = 16, kConvTC = 16, kConvCK = 32, kConvCKP = 40;
+
+template <int KS, int COT>
+constexpr int conv_lds_elems() {
+    constexpr int PR = kConvTR + KS - 1, PC = kConvTC + KS - 1;
+    constexpr int in = PR * PC * kConvCKP + COT * KS * KS * kConvCKP;
+    constexpr int out = kConvTR * kConvTC * (COT + 8);
+    return in > out ? in : out;
 }
 
-// LDS-tiled convolution (same contract as conv_fwd_kernel): a workgroup of 4 waves computes a
-// tile of 4 rows x 16 columns of one image (wave w: row w) for COT output channels. Per chunk
-// of 32 input channels it stages the input patch (with its KS-1 halo, circular) and the
-// weights of the COT channels in LDS, then every tap is one 16x16x32 MFMA per 16 output
-// channels with the A fragment shared across them. The next chunk is loaded into registers
-// while the current one is multiplied. Pixels beyond the image (a ragged tile) are computed
-// from wrapped data and not stored.
+__device__ __forceinline__ int wrap_coord(int v, int m) {
+    if ((unsigned)v < (unsigned)m) return v;
+    const int r = v % m;
+    return r < 0 ? r + m : r;
+}
+
 template <int KS, bool RELU, int COT>
-__global__ __launch_bounds__(256) void conv_lds_kernel(const bf16* __restrict__ x, int xs, int xo,
-                                                       int Cin, const bf16* __restrict__ w,
-                                                       const float* __restrict__ bias,
-                                                       bf16* __restrict__ y, int ys, int yo,
-                                                       int Cout, float* __restrict__ yf, int N,
-                                                       int H, int W) {
-    constexpr int TR = 4, TC = 16, CK = 32, CKP = 40;  // CKP: padded LDS row (bank spread)
+__global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs a) {
+    constexpr int TR = kConvTR, TC = kConvTC, CK = kConvCK, CKP = kConvCKP;
     constexpr int HALO = KS - 1, PR = TR + HALO, PC = TC + HALO, T = KS * KS;
-    constexpr int NPATCH = PR * PC * (CK / 8);           // 16-byte pieces of the patch
-    constexpr int NWT = COT * T * (CK / 8);              // 16-byte pieces of the weights
+    constexpr int PIECES = CK / 8;                  // 16-byte pieces per pixel and chunk
+    constexpr int NPATCH = PR * PC * PIECES;
+    constexpr int NWT = COT * T * PIECES;
     constexpr int PP = (NPATCH + 255) / 256, PW = (NWT + 255) / 256;
-    __shared__ __attribute__((aligned(16))) bf16 s_x[PR * PC * CKP];
-    __shared__ __attribute__((aligned(16))) bf16 s_w[COT * T * CKP];
+    constexpr int MF = TR / 4, NF = COT / 16, COTP = COT + 8;
+    extern __shared__ __attribute__((aligned(16))) bf16 conv_lds[];
+    bf16* s_x = conv_lds;
+    bf16* s_w = conv_lds + PR * PC * CKP;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int H = a.H, W = a.W, Cin = a.Cin, Cl = a.Cl, Cout = a.Cout;
     const int tiles_x = (W + TC - 1) / TC, tiles_y = (H + TR - 1) / TR;
     const int tile = blockIdx.x;
     const int tx0 = (tile % tiles_x) * TC, ty0 = ((tile / tiles_x) % tiles_y) * TR;
-    const long long n = tile / (tiles_x * tiles_y);
+    const int n = tile / (tiles_x * tiles_y);
     const int co0 = blockIdx.y * COT;
-    const int K = T * Cin;
-    const int h0 = HALO / 2;
+    const int h0 = HALO / 2, Hl = H >> 1, Wl = W >> 1;
 
     short8_t rp[PP], rw[PW];
     auto fetch = [&](int kc) {
@@ -172,13 +128,15 @@ __global__ __launch_bounds__(256) void conv_lds_kernel(const bf16* __restrict__ 
             const int piece = tid + 256 * i;
             short8_t v = {0, 0, 0, 0, 0, 0, 0, 0};
             if (piece < NPATCH) {
-                const int q = piece % (CK / 8), pix = piece / (CK / 8);
-                const int pr = pix / PC, pc = pix % PC;
-                int sy = ty0 + pr - h0, sx = tx0 + pc - h0;
-                sy = ((sy % H) + H) % H;
-                sx = ((sx % W) + W) % W;
+                const int q = piece % PIECES, pix = piece / PIECES;
+                const int sy = wrap_coord(ty0 + pix / PC - h0, H), sx = wrap_coord(tx0 + pix % PC - h0, W);
                 const int ci = kc + 8 * q;
-                if (ci < Cin) v = *reinterpret_cast<const short8_t*>(x + ((n * H + sy) * W + sx) * xs + xo + ci);
+                if (ci < Cl)
+                    v = *reinterpret_cast<const short8_t*>(
+                        a.xl + ((size_t)(n * Hl + (sy >> 1)) * Wl + (sx >> 1)) * a.xls + a.xlo + ci);
+                else if (ci < Cin)
+                    v = *reinterpret_cast<const short8_t*>(
+                        a.x + ((size_t)(n * H + sy) * W + sx) * a.xs + a.xo + (ci - Cl));
             }
             rp[i] = v;
         }
@@ -187,10 +145,10 @@ __global__ __launch_bounds__(256) void conv_lds_kernel(const bf16* __restrict__ 
             const int piece = tid + 256 * i;
             short8_t v = {0, 0, 0, 0, 0, 0, 0, 0};
             if (piece < NWT) {
-                const int q = piece % (CK / 8), r = piece / (CK / 8);
-                const int tap = r % T, col = r / T;
-                const int co = co0 + col, ci = kc + 8 * q;
-                if (co < Cout && ci < Cin) v = *reinterpret_cast<const short8_t*>(w + (long long)co * K + tap * Cin + ci);
+                const int q = piece % PIECES, r = piece / PIECES;
+                const int co = co0 + r / T, ci = kc + 8 * q;
+                if (co < Cout && ci < Cin)
+                    v = *reinterpret_cast<const short8_t*>(a.w + ((size_t)co * T + r % T) * Cin + ci);
             }
             rw[i] = v;
         }
@@ -199,24 +157,22 @@ __global__ __launch_bounds__(256) void conv_lds_kernel(const bf16* __restrict__ 
 #pragma unroll
         for (int i = 0; i < PP; ++i) {
             const int piece = tid + 256 * i;
-            if (piece < NPATCH) {
-                const int q = piece % (CK / 8), pix = piece / (CK / 8);
-                *reinterpret_cast<short8_t*>(s_x + pix * CKP + 8 * q) = rp[i];
-            }
+            if (piece < NPATCH)
+                *reinterpret_cast<short8_t*>(s_x + (piece / PIECES) * CKP + 8 * (piece % PIECES)) = rp[i];
         }
 #pragma unroll
         for (int i = 0; i < PW; ++i) {
             const int piece = tid + 256 * i;
-            if (piece < NWT) {
-                const int q = piece % (CK / 8), r = piece / (CK / 8);
-                *reinterpret_cast<short8_t*>(s_w + r * CKP + 8 * q) = rw[i];
-            }
+            if (piece < NWT)
+                *reinterpret_cast<short8_t*>(s_w + (piece / PIECES) * CKP + 8 * (piece % PIECES)) = rw[i];
         }
     };
 
-    float4_t acc[COT / 16];
+    float4_t acc[MF][NF];
 #pragma unroll
-    for (int j = 0; j < COT / 16; ++j) acc[j] = {0.f, 0.f, 0.f, 0.f};
+    for (int f = 0; f < MF; ++f)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) acc[f][j] = {0.f, 0.f, 0.f, 0.f};
     const int m = lane & 15, kq = 8 * (lane >> 4);
     fetch(0);
     for (int kc = 0; kc < Cin; kc += CK) {
@@ -227,31 +183,74 @@ __global__ __launch_bounds__(256) void conv_lds_kernel(const bf16* __restrict__ 
 #pragma unroll
         for (int tap = 0; tap < T; ++tap) {
             const int dy = KS == 3 ? tap / 3 - 1 : 0, dx = KS == 3 ? tap % 3 - 1 : 0;
-            const short8_t a = *reinterpret_cast<const short8_t*>(
-                s_x + ((wave + dy + h0) * PC + (m + dx + h0)) * CKP + kq);
+            short8_t b[NF];
 #pragma unroll
-            for (int j = 0; j < COT / 16; ++j) {
-                const short8_t b = *reinterpret_cast<const short8_t*>(s_w + ((16 * j + m) * T + tap) * CKP + kq);
-                acc[j] = mfma32(a, b, acc[j]);
+            for (int j = 0; j < NF; ++j)
+                b[j] = *reinterpret_cast<const short8_t*>(s_w + ((16 * j + m) * T + tap) * CKP + kq);
+#pragma unroll
+            for (int f = 0; f < MF; ++f) {
+                const int row = wave * MF + f;
+                const short8_t av = *reinterpret_cast<const short8_t*>(
+                    s_x + ((row + dy + h0) * PC + (m + dx + h0)) * CKP + kq);
+#pragma unroll
+                for (int j = 0; j < NF; ++j) acc[f][j] = mfma32(av, b[j], acc[f][j]);
             }
         }
     }
-    // D: lane (j, i/4): column = output channel, rows = 4 consecutive pixels of this wave's row
+
+    // epilogue. D fragment: lane (16 * g + c) holds pixels 4g .. 4g+3 of the row, channel c.
+    __syncthreads();  // LDS is reused for the output tile
+    bf16* s_o = conv_lds;
 #pragma unroll
-    for (int j = 0; j < COT / 16; ++j) {
+    for (int j = 0; j < NF; ++j) {
         const int co = co0 + 16 * j + m;
-        if (co >= Cout) continue;
-        const float bb = bias ? bias[co] : 0.0f;
-        const int yy = ty0 + wave;
+        const float bb = (a.bias && co < Cout) ? a.bias[co] : 0.0f;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int xx = tx0 + 4 * (lane >> 4) + e;
-            if (yy >= H || xx >= W) continue;
-            const long long p = (n * H + yy) * W + xx;
-            float v = acc[j][e] + bb;
-            if (RELU) v = fmaxf(v, 0.0f);
-            y[p * ys + yo + co] = f2bf(v);
-            if (yf) yf[p * Cout + co] = v;
+        for (int f = 0; f < MF; ++f) {
+            const int py = wave * MF + f, yy = ty0 + py;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int px = 4 * (lane >> 4) + e, xx = tx0 + px;
+                float v = acc[f][j][e] + bb;
+                if (RELU) v = fmaxf(v, 0.0f);
+                if (a.y || a.yp) s_o[(py * TC + px) * COTP + 16 * j + m] = f2bf(v);
+                if (yy < H && xx < W && co < Cout) {
+                    const size_t p = (size_t)(n * H + yy) * W + xx;
+                    if (a.yf) a.yf[p * Cout + co] = v;
+                    if (a.pred && co < a.rc) a.pred[p * a.rc + co] = a.res[p * a.rc + co] + v;
+                }
+            }
+        }
+    }
+    if (!a.y && !a.yp) return;
+    __syncthreads();
+    if (a.y) {
+        for (int piece = tid; piece < TR * TC * (COT / 8); piece += 256) {
+            const int q = piece % (COT / 8), pix = piece / (COT / 8);
+            const int yy = ty0 + pix / TC, xx = tx0 + pix % TC, co = co0 + 8 * q;
+            if (yy < H && xx < W && co < Cout)
+                *reinterpret_cast<short8_t*>(a.y + ((size_t)(n * H + yy) * W + xx) * a.ys + a.yo + co) =
+                    *reinterpret_cast<const short8_t*>(s_o + pix * COTP + 8 * q);
+        }
+    }
+    if (a.yp) {
+        const int Hp = H >> 1, Wp = W >> 1;
+        for (int piece = tid; piece < (TR / 2) * (TC / 2) * (COT / 8); piece += 256) {
+            const int q = piece % (COT / 8), pix = piece / (COT / 8);
+            const int py = pix / (TC / 2), px = pix % (TC / 2);
+            const int yy = (ty0 >> 1) + py, xx = (tx0 >> 1) + px, co = co0 + 8 * q;
+            if (yy >= Hp || xx >= Wp || co >= Cout) continue;
+            const bf16* o = s_o + ((2 * py) * TC + 2 * px) * COTP + 8 * q;
+            const short8_t v0 = *reinterpret_cast<const short8_t*>(o);
+            const short8_t v1 = *reinterpret_cast<const short8_t*>(o + COTP);
+            const short8_t v2 = *reinterpret_cast<const short8_t*>(o + TC * COTP);
+            const short8_t v3 = *reinterpret_cast<const short8_t*>(o + (TC + 1) * COTP);
+            short8_t r;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                r[k] = (short)f2bf(0.25f * (bf2f((bf16)v0[k]) + bf2f((bf16)v1[k]) + bf2f((bf16)v2[k]) +
+                                            bf2f((bf16)v3[k])));
+            *reinterpret_cast<short8_t*>(a.yp + ((size_t)(n * Hp + yy) * Wp + xx) * a.yps + a.ypo + co) = r;
         }
     }
 }
@@ -345,91 +344,128 @@ __global__ void sum_chunks_kernel(const float* __restrict__ part, long long n, i
     }
 }
 
-// 2x2 average pool: y[n, Y, X, c] = mean of x[n, 2Y..2Y+1, 2X..2X+1, c] (x slice xs/xo, C ch)
-__global__ void avgpool_kernel(const bf16* __restrict__ x, int xs, int xo, bf16* __restrict__ y,
-                               int ys, int yo, int C, int N, int H, int W) {
-    const int Ho = H / 2, Wo = W / 2;
-    const long long n = (long long)N * Ho * Wo * C;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        const long long q = i / C;
-        const int X = (int)(q % Wo), Y = (int)((q / Wo) % Ho);
-        const long long nn = q / ((long long)Wo * Ho);
-        const long long b = ((nn * H + 2 * Y) * W + 2 * X);
-        const float s = bf2f(x[b * xs + xo + c]) + bf2f(x[(b + 1) * xs + xo + c]) +
-                        bf2f(x[(b + W) * xs + xo + c]) + bf2f(x[(b + W + 1) * xs + xo + c]);
-        y[q * ys + yo + c] = f2bf(0.25f * s);
+// Elementwise kernels on NHWC bf16 slices, 8 channels (one 16-byte piece) per thread: block b
+// walks image rows b, b + gridDim.x, ... (row = n * rows_per_image + y); the threads of a block
+// walk the (pixel, piece) pairs of the row. C, channel strides and offsets are multiples of 8.
+__device__ __forceinline__ short8_t ld8(const bf16* p) { return *reinterpret_cast<const short8_t*>(p); }
+__device__ __forceinline__ void st8(bf16* p, short8_t v) { *reinterpret_cast<short8_t*>(p) = v; }
+__device__ __forceinline__ float s2f(short s) { return bf2f((bf16)s); }
+
+// 2x2 average pool: y[n, Y, X, c] = mean of x[n, 2Y..2Y+1, 2X..2X+1, c] (H x W input)
+__global__ __launch_bounds__(256) void avgpool_kernel(const bf16* __restrict__ x, int xs, int xo,
+                                                      bf16* __restrict__ y, int ys, int yo, int C,
+                                                      int N, int H, int W) {
+    const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
+    for (int row = blockIdx.x; row < N * Ho; row += gridDim.x) {
+        const int nn = row / Ho, Y = row % Ho;
+        const size_t b0 = (size_t)(nn * H + 2 * Y) * W;
+        for (int j = threadIdx.x; j < Wo * C8; j += blockDim.x) {
+            const int X = j / C8, c = 8 * (j % C8);
+            const size_t b = b0 + 2 * X;
+            const short8_t v0 = ld8(x + b * xs + xo + c), v1 = ld8(x + (b + 1) * xs + xo + c);
+            const short8_t v2 = ld8(x + (b + W) * xs + xo + c), v3 = ld8(x + (b + W + 1) * xs + xo + c);
+            short8_t o;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                o[k] = (short)f2bf(0.25f * (s2f(v0[k]) + s2f(v1[k]) + s2f(v2[k]) + s2f(v3[k])));
+            st8(y + ((size_t)row * Wo + X) * ys + yo + c, o);
+        }
     }
 }
 
 // gradient of the pool added into the input-gradient slice: dx[p] += dy[parent(p)] / 4
-__global__ void avgpool_bwd_add_kernel(const bf16* __restrict__ dy, int dys, int dyo,
-                                       bf16* __restrict__ dx, int dxs, int dxo, int C, int N, int H,
-                                       int W) {
-    const long long n = (long long)N * H * W * C;
-    const int Ho = H / 2, Wo = W / 2;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        const long long p = i / C;
-        const int xx = (int)(p % W), yy = (int)((p / W) % H);
-        const long long nn = p / ((long long)W * H);
-        const long long q = (nn * Ho + yy / 2) * Wo + xx / 2;
-        const float v = bf2f(dx[p * dxs + dxo + c]) + 0.25f * bf2f(dy[q * dys + dyo + c]);
-        dx[p * dxs + dxo + c] = f2bf(v);
+__global__ __launch_bounds__(256) void avgpool_bwd_add_kernel(const bf16* __restrict__ dy, int dys, int dyo,
+                                                              bf16* __restrict__ dx, int dxs, int dxo,
+                                                              int C, int N, int H, int W) {
+    const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
+    for (int row = blockIdx.x; row < N * H; row += gridDim.x) {
+        const int nn = row / H, yy = row % H;
+        const size_t q0 = (size_t)(nn * Ho + yy / 2) * Wo;
+        for (int j = threadIdx.x; j < W * C8; j += blockDim.x) {
+            const int xx = j / C8, c = 8 * (j % C8);
+            bf16* d = dx + ((size_t)row * W + xx) * dxs + dxo + c;
+            const short8_t g = ld8(dy + (q0 + xx / 2) * dys + dyo + c), v = ld8(d);
+            short8_t o;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) o[k] = (short)f2bf(s2f(v[k]) + 0.25f * s2f(g[k]));
+            st8(d, o);
+        }
     }
 }
 
 // nearest 2x upsample: y[n, y, x, c] = x[n, y/2, x/2, c] (output H x W)
-__global__ void upsample_kernel(const bf16* __restrict__ x, int xs, int xo, bf16* __restrict__ y,
-                                int ys, int yo, int C, int N, int H, int W) {
-    const long long n = (long long)N * H * W * C;
-    const int Hi = H / 2, Wi = W / 2;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        const long long p = i / C;
-        const int xx = (int)(p % W), yy = (int)((p / W) % H);
-        const long long nn = p / ((long long)W * H);
-        y[p * ys + yo + c] = x[((nn * Hi + yy / 2) * Wi + xx / 2) * xs + xo + c];
+__global__ __launch_bounds__(256) void upsample_kernel(const bf16* __restrict__ x, int xs, int xo,
+                                                       bf16* __restrict__ y, int ys, int yo, int C,
+                                                       int N, int H, int W) {
+    const int Hi = H / 2, Wi = W / 2, C8 = C / 8;
+    for (int row = blockIdx.x; row < N * H; row += gridDim.x) {
+        const int nn = row / H, yy = row % H;
+        const size_t q0 = (size_t)(nn * Hi + yy / 2) * Wi;
+        for (int j = threadIdx.x; j < W * C8; j += blockDim.x) {
+            const int xx = j / C8, c = 8 * (j % C8);
+            st8(y + ((size_t)row * W + xx) * ys + yo + c, ld8(x + (q0 + xx / 2) * xs + xo + c));
+        }
     }
 }
 
-// gradient of the upsample: dx[q, c] = sum of dy over the 4 children of q (dx full buffer)
-__global__ void upsample_bwd_kernel(const bf16* __restrict__ dy, int dys, int dyo,
-                                    bf16* __restrict__ dx, int dxs, int dxo, int C, int N, int H,
-                                    int W) {
-    const int Ho = H / 2, Wo = W / 2;
-    const long long n = (long long)N * Ho * Wo * C;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        const long long q = i / C;
-        const int X = (int)(q % Wo), Y = (int)((q / Wo) % Ho);
-        const long long nn = q / ((long long)Wo * Ho);
-        const long long b = ((nn * H + 2 * Y) * W + 2 * X);
-        const float s = bf2f(dy[b * dys + dyo + c]) + bf2f(dy[(b + 1) * dys + dyo + c]) +
-                        bf2f(dy[(b + W) * dys + dyo + c]) + bf2f(dy[(b + W + 1) * dys + dyo + c]);
-        dx[q * dxs + dxo + c] = f2bf(s);
+// gradient of the upsample: dx[q, c] = sum of dy over the 4 children of q (dy is H x W)
+__global__ __launch_bounds__(256) void upsample_bwd_kernel(const bf16* __restrict__ dy, int dys, int dyo,
+                                                           bf16* __restrict__ dx, int dxs, int dxo,
+                                                           int C, int N, int H, int W) {
+    const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
+    for (int row = blockIdx.x; row < N * Ho; row += gridDim.x) {
+        const int nn = row / Ho, Y = row % Ho;
+        const size_t b0 = (size_t)(nn * H + 2 * Y) * W;
+        for (int j = threadIdx.x; j < Wo * C8; j += blockDim.x) {
+            const int X = j / C8, c = 8 * (j % C8);
+            const size_t b = b0 + 2 * X;
+            const short8_t v0 = ld8(dy + b * dys + dyo + c), v1 = ld8(dy + (b + 1) * dys + dyo + c);
+            const short8_t v2 = ld8(dy + (b + W) * dys + dyo + c), v3 = ld8(dy + (b + W + 1) * dys + dyo + c);
+            short8_t o;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                o[k] = (short)f2bf(s2f(v0[k]) + s2f(v1[k]) + s2f(v2[k]) + s2f(v3[k]));
+            st8(dx + ((size_t)row * Wo + X) * dxs + dxo + c, o);
+        }
     }
 }
 
-// ReLU gradient in place: g *= (a > 0), a the post-activation of the same slice layout
-__global__ void relu_bwd_kernel(bf16* __restrict__ g, int gs, int go, const bf16* __restrict__ a,
-                                int as, int ao, int C, long long npix) {
-    const long long n = npix * C;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        const long long p = i / C;
-        if (!(bf2f(a[p * as + ao + c]) > 0.0f)) g[p * gs + go + c] = 0;
+// ReLU gradient in place: g *= (a > 0), a the post-activation of the same slice layout;
+// npix pixels taken as rows of 1024 pixels (the last one partial)
+__global__ __launch_bounds__(256) void relu_bwd_kernel(bf16* __restrict__ g, int gs, int go,
+                                                       const bf16* __restrict__ a, int as, int ao,
+                                                       int C, long long npix) {
+    const int C8 = C / 8;
+    const long long rows = (npix + 1023) / 1024;
+    for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
+        const long long p0 = row * 1024;
+        const int w = (int)min(1024LL, npix - p0);
+        for (int j = threadIdx.x; j < w * C8; j += blockDim.x) {
+            const size_t p = (size_t)(p0 + j / C8);
+            const int c = 8 * (j % C8);
+            const short8_t av = ld8(a + p * as + ao + c);
+            short8_t gv = ld8(g + p * gs + go + c);
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (!(s2f(av[k]) > 0.0f)) gv[k] = 0;
+            st8(g + p * gs + go + c, gv);
+        }
     }
 }
 
 // pack network input: x0 (bf16, 16 channels, zero beyond cin) from FP32 NHWC [.., cin]
-__global__ void pack_input_kernel(const float* __restrict__ in, int cin, bf16* __restrict__ x0,
-                                  long long npix) {
-    const long long n = npix * 16;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(i % 16);
-        const long long p = i / 16;
-        x0[i] = c < cin ? f2bf(in[p * cin + c]) : (bf16)0;
+__global__ __launch_bounds__(256) void pack_input_kernel(const float* __restrict__ in, int cin,
+                                                         bf16* __restrict__ x0, long long npix) {
+    for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < npix; p += (long long)gridDim.x * 256) {
+        short8_t lo = {0, 0, 0, 0, 0, 0, 0, 0}, hi = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            if (c >= cin) break;
+            const short v = (short)f2bf(in[p * cin + c]);
+            if (c < 8) lo[c] = v; else hi[c - 8] = v;
+        }
+        st8(x0 + p * 16, lo);
+        st8(x0 + p * 16 + 8, hi);
     }
 }
 
@@ -514,38 +550,54 @@ hipError_t unet_mfma_probe(int k32, const bf16* A, const bf16* B, float* D, hipS
     return hipGetLastError();
 }
 
+template <int KS, bool R, int C>
+static hipError_t launch_conv_t(const ConvArgs& a, hipStream_t st) {
+    constexpr size_t lds = (size_t)conv_lds_elems<KS, C>() * sizeof(bf16);
+    static bool attr = false;  // dynamic LDS above 64 KiB must be requested once per kernel
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)&conv_tile_kernel<KS, R, C>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const long long tiles = (long long)a.N * ((a.H + kConvTR - 1) / kConvTR) * ((a.W + kConvTC - 1) / kConvTC);
+    dim3 grid((unsigned)tiles, (unsigned)((a.Cout + C - 1) / C));
+    hipLaunchKernelGGL((conv_tile_kernel<KS, R, C>), grid, dim3(256), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t unet_conv(int ks, bool relu, const ConvArgs& a, hipStream_t st) {
+    const bool aligned = a.Cin % 8 == 0 && a.xs % 8 == 0 && a.xo % 8 == 0 &&
+                         (a.Cl == 0 || (a.Cl % 8 == 0 && a.xls % 8 == 0 && a.xlo % 8 == 0 &&
+                                        a.H % 2 == 0 && a.W % 2 == 0)) &&
+                         (!a.y || (a.Cout % 8 == 0 && a.ys % 8 == 0 && a.yo % 8 == 0)) &&
+                         (!a.yp || (a.Cout % 8 == 0 && a.yps % 8 == 0 && a.ypo % 8 == 0 &&
+                                    a.H % 2 == 0 && a.W % 2 == 0)) &&
+                         (!a.pred || (a.res && a.rc <= a.Cout));
+    if (!aligned || (ks != 1 && ks != 3) || a.Cl > a.Cin || a.N < 1 || a.H < 1 || a.W < 1)
+        return hipErrorInvalidValue;
+    const int cot = a.Cout <= 16 ? 16 : (a.Cout <= 32 ? 32 : 64);
+#define LBPF_CONV(KS_, C_) return relu ? launch_conv_t<KS_, true, C_>(a, st) : launch_conv_t<KS_, false, C_>(a, st)
+    if (ks == 3) {
+        if (cot == 16) LBPF_CONV(3, 16);
+        if (cot == 32) LBPF_CONV(3, 32);
+        LBPF_CONV(3, 64);
+    }
+    if (cot == 16) LBPF_CONV(1, 16);
+    if (cot == 32) LBPF_CONV(1, 32);
+    LBPF_CONV(1, 64);
+#undef LBPF_CONV
+}
+
 hipError_t unet_conv_fwd(int ks, bool relu, const bf16* x, int xs, int xo, int Cin, const bf16* w,
                          const float* bias, bf16* y, int ys, int yo, int Cout, float* yf, int N,
                          int H, int W, hipStream_t st) {
-    // LDS-tiled MFMA kernel whenever the 16-byte pieces stay aligned, else the plain one
-    const bool tiled = (Cin % 8 == 0) && (xs % 8 == 0) && (xo % 8 == 0);
-    if (tiled) {
-        const long long tiles = (long long)N * ((H + 3) / 4) * ((W + 15) / 16);
-        const int cot = Cout <= 32 ? 32 : 64;
-        dim3 grid((unsigned)tiles, (unsigned)((Cout + cot - 1) / cot));
-#define LBPF_CONV(KS_, R_, C_) hipLaunchKernelGGL((conv_lds_kernel<KS_, R_, C_>), grid, dim3(256), 0, st, \
-                                                  x, xs, xo, Cin, w, bias, y, ys, yo, Cout, yf, N, H, W)
-        if (ks == 3) {
-            if (relu) { if (cot == 32) LBPF_CONV(3, true, 32); else LBPF_CONV(3, true, 64); }
-            else { if (cot == 32) LBPF_CONV(3, false, 32); else LBPF_CONV(3, false, 64); }
-        } else {
-            if (relu) { if (cot == 32) LBPF_CONV(1, true, 32); else LBPF_CONV(1, true, 64); }
-            else { if (cot == 32) LBPF_CONV(1, false, 32); else LBPF_CONV(1, false, 64); }
-        }
-#undef LBPF_CONV
-        return hipGetLastError();
-    }
-    const long long npix = (long long)N * H * W;
-    dim3 grid((unsigned)((npix + 63) / 64), (unsigned)((Cout + 63) / 64));
-    if (ks == 3 && relu)
-        hipLaunchKernelGGL((conv_fwd_kernel<3, true>), grid, dim3(256), 0, st, x, xs, xo, Cin, w, bias, y, ys, yo, Cout, yf, N, H, W);
-    else if (ks == 3)
-        hipLaunchKernelGGL((conv_fwd_kernel<3, false>), grid, dim3(256), 0, st, x, xs, xo, Cin, w, bias, y, ys, yo, Cout, yf, N, H, W);
-    else if (relu)
-        hipLaunchKernelGGL((conv_fwd_kernel<1, true>), grid, dim3(256), 0, st, x, xs, xo, Cin, w, bias, y, ys, yo, Cout, yf, N, H, W);
-    else
-        hipLaunchKernelGGL((conv_fwd_kernel<1, false>), grid, dim3(256), 0, st, x, xs, xo, Cin, w, bias, y, ys, yo, Cout, yf, N, H, W);
-    return hipGetLastError();
+    ConvArgs a{};
+    a.x = x; a.xs = xs; a.xo = xo;
+    a.Cin = Cin; a.w = w; a.bias = bias;
+    a.y = y; a.ys = ys; a.yo = yo; a.yf = yf;
+    a.Cout = Cout; a.N = N; a.H = H; a.W = W;
+    return unet_conv(ks, relu, a, st);
 }
 
 hipError_t unet_flip_weights(const bf16* w, bf16* wt, int Cout, int Cin, int taps, hipStream_t st) {
@@ -573,28 +625,30 @@ hipError_t unet_conv_wgrad(int ks, const bf16* dy, int dys, int dyo, int Cout, c
     return hipGetLastError();
 }
 
+static dim3 row_grid(long long rows) { return dim3((unsigned)(rows < 65536 ? (rows < 1 ? 1 : rows) : 65536)); }
+
 hipError_t unet_avgpool(const bf16* x, int xs, int xo, bf16* y, int ys, int yo, int C, int N, int H, int W, hipStream_t st) {
-    hipLaunchKernelGGL(avgpool_kernel, ew_grid((long long)N * H * W * C / 4), dim3(256), 0, st, x, xs, xo, y, ys, yo, C, N, H, W);
+    hipLaunchKernelGGL(avgpool_kernel, row_grid((long long)N * H / 2), dim3(256), 0, st, x, xs, xo, y, ys, yo, C, N, H, W);
     return hipGetLastError();
 }
 hipError_t unet_avgpool_bwd_add(const bf16* dy, int dys, int dyo, bf16* dx, int dxs, int dxo, int C, int N, int H, int W, hipStream_t st) {
-    hipLaunchKernelGGL(avgpool_bwd_add_kernel, ew_grid((long long)N * H * W * C), dim3(256), 0, st, dy, dys, dyo, dx, dxs, dxo, C, N, H, W);
+    hipLaunchKernelGGL(avgpool_bwd_add_kernel, row_grid((long long)N * H), dim3(256), 0, st, dy, dys, dyo, dx, dxs, dxo, C, N, H, W);
     return hipGetLastError();
 }
 hipError_t unet_upsample(const bf16* x, int xs, int xo, bf16* y, int ys, int yo, int C, int N, int H, int W, hipStream_t st) {
-    hipLaunchKernelGGL(upsample_kernel, ew_grid((long long)N * H * W * C), dim3(256), 0, st, x, xs, xo, y, ys, yo, C, N, H, W);
+    hipLaunchKernelGGL(upsample_kernel, row_grid((long long)N * H), dim3(256), 0, st, x, xs, xo, y, ys, yo, C, N, H, W);
     return hipGetLastError();
 }
 hipError_t unet_upsample_bwd(const bf16* dy, int dys, int dyo, bf16* dx, int dxs, int dxo, int C, int N, int H, int W, hipStream_t st) {
-    hipLaunchKernelGGL(upsample_bwd_kernel, ew_grid((long long)N * H * W * C / 4), dim3(256), 0, st, dy, dys, dyo, dx, dxs, dxo, C, N, H, W);
+    hipLaunchKernelGGL(upsample_bwd_kernel, row_grid((long long)N * H / 2), dim3(256), 0, st, dy, dys, dyo, dx, dxs, dxo, C, N, H, W);
     return hipGetLastError();
 }
 hipError_t unet_relu_bwd(bf16* g, int gs, int go, const bf16* a, int as, int ao, int C, long long npix, hipStream_t st) {
-    hipLaunchKernelGGL(relu_bwd_kernel, ew_grid(npix * C), dim3(256), 0, st, g, gs, go, a, as, ao, C, npix);
+    hipLaunchKernelGGL(relu_bwd_kernel, row_grid((npix + 1023) / 1024), dim3(256), 0, st, g, gs, go, a, as, ao, C, npix);
     return hipGetLastError();
 }
 hipError_t unet_pack_input(const float* in, int cin, bf16* x0, long long npix, hipStream_t st) {
-    hipLaunchKernelGGL(pack_input_kernel, ew_grid(npix * 16), dim3(256), 0, st, in, cin, x0, npix);
+    hipLaunchKernelGGL(pack_input_kernel, ew_grid(npix), dim3(256), 0, st, in, cin, x0, npix);
     return hipGetLastError();
 }
 hipError_t unet_predict_loss(const float* in, const float* head, int cout, float* pred, const float* target,

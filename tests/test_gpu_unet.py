@@ -85,6 +85,24 @@ def test_forward_and_gradients_match_oracle():
         assert ei < 6e-2
 
 
+@pytest.mark.parametrize("n,h,w", [(1, 40, 24), (3, 16, 72)])
+def test_inference_forward_matches_oracle(n, h, w):
+    # inference networks fuse the decoder upsampling into the convolutions and write the
+    # prediction from the head; sizes with partial 16 x 16 tiles at every level
+    import torch
+    from paper_1902_08933_amd import lbpf
+    rng = np.random.default_rng(11 + n)
+    net = lbpf.UNet(max_batch=n, max_h=h, max_w=w, train=False, seed=3)
+    p = random_params(net, rng)
+    net.set_params(torch.from_numpy(p.astype(np.float32)))
+    x = U.bf16_round(rng.normal(size=(n, h, w, 4)))
+    pred = net.forward(torch.from_numpy(x.astype(np.float32)).cuda()).double().cpu().numpy()
+    ref, _ = U.forward(p, x, base=32)
+    e = rel(pred - x, ref - x)
+    print(f"inference forward {n}x{h}x{w}: change rel L2 {e:.3e}", flush=True)
+    assert e < 2e-2
+
+
 def test_training_fits_a_fixed_batch():
     import torch
     from paper_1902_08933_amd import lbpf
