@@ -244,7 +244,8 @@ typedef struct lbpf_unet_cfg {
     int32_t max_batch;    /* largest n * h * w the workspace holds is max_batch*max_h*max_w */
     int32_t max_h, max_w; /* multiples of 8 */
     int32_t train;        /* nonzero: workspace includes gradients and Adam moments */
-    int32_t wgrad_chunks; /* pixel chunks of the weight-gradient reduction (0: 64) */
+    int32_t wgrad_chunks; /* size of the weight-gradient partial buffers, in pixel chunks of the
+                           * largest layer (0: 64); smaller layers use proportionally more chunks */
     int32_t pad;
     uint64_t seed;        /* He-normal initial weights; the head starts at zero */
 } lbpf_unet_cfg;

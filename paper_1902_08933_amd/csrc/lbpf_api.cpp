@@ -388,8 +388,8 @@ lbpf_status lbpf_autotune(lbpf_ctx* c, int32_t trial_steps, void* scratch_state,
         if (ms_out) ms_out[t] = ms;
         if (t == 0 || ms < best_ms) { best_ms = ms; best = t; }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);  // cleanup: nothing to do on failure
+    (void)hipEventDestroy(e1);
     c->tile = keep;
     if (st != LBPF_OK) return st;
     if (lbpf_status s = lbpf_load_state(c, scratch_state)) return s;
@@ -541,8 +541,8 @@ static size_t batch_header_bytes(int n, const lbpf_params* params) {
 
 static void destroy_graphs(lbpf_batch* b) {
     for (int i = 0; i < 2; ++i) {
-        if (b->exec[i]) hipGraphExecDestroy(b->exec[i]);
-        if (b->graph[i]) hipGraphDestroy(b->graph[i]);
+        if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
+        if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
         b->exec[i] = nullptr;
         b->graph[i] = nullptr;
     }
@@ -849,8 +849,8 @@ lbpf_status lbpf_batch_autotune(lbpf_batch* b, int32_t trial_steps, void* scratc
         if (ms_out) ms_out[t] = ms;
         if (t == 0 || ms < best_ms) { best_ms = ms; best = t; }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);  // cleanup: nothing to do on failure
+    (void)hipEventDestroy(e1);
     if (st != LBPF_OK) return st;
     // restore: every instance state back into copy A, then the batch continues from parity 0
     for (int k = 0; k < b->n; ++k)

@@ -205,6 +205,16 @@ static lbpf_status check_dims(lbpf_unet* u, int n, int h, int w) {
     return LBPF_OK;
 }
 
+// Largest number of pixel chunks whose weight-gradient partials of layer L fit the partial
+// buffers (sized for wgrad_chunks chunks of the largest layer).
+static int wgrad_max_chunks(const lbpf_unet* u, const Layer& L) {
+    const long long cfg_chunks = u->cfg.wgrad_chunks > 0 ? u->cfg.wgrad_chunks : 64;
+    const long long by_w = cfg_chunks * u->g.max_layer_w / ((long long)L.cout * L.ks * L.ks * L.cin);
+    const long long by_b = cfg_chunks * (u->cfg.base_ch << 3) / L.cout;
+    const long long m = by_w < by_b ? by_w : by_b;
+    return (int)(m > (1 << 20) ? (1 << 20) : m);
+}
+
 // Forward pass. The decoder convolutions read the upsampled half of their input straight from
 // the lower level (the concat is never formed). With `pred` (inference) the 1x1 head writes the
 // prediction input + Y[:, :in_ch] and nothing else; without it (loss and gradients) the head's
@@ -287,8 +297,7 @@ static lbpf_status conv_backward(lbpf_unet* u, int i, int lev, int n, int h, int
     const Layer& L = u->g.layer[i];
     hipStream_t st = u->stream;
     const int H = h >> lev, Wd = w >> lev;
-    const int chunks = u->cfg.wgrad_chunks > 0 ? u->cfg.wgrad_chunks : 64;
-    UCHK(unet_conv_wgrad(L.ks, u->gact[yb], ys, 0, L.cout, u->act[xb], xs, xo, L.cin, n, H, Wd, chunks,
+    UCHK(unet_conv_wgrad(L.ks, u->gact[yb], ys, 0, L.cout, u->act[xb], xs, xo, L.cin, n, H, Wd, wgrad_max_chunks(u, L),
                          u->wpart, u->bpart, u->grad + L.woff, u->grad + L.boff, st));
     if (dxb >= 0) {
         UCHK(unet_flip_weights(u->wbf + L.woff, u->wflip + L.woff, L.cout, L.cin, L.ks * L.ks, st));
@@ -326,7 +335,7 @@ static lbpf_status backward(lbpf_unet* u, int n, int h, int w) {
     UCHK(unet_relu_bwd(u->gact[U2], su2, c[3], u->act[U2], su2, c[3], c[2], np2, st));
     {
         const Layer& L = u->g.layer[2];
-        const int chunks = u->cfg.wgrad_chunks > 0 ? u->cfg.wgrad_chunks : 64;
+        const int chunks = wgrad_max_chunks(u, L);
         UCHK(unet_conv_wgrad(3, u->gact[U2], su2, c[3], L.cout, u->act[P2], c[1], 0, L.cin, n, h / 4, w / 4,
                              chunks, u->wpart, u->bpart, u->grad + L.woff, u->grad + L.boff, st));
         UCHK(unet_flip_weights(u->wbf + L.woff, u->wflip + L.woff, L.cout, L.cin, 9, st));
@@ -337,7 +346,7 @@ static lbpf_status backward(lbpf_unet* u, int n, int h, int w) {
     UCHK(unet_relu_bwd(u->gact[U1], su1, c[2], u->act[U1], su1, c[2], c[1], np1, st));
     {
         const Layer& L = u->g.layer[1];
-        const int chunks = u->cfg.wgrad_chunks > 0 ? u->cfg.wgrad_chunks : 64;
+        const int chunks = wgrad_max_chunks(u, L);
         UCHK(unet_conv_wgrad(3, u->gact[U1], su1, c[2], L.cout, u->act[P1], c[0], 0, L.cin, n, h / 2, w / 2,
                              chunks, u->wpart, u->bpart, u->grad + L.woff, u->grad + L.boff, st));
         UCHK(unet_flip_weights(u->wbf + L.woff, u->wflip + L.woff, L.cout, L.cin, 9, st));
@@ -348,7 +357,7 @@ static lbpf_status backward(lbpf_unet* u, int n, int h, int w) {
     UCHK(unet_relu_bwd(u->gact[U0], su0, c[1], u->act[U0], su0, c[1], c[0], np0, st));
     {
         const Layer& L = u->g.layer[0];
-        const int chunks = u->cfg.wgrad_chunks > 0 ? u->cfg.wgrad_chunks : 64;
+        const int chunks = wgrad_max_chunks(u, L);
         UCHK(unet_conv_wgrad(3, u->gact[U0], su0, c[1], L.cout, u->act[X0], 16, 0, L.cin, n, h, w,
                              chunks, u->wpart, u->bpart, u->grad + L.woff, u->grad + L.boff, st));
     }

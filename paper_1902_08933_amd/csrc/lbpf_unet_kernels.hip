@@ -270,77 +270,137 @@ __global__ void flip_weights_kernel(const bf16* __restrict__ w, bf16* __restrict
 
 // Weight gradient partials: part[chunk][co][tap][ci] = sum over the chunk's pixels p of
 // dy[p, co] x[p + off(tap), ci]; bias partial bpart[chunk][co] = sum_p dy[p, co].
-// One wave per (16 output channels, 64 input channels, tap, pixel chunk).
-template <int KS>
-__global__ __launch_bounds__(64) void conv_wgrad_kernel(const bf16* __restrict__ dy, int dys, int dyo,
-                                                        int Cout, const bf16* __restrict__ x,
-                                                        int xs, int xo, int Cin, int N, int H, int W,
-                                                        int chunk_pix, float* __restrict__ part,
-                                                        float* __restrict__ bpart) {
-    const int lane = threadIdx.x;
-    const int co0 = blockIdx.x * 16, ci0 = blockIdx.y * 64;
-    const int tap = blockIdx.z % (KS * KS), chunk = blockIdx.z / (KS * KS);
-    const int dyy = KS == 3 ? tap / 3 - 1 : 0, dxx = KS == 3 ? tap % 3 - 1 : 0;
-    const long long npix = (long long)N * H * W;
-    const long long pbeg = (long long)chunk * chunk_pix;
-    const long long pend = min(npix, pbeg + chunk_pix);
-    float4_t acc[4];
-    for (int j = 0; j < 4; ++j) acc[j] = {0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.0f;
-    const int kq = 4 * (lane >> 4);
-    for (long long p0 = pbeg; p0 < pend; p0 += 16) {
-        short4_t a;
-        short4_t b[4];
+// An implicit GEMM with the pixels as the contraction: M = output channels, N = input
+// channels, K = pixels, on the 16x16x32 MFMA. A workgroup of 4 waves owns COT output channels
+// x 64 input channels (wave w: channels 16w .. 16w+15) and walks the 8 x 16 pixel tiles of
+// its chunk; per tile the output gradient and the input patch (with its KS-1 halo, circular)
+// are staged in LDS in their NHWC order, and every fragment (8 consecutive pixels of one
+// channel per lane) is gathered with 2-byte LDS reads. Rows are padded to 68 bf16 so that the
+// four 8-pixel groups of a fragment fall on different banks. All KS*KS taps accumulate at
+// once; the bias is one more MFMA against a fragment of ones. Pixels beyond a ragged image
+// edge carry a zero output gradient.
+constexpr int kWgTH = 8, kWgTW = 16, kWgCIT = 64;
+
+template <int KS, int COT>
+__global__ __launch_bounds__(256) void wgrad_tile_kernel(const bf16* __restrict__ dy, int dys, int dyo,
+                                                         int Cout, const bf16* __restrict__ x, int xs,
+                                                         int xo, int Cin, int N, int H, int W,
+                                                         int tiles_per_chunk, float* __restrict__ part,
+                                                         float* __restrict__ bpart) {
+    constexpr int TH = kWgTH, TW = kWgTW, NPX = TH * TW, CIT = kWgCIT;
+    constexpr int HALO = KS - 1, XH = TH + HALO, XW = TW + HALO, T = KS * KS;
+    constexpr int DYP = COT + 4, XP = CIT + 4, NF = COT / 16;
+    __shared__ __attribute__((aligned(16))) bf16 s_dy[NPX * DYP];
+    __shared__ __attribute__((aligned(16))) bf16 s_x[XH * XW * XP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int co0 = blockIdx.x * COT, ci0 = blockIdx.y * CIT, chunk = blockIdx.z;
+    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
+    const int ntiles = N * tiles_x * tiles_y;
+    const int t_begin = chunk * tiles_per_chunk;
+    const int t_end = min(ntiles, t_begin + tiles_per_chunk);
+    const int h0 = HALO / 2;
+    const bool bias_wave = blockIdx.y == 0 && wave == 0;
+    const int g = lane >> 4, i = lane & 15;
+
+    float4_t acc[NF][T], accb[NF];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const long long p = p0 + kq + e;
-            const bool ok = p < pend;
-            // A[i = co][k = pixel]
-            a[e] = ok ? (short)dy[p * dys + dyo + co0 + (lane & 15)] : (short)0;
-            long long src = 0;
-            if (ok) {
-                const int xx = (int)(p % W), yy = (int)((p / W) % H);
-                const long long nn = p / ((long long)W * H);
-                int sy = yy + dyy, sx = xx + dxx;
-                sy = sy < 0 ? sy + H : (sy >= H ? sy - H : sy);
-                sx = sx < 0 ? sx + W : (sx >= W ? sx - W : sx);
-                src = ((nn * H + sy) * W + sx) * xs + xo;
-            }
+    for (int f = 0; f < NF; ++f) {
+        accb[f] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int ci = ci0 + 16 * j + (lane & 15);
-                b[j][e] = (ok && ci < Cin) ? (short)x[src + ci] : (short)0;
-            }
+        for (int t = 0; t < T; ++t) acc[f][t] = {0.f, 0.f, 0.f, 0.f};
+    }
+    short8_t ones;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ones[k] = (short)0x3f80;  // bf16 1.0
+
+    for (int t = t_begin; t < t_end; ++t) {
+        const int tx0 = (t % tiles_x) * TW, ty0 = ((t / tiles_x) % tiles_y) * TH;
+        const int n = t / (tiles_x * tiles_y);
+        __syncthreads();  // the previous tile's fragments have been read
+        for (int piece = tid; piece < NPX * (COT / 8); piece += 256) {
+            const int q = piece % (COT / 8), pix = piece / (COT / 8);
+            const int yy = ty0 + pix / TW, xx = tx0 + pix % TW, co = co0 + 8 * q;
+            short8_t v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (yy < H && xx < W && co < Cout)
+                v = *reinterpret_cast<const short8_t*>(dy + ((size_t)(n * H + yy) * W + xx) * dys + dyo + co);
+            short4_t* d = reinterpret_cast<short4_t*>(s_dy + pix * DYP + 8 * q);
+            d[0] = short4_t{v[0], v[1], v[2], v[3]};
+            d[1] = short4_t{v[4], v[5], v[6], v[7]};
         }
+        for (int piece = tid; piece < XH * XW * (CIT / 8); piece += 256) {
+            const int q = piece % (CIT / 8), pix = piece / (CIT / 8);
+            const int sy = wrap_coord(ty0 + pix / XW - h0, H), sx = wrap_coord(tx0 + pix % XW - h0, W);
+            const int ci = ci0 + 8 * q;
+            short8_t v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (ci < Cin)
+                v = *reinterpret_cast<const short8_t*>(x + ((size_t)(n * H + sy) * W + sx) * xs + xo + ci);
+            short4_t* d = reinterpret_cast<short4_t*>(s_x + pix * XP + 8 * q);
+            d[0] = short4_t{v[0], v[1], v[2], v[3]};
+            d[1] = short4_t{v[4], v[5], v[6], v[7]};
+        }
+        __syncthreads();
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[j] = mfma16(a, b[j], acc[j]);
-        if (tap == 0 && blockIdx.y == 0) {
-            // bias: lanes 0..15 sum dy over the 16 pixels of this step for their channel
-            if (lane < 16)
-                for (int k = 0; k < 16 && p0 + k < pend; ++k) bsum += bf2f(dy[(p0 + k) * dys + dyo + co0 + lane]);
+        for (int ks = 0; ks < NPX / 32; ++ks) {
+            // this lane's 8 pixels of the 32-pixel K step: row 2 ks + g/2, columns 8 (g&1) + 0..7
+            const int prow = 2 * ks + (g >> 1), pcol = 8 * (g & 1);
+            short8_t af[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) af[f][e] = (short)s_dy[(prow * TW + pcol + e) * DYP + 16 * f + i];
+#pragma unroll
+            for (int tap = 0; tap < T; ++tap) {
+                const int ddy = KS == 3 ? tap / 3 - 1 : 0, ddx = KS == 3 ? tap % 3 - 1 : 0;
+                short8_t bf;
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    bf[e] = (short)s_x[((prow + ddy + h0) * XW + pcol + e + ddx + h0) * XP + 16 * wave + i];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) acc[f][tap] = mfma32(af[f], bf, acc[f][tap]);
+            }
+            if (bias_wave) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) accb[f] = mfma32(af[f], ones, accb[f]);
+            }
         }
     }
-    const int taps = KS * KS;
+    // D: lane (i + 16 g) holds rows 4g .. 4g+3 (output channels) of column i (input channel)
+    const int ci = ci0 + 16 * wave + i;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int ci = ci0 + 16 * j + (lane & 15);
-        if (ci >= Cin) continue;
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int co = co0 + 4 * (lane >> 4) + e;
-            part[(((long long)chunk * Cout + co) * taps + tap) * Cin + ci] = acc[j][e];
+            const int co = co0 + 16 * f + 4 * g + e;
+            if (co >= Cout) continue;
+            if (ci < Cin) {
+#pragma unroll
+                for (int tap = 0; tap < T; ++tap)
+                    part[(((size_t)chunk * Cout + co) * T + tap) * Cin + ci] = acc[f][tap][e];
+            }
+            if (bias_wave && i == 0) bpart[(size_t)chunk * Cout + co] = accb[f][e];
         }
-    }
-    if (tap == 0 && blockIdx.y == 0 && lane < 16) bpart[(long long)chunk * Cout + co0 + lane] = bsum;
 }
 
-// Deterministic sum over chunks: out[i] = sum_c part[c][i]
-__global__ void sum_chunks_kernel(const float* __restrict__ part, long long n, int nchunks,
-                                  float* __restrict__ out) {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+// Deterministic sum over chunks: out[i] = sum_c part[c][i]. A workgroup takes 16 consecutive
+// indices; its 16 chunk lanes each sum the chunks c = lane, lane + 16, ... in order, and the
+// 16 lane sums are added in lane order.
+__global__ __launch_bounds__(256) void sum_chunks_kernel(const float* __restrict__ part, long long n,
+                                                         int nchunks, float* __restrict__ out) {
+    __shared__ float sh[16][17];
+    const int j = threadIdx.x & 15, cl = threadIdx.x >> 4;
+    for (long long i0 = (long long)blockIdx.x * 16; i0 < n; i0 += (long long)gridDim.x * 16) {
+        const long long i = i0 + j;
         float s = 0.0f;
-        for (int c = 0; c < nchunks; ++c) s += part[(long long)c * n + i];
-        out[i] = s;
+        if (i < n)
+            for (int c = cl; c < nchunks; c += 16) s += part[(long long)c * n + i];
+        sh[cl][j] = s;
+        __syncthreads();
+        if (cl == 0 && i < n) {
+            float t = 0.0f;
+            for (int k = 0; k < 16; ++k) t += sh[k][j];
+            out[i] = t;
+        }
+        __syncthreads();
     }
 }
 
@@ -431,15 +491,15 @@ __global__ __launch_bounds__(256) void upsample_bwd_kernel(const bf16* __restric
 }
 
 // ReLU gradient in place: g *= (a > 0), a the post-activation of the same slice layout;
-// npix pixels taken as rows of 1024 pixels (the last one partial)
+// npix pixels taken as rows of 64 pixels (the last one partial)
 __global__ __launch_bounds__(256) void relu_bwd_kernel(bf16* __restrict__ g, int gs, int go,
                                                        const bf16* __restrict__ a, int as, int ao,
                                                        int C, long long npix) {
     const int C8 = C / 8;
-    const long long rows = (npix + 1023) / 1024;
+    const long long rows = (npix + 63) / 64;
     for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
-        const long long p0 = row * 1024;
-        const int w = (int)min(1024LL, npix - p0);
+        const long long p0 = row * 64;
+        const int w = (int)min(64LL, npix - p0);
         for (int j = threadIdx.x; j < w * C8; j += blockDim.x) {
             const size_t p = (size_t)(p0 + j / C8);
             const int c = 8 * (j % C8);
@@ -535,6 +595,8 @@ __global__ void bf16_to_f32_kernel(const bf16* __restrict__ b, float* __restrict
 // ---------------------------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------------------------
+static dim3 row_grid(long long rows) { return dim3((unsigned)(rows < 65536 ? (rows < 1 ? 1 : rows) : 65536)); }
+
 static dim3 ew_grid(long long n) {
     long long b = (n + 255) / 256;
     if (b > 65536) b = 65536;
@@ -606,26 +668,33 @@ hipError_t unet_flip_weights(const bf16* w, bf16* wt, int Cout, int Cin, int tap
 }
 
 hipError_t unet_conv_wgrad(int ks, const bf16* dy, int dys, int dyo, int Cout, const bf16* x, int xs,
-                           int xo, int Cin, int N, int H, int W, int nchunks, float* part,
+                           int xo, int Cin, int N, int H, int W, int max_chunks, float* part,
                            float* bpart, float* dw, float* db, hipStream_t st) {
-    const long long npix = (long long)N * H * W;
-    long long chunk = (npix + nchunks - 1) / nchunks;
-    chunk = (chunk + 15) / 16 * 16;
+    if ((ks != 1 && ks != 3) || max_chunks < 1 || dys % 8 || dyo % 8 || xs % 8 || xo % 8 || Cout % 8 || Cin % 8)
+        return hipErrorInvalidValue;
     const int taps = ks * ks;
-    dim3 grid((unsigned)(Cout / 16), (unsigned)((Cin + 63) / 64), (unsigned)(taps * nchunks));
-    if (ks == 3)
-        hipLaunchKernelGGL((conv_wgrad_kernel<3>), grid, dim3(64), 0, st, dy, dys, dyo, Cout, x, xs, xo, Cin, N, H, W, (int)chunk, part, bpart);
-    else
-        hipLaunchKernelGGL((conv_wgrad_kernel<1>), grid, dim3(64), 0, st, dy, dys, dyo, Cout, x, xs, xo, Cin, N, H, W, (int)chunk, part, bpart);
+    const long long ntiles = (long long)N * ((H + kWgTH - 1) / kWgTH) * ((W + kWgTW - 1) / kWgTW);
+    const int cot = Cout <= 32 ? 32 : 64;
+    const int gx = (Cout + cot - 1) / cot, gy = (Cin + kWgCIT - 1) / kWgCIT;
+    // pixel chunks: about 1024 workgroups in all, within the partial buffer
+    long long want = (1024 + gx * gy - 1) / (gx * gy);
+    if (want > max_chunks) want = max_chunks;
+    if (want > ntiles) want = ntiles;
+    const int tpc = (int)((ntiles + want - 1) / want);
+    const int chunks = (int)((ntiles + tpc - 1) / tpc);
+    dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)chunks);
+#define LBPF_WG(KS_, C_) hipLaunchKernelGGL((wgrad_tile_kernel<KS_, C_>), grid, dim3(256), 0, st, dy, dys, dyo, \
+                                            Cout, x, xs, xo, Cin, N, H, W, tpc, part, bpart)
+    if (ks == 3) { if (cot == 32) LBPF_WG(3, 32); else LBPF_WG(3, 64); }
+    else { if (cot == 32) LBPF_WG(1, 32); else LBPF_WG(1, 64); }
+#undef LBPF_WG
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long nw = (long long)Cout * taps * Cin;
-    hipLaunchKernelGGL(sum_chunks_kernel, ew_grid(nw), dim3(256), 0, st, part, nw, nchunks, dw);
-    hipLaunchKernelGGL(sum_chunks_kernel, ew_grid(Cout), dim3(256), 0, st, bpart, (long long)Cout, nchunks, db);
+    hipLaunchKernelGGL(sum_chunks_kernel, row_grid((nw + 15) / 16), dim3(256), 0, st, part, nw, chunks, dw);
+    hipLaunchKernelGGL(sum_chunks_kernel, row_grid((Cout + 15) / 16), dim3(256), 0, st, bpart, (long long)Cout, chunks, db);
     return hipGetLastError();
 }
-
-static dim3 row_grid(long long rows) { return dim3((unsigned)(rows < 65536 ? (rows < 1 ? 1 : rows) : 65536)); }
 
 hipError_t unet_avgpool(const bf16* x, int xs, int xo, bf16* y, int ys, int yo, int C, int N, int H, int W, hipStream_t st) {
     hipLaunchKernelGGL(avgpool_kernel, row_grid((long long)N * H / 2), dim3(256), 0, st, x, xs, xo, y, ys, yo, C, N, H, W);
@@ -644,7 +713,7 @@ hipError_t unet_upsample_bwd(const bf16* dy, int dys, int dyo, bf16* dx, int dxs
     return hipGetLastError();
 }
 hipError_t unet_relu_bwd(bf16* g, int gs, int go, const bf16* a, int as, int ao, int C, long long npix, hipStream_t st) {
-    hipLaunchKernelGGL(relu_bwd_kernel, row_grid((npix + 1023) / 1024), dim3(256), 0, st, g, gs, go, a, as, ao, C, npix);
+    hipLaunchKernelGGL(relu_bwd_kernel, row_grid((npix + 63) / 64), dim3(256), 0, st, g, gs, go, a, as, ao, C, npix);
     return hipGetLastError();
 }
 hipError_t unet_pack_input(const float* in, int cin, bf16* x0, long long npix, hipStream_t st) {

@@ -46,8 +46,11 @@ hipError_t unet_conv_fwd(int ks, bool relu, const bf16* x, int xs, int xo, int C
                          int H, int W, hipStream_t st);
 hipError_t unet_mfma_probe(int k32, const bf16* A, const bf16* B, float* D, hipStream_t st);
 hipError_t unet_flip_weights(const bf16* w, bf16* wt, int Cout, int Cin, int taps, hipStream_t st);
+// weight and bias gradients of a convolution (dw [Cout][KS*KS][Cin], db [Cout], FP32), from
+// deterministic per-chunk partials: part and bpart hold at least max_chunks * Cout * KS*KS * Cin
+// and max_chunks * Cout floats
 hipError_t unet_conv_wgrad(int ks, const bf16* dy, int dys, int dyo, int Cout, const bf16* x, int xs,
-                           int xo, int Cin, int N, int H, int W, int nchunks, float* part,
+                           int xo, int Cin, int N, int H, int W, int max_chunks, float* part,
                            float* bpart, float* dw, float* db, hipStream_t st);
 // C channels (C, strides, offsets multiples of 8)
 hipError_t unet_avgpool(const bf16* x, int xs, int xo, bf16* y, int ys, int yo, int C, int N, int H, int W, hipStream_t st);
