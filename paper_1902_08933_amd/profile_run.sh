@@ -7,6 +7,21 @@
 # Raw rocprofv3 output goes to gpurun_out/prof_<workload>/; PROFILE_OUT overrides profiles/.
 set -o pipefail
 W=${1:-spinodal1024}
+if [ "$W" = "unet1024" ]; then
+    # surrogate forward pass at 1024^2: kernel trace of 1 + 10 forwards (214 GFLOP each)
+    OUT=gpurun_out/prof_unet1024
+    PROF=${PROFILE_OUT:-profiles}
+    mkdir -p "$OUT" "$PROF"
+    export TMPDIR=/tmp
+    CMD="python3 -m paper_1902_08933_amd.profile_unet --h 1024 --w 1024 --reps 10"
+    echo "profile: kernel trace unet1024" && \
+    timeout -k 10 180 rocprofv3 --kernel-trace --stats -d "$OUT/trace" -o run -- $CMD > "$OUT/trace.log" 2>&1 && \
+    python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --iterations 11 \
+        --flop "$(python3 -m paper_1902_08933_amd.profile_unet --h 1024 --w 1024 --flop-only)" \
+        --command "bash paper_1902_08933_amd/profile_run.sh unet1024  (rocprofv3 --kernel-trace --stats -- $CMD)" \
+        --out "$PROF/unet_forward_1024_trace.txt"
+    exit $?
+fi
 N=${W#spinodal}
 CELLS=$((N * N))
 OUT=gpurun_out/prof_$W

@@ -12,6 +12,16 @@ import numpy as np
 from . import lbpf
 
 
+def forward_flop(n, h, w, base=32):
+    """FLOPs (2 per multiply-add) of one forward pass of the network at n x h x w: per layer,
+    pixels at its level x Cout x KS^2 x Cin (layer table of the library's network)."""
+    c = [base << l for l in range(4)]
+    layers = [(0, 16, c[0], 3), (1, c[0], c[1], 3), (2, c[1], c[2], 3), (3, c[2], c[3], 3),
+              (2, c[3] + c[2], c[2], 3), (1, c[2] + c[1], c[1], 3), (0, c[1] + c[0], c[0], 3),
+              (0, c[0], 16, 1)]
+    return sum(2 * n * (h >> lev) * (w >> lev) * co * ks * ks * ci for lev, ci, co, ks in layers)
+
+
 def main():
     import torch
     ap = argparse.ArgumentParser()
@@ -20,7 +30,12 @@ def main():
     ap.add_argument("--batch", type=int, default=1)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--train", action="store_true")
+    ap.add_argument("--flop-only", action="store_true",
+                    help="print the multiply-add FLOPs of one forward pass and exit (no GPU)")
     a = ap.parse_args()
+    if a.flop_only:
+        print(forward_flop(a.batch, a.h, a.w))
+        return 0
     net = lbpf.UNet(max_batch=a.batch, max_h=a.h, max_w=a.w, train=a.train, seed=1)
     g = torch.Generator().manual_seed(0)
     x = (torch.randn(a.batch, a.h, a.w, 4, generator=g) * 0.1).cuda()

@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--kernel", default="strip_kernel")
     ap.add_argument("--cells", type=int, default=0)
     ap.add_argument("--alg-bytes-per-cell", type=float, default=168.0)
+    ap.add_argument("--iterations", type=int, default=0,
+                    help="with --trace: report the summed kernel time per iteration of the program")
+    ap.add_argument("--flop", type=float, default=0.0, help="with --iterations: FLOP per iteration")
     ap.add_argument("--command", default="")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
@@ -80,6 +83,12 @@ def main():
         lines.append(f"{'calls':>6} {'total_us':>12} {'avg_us':>10} {'median_us':>10}  kernel")
         for k, (n, tot, avg, med) in sorted(trace_stats(a.trace).items(), key=lambda kv: -kv[1][1]):
             lines.append(f"{n:6d} {tot / 1e3:12.1f} {avg / 1e3:10.3f} {med / 1e3:10.3f}  {k[:110]}")
+        if a.iterations:
+            total = sum(v[1] for v in trace_stats(a.trace).values()) / a.iterations
+            lines.append(f"total_kernel_us_per_iteration: {total / 1e3:.3f}")
+            if a.flop:
+                lines.append(f"flop_per_iteration: {a.flop:.6e}")
+                lines.append(f"TFLOPs_at_total: {a.flop / (total * 1e-9) / 1e12:.1f}")
         if a.cells:
             name, (n, tot, avg, med) = pick(trace_stats(a.trace), a.kernel)
             gbs = a.alg_bytes_per_cell * a.cells / (avg * 1e-9) / 1e9
