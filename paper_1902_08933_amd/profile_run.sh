@@ -16,7 +16,7 @@ if [ "$W" = "unet1024" ]; then
     CMD="python3 -m paper_1902_08933_amd.profile_unet --h 1024 --w 1024 --reps 10"
     echo "profile: kernel trace unet1024" && \
     timeout -k 10 180 rocprofv3 --kernel-trace --stats -d "$OUT/trace" -o run -- $CMD > "$OUT/trace.log" 2>&1 && \
-    python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --iterations 11 \
+    python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --iterations 11 --sources unet \
         --flop "$(python3 -m paper_1902_08933_amd.profile_unet --h 1024 --w 1024 --flop-only)" \
         --command "bash paper_1902_08933_amd/profile_run.sh unet1024  (rocprofv3 --kernel-trace --stats -- $CMD)" \
         --out "$PROF/unet_forward_1024_trace.txt"

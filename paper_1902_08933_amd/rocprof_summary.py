@@ -16,13 +16,16 @@ import sqlite3
 import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_FILES = [os.path.join(HERE, "csrc", n) for n in ("lbpf_kernels.hip", "lbpf_cell.hpp",
-                                                        "lbpf_model.hpp")]
+KERNEL_FILES = {
+    "step": [os.path.join(HERE, "csrc", n) for n in ("lbpf_kernels.hip", "lbpf_cell.hpp", "lbpf_model.hpp")],
+    "unet": [os.path.join(HERE, "csrc", n) for n in ("lbpf_unet_kernels.hip", "lbpf_unet_ops.hpp",
+                                                     "lbpf_unet.cpp")],
+}
 
 
-def kernel_source_hash():
+def kernel_source_hash(which="step"):
     h = hashlib.sha256()
-    for p in KERNEL_FILES:
+    for p in KERNEL_FILES[which]:
         with open(p, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -70,11 +73,13 @@ def main():
     ap.add_argument("--iterations", type=int, default=0,
                     help="with --trace: report the summed kernel time per iteration of the program")
     ap.add_argument("--flop", type=float, default=0.0, help="with --iterations: FLOP per iteration")
+    ap.add_argument("--sources", default="step", choices=sorted(KERNEL_FILES),
+                    help="which kernel sources the summary's hash covers")
     ap.add_argument("--command", default="")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     lines = [f"# rocprofv3 summary", f"command: {a.command}",
-             f"kernel_source_sha256_16: {kernel_source_hash()}"]
+             f"kernel_sources: {a.sources}", f"kernel_source_sha256_16: {kernel_source_hash(a.sources)}"]
     if a.cells:
         lines.append(f"cells: {a.cells}")
     if a.trace:
