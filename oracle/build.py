@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "lbpf_oracle.c")
+SRCS = [os.path.join(HERE, "lbpf_oracle.c"), os.path.join(HERE, "sp_oracle.c")]
 LIB = os.path.join(HERE, "liblbpf_oracle.so")
 
 
@@ -12,7 +12,7 @@ def build(verbose=False):
     # -O2 keeps strict IEEE double semantics: no -ffast-math, no FMA contraction, so that
     # the oracle evaluates every formula in the order it is written.
     cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
-           "-o", LIB + ".tmp", SRC, "-lm"]
+           "-o", LIB + ".tmp"] + SRCS + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session", autouse=True)
 def _built_oracle():
-    """Build the CPU oracle if it is not built yet (it is test infrastructure)."""
+    """Build the CPU oracle if it is not built or older than its sources (test infrastructure)."""
     from oracle import build as ob
-    if not os.path.exists(ob.LIB):
+    if not os.path.exists(ob.LIB) or os.path.getmtime(ob.LIB) < max(os.path.getmtime(s) for s in ob.SRCS):
         ob.build()

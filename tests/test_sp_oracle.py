@@ -1,0 +1,153 @@
+"""Pins of the FP64 CPU oracle of the generalized single-phase model with a mass source
+(Sec. 2, Remarks 1 and 3): moment identities fixed by the lattice, exact global balances of
+mass and momentum, the S = 0 limit (Guo et al. forced BGK) and the analytic steady flow driven
+by a sinusoidal source, whose pressure carries the bulk viscosity set through Q."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sp
+
+CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)
+CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)
+CS2 = 1.0 / 3.0
+RNG = np.random.default_rng(5)
+
+
+def moments(f):
+    m0 = f.sum()
+    m1 = np.array([(CX * f).sum(), (CY * f).sum()])
+    m2 = np.array([[(CX * CX * f).sum(), (CX * CY * f).sum()], [(CY * CX * f).sum(), (CY * CY * f).sum()]])
+    return m0, m1, m2
+
+
+def test_equilibria_moments():
+    for _ in range(5):
+        rho, p, ux, uy = 1 + 0.1 * RNG.normal(), 0.01 * RNG.normal(), 0.05 * RNG.normal(), 0.05 * RNG.normal()
+        u = np.array([ux, uy])
+        # eq. (29bb): the moments of a nearly incompressible equilibrium
+        m0, m1, m2 = moments(sp.equilibrium_ni(rho, ux, uy))
+        assert abs(m0 - rho) < 1e-14
+        np.testing.assert_allclose(m1, rho * u, atol=1e-15)
+        np.testing.assert_allclose(m2, rho * CS2 * np.eye(2) + rho * np.outer(u, u), atol=1e-15)
+        # eq. (25) with rho = 1: sum = rho_0, first moment u, second p I + uu
+        m0, m1, m2 = moments(sp.equilibrium_inc(1.0, p, ux, uy))
+        assert abs(m0 - 1.0) < 1e-14
+        np.testing.assert_allclose(m1, u, atol=1e-15)
+        np.testing.assert_allclose(m2, p * np.eye(2) + np.outer(u, u), atol=1e-15)
+
+
+def test_force_term_moments():
+    # eq. (27): sum G = S, sum c G = F, sum c c G = c_s^2 S I + A by the isotropy of the lattice
+    for _ in range(5):
+        S, Fx, Fy = RNG.normal(size=3) * 1e-3
+        axx, axy, ayy = RNG.normal(size=3) * 1e-3
+        m0, m1, m2 = moments(sp.force_distribution(S, Fx, Fy, axx, axy, ayy))
+        assert abs(m0 - S) < 1e-18
+        np.testing.assert_allclose(m1, [Fx, Fy], atol=1e-18)
+        np.testing.assert_allclose(m2, CS2 * S * np.eye(2) + np.array([[axx, axy], [axy, ayy]]), atol=1e-18)
+
+
+def test_pressure_inverts_incompressible_equilibrium():
+    # eq. (28) applied to g^eq(p, u) with no source and no force returns p
+    for _ in range(5):
+        p, ux, uy = 0.01 * RNG.normal(), 0.05 * RNG.normal(), 0.05 * RNG.normal()
+        g = sp.equilibrium_inc(1.0, p, ux, uy)
+        assert abs(sp.pressure_inc(g, 0.0, ux, uy, 0.8, 0.0) - p) < 1e-16
+
+
+def source_cfg(model, nx, ny, **kw):
+    return dict(dict(nx=nx, ny=ny, model=model, nu=1.0 / 6.0, xi=0.0, full=True), **kw)
+
+
+@pytest.mark.parametrize("model", ["nearly_incompressible", "incompressible"])
+def test_global_mass_and_momentum_balance(model):
+    # per step: total momentum sum(rho u) grows by sum F exactly (both models); in the nearly
+    # incompressible model total rho~ = sum(g) + S/2 grows by sum S exactly (eq. 27aa)
+    nx, ny = 12, 10
+    S = 1e-3 * RNG.normal(size=(ny, nx)) + 2e-4
+    Fx = 1e-4 * RNG.normal(size=(ny, nx)) + 1e-5
+    Fy = 1e-4 * RNG.normal(size=(ny, nx))
+    a0 = (1.0 + 1e-3 * RNG.normal(size=(ny, nx))) if model == "nearly_incompressible" else 1e-3 * RNG.normal(size=(ny, nx))
+    o = sp.SpOracle(source_cfg(model, nx, ny)).init(a0, 1e-3 * RNG.normal(size=(ny, nx)),
+                                                     1e-3 * RNG.normal(size=(ny, nx)), S, Fx, Fy)
+    for _ in range(20):
+        rho = o.read("rho")
+        mom = np.array([(rho * o.read("ux")).sum(), (rho * o.read("uy")).sum()])
+        m = o.sum_rho_tilde()
+        o.step(1)
+        rho = o.read("rho")
+        mom2 = np.array([(rho * o.read("ux")).sum(), (rho * o.read("uy")).sum()])
+        np.testing.assert_allclose(mom2 - mom, [Fx.sum(), Fy.sum()], rtol=1e-10, atol=1e-15)
+        if model == "nearly_incompressible":
+            assert abs(o.sum_rho_tilde() - m - S.sum()) < 1e-12
+
+
+def poiseuille(model, ny, tau, G=1e-6):
+    nu = (tau - 0.5) / 3.0
+    cfg = dict(nx=3, ny=ny, model=model, nu=nu, bc="walls_y", full=True)
+    o = sp.SpOracle(cfg).init(Fx=np.full((ny, 3), G))
+    o.step(int(25 * ny * ny / nu / math.pi ** 2))
+    u = o.read("ux")[:, 0]
+    h = ny / 2.0
+    y = np.arange(ny) + 0.5 - h
+    ua = G / (2 * nu) * (h * h - y * y)
+    return np.abs(u - ua).max() / ua.max()
+
+
+@pytest.mark.parametrize("model", ["nearly_incompressible", "incompressible"])
+def test_zero_source_limit_is_forced_bgk(model):
+    # S = 0: both reductions are the forced BGK scheme of Guo et al.; with halfway bounce-back
+    # the body-force channel flow is exact when (tau - 1/2)^2 = 3/16, second order otherwise
+    assert poiseuille(model, 8, 0.5 + math.sqrt(3) / 4) < 1e-9
+    e8, e16 = poiseuille(model, 8, 1.0), poiseuille(model, 16, 1.0)
+    assert 3.5 < e8 / e16 < 4.5
+
+
+def source_flow(model, nx, xi=0.0, S0=1e-4, full=True, steps=None):
+    """Steady flow driven by S = S0 sin(kx) on a periodic nx x 3 grid. Continuity gives
+    u_x = -(S0/k) cos(kx) (times 1/rho in the nearly incompressible model); the x momentum
+    balance d_x(rho u^2 + p) = d_x((mu + xi) d_x u) gives the pressure up to a constant:
+    p = -rho u^2 + (nu + xi) S0 sin(kx), i.e. a sin(kx) component of amplitude (nu + xi) S0."""
+    ny = 3
+    k = 2 * math.pi / nx
+    x = np.arange(nx)
+    S = np.tile(S0 * np.sin(k * x), (ny, 1))
+    o = sp.SpOracle(source_cfg(model, nx, ny, xi=xi, full=full)).init(S=S)
+    nu = 1.0 / 6.0
+    o.step(steps or int(36 / ((nu + xi) * k * k)))  # ~36 slowest viscous e-folding times
+    rho, u, p = o.read("rho")[1], o.read("ux")[1], o.read("p")[1]
+    mass_flux = rho * u
+    flux_err = np.abs(mass_flux - (-(S0 / k) * np.cos(k * x))).max() / (S0 / k)
+    sin_amp = 2 * (p * np.sin(k * x)).mean()
+    return flux_err, sin_amp, o
+
+
+@pytest.mark.parametrize("model", ["nearly_incompressible", "incompressible"])
+def test_source_flow_velocity_second_order(model):
+    e16, _, _ = source_flow(model, 16)
+    e32, _, _ = source_flow(model, 32)
+    print(f"{model}: mass-flux error {e16:.3e} (nx 16), {e32:.3e} (nx 32)")
+    assert e32 < 5e-3
+    assert 3.0 < e16 / e32 < 5.0
+
+
+@pytest.mark.parametrize("model", ["nearly_incompressible", "incompressible"])
+@pytest.mark.parametrize("xi", [0.0, 0.1])
+def test_source_flow_pressure_carries_bulk_viscosity(model, xi):
+    # the sin(kx) part of the pressure is (nu + xi) S0: the bulk viscosity xi enters only
+    # through Q of the force term, so this pins Q (div u) I of eq. (27)
+    S0, nu = 1e-4, 1.0 / 6.0
+    _, amp, _ = source_flow(model, 32, xi=xi, S0=S0)
+    print(f"{model} xi {xi}: sin amplitude {amp:.6e} vs {(nu + xi) * S0:.6e}")
+    assert abs(amp / ((nu + xi) * S0) - 1) < 0.02
+
+
+def test_incompressible_remark_and_full_forms_agree_at_low_mach():
+    # the terms Remark 3 drops (d_t p, grad p in F~, u u S) are higher order in Ma: at a small
+    # source both forms give the same steady flow
+    e_full, a_full, of = source_flow("incompressible", 32, full=True)
+    e_rem, a_rem, orm = source_flow("incompressible", 32, full=False)
+    np.testing.assert_allclose(of.read("ux"), orm.read("ux"), rtol=0, atol=1e-3 * 1e-4 * 32 / (2 * math.pi))
+    assert abs(a_full / a_rem - 1) < 0.01
