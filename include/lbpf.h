@@ -288,6 +288,59 @@ lbpf_status lbpf_fields_to_nhwc(lbpf_ctx* ctx, float* dst, const float* shift, c
 lbpf_status lbpf_init_from_nhwc(lbpf_ctx* ctx, const float* src, const float* shift,
                                 const float* scale, int64_t step);
 
+/* ------------------------------------------------------------------------------------------
+ * Generalized single-phase model with a mass source (Sec. 2): the evolution eq. (24), the
+ * equilibrium eq. (25) and the force term eq. (27), with the velocity eq. (27a), in the two
+ * reductions the paper spells out:
+ *   LBPF_SP_NEARLY_INCOMPRESSIBLE  Remark 1: rho~ = rho = sum_i g_i + S/2 (eq. 27aa),
+ *       p = rho c_s^2, g_i^eq = rho [w_i + s_i(u)] (eq. 29bb); force bracket
+ *       uF + Fu - uu S + Q (div u) I, with div u of the previous step's velocity (eq. 30a).
+ *   LBPF_SP_INCOMPRESSIBLE  Remark 3: rho~ = rho0, rho = 1, g^eq of eq. (25), p by eq. (28)
+ *       (or eq. 29); force bracket uF + Fu + Q S I. With `full`, the terms of eq. (27) that
+ *       Remark 3 neglects are kept: -grad p^{n-1} (eq. 30a) in F~, -uu S, and d_t p I with
+ *       d_t p = p^n - p^{n-1}, for which eq. (28) is solved in closed form (G_0 is affine in it).
+ * Q = (2/d) rho c_s^2 - xi / (tau_g - 1/2), tau_g = nu / c_s^2 + 1/2. S(x) and F(x) are fields
+ * given at lbpf_sp_init and constant in time. Same conventions as the two-phase solver: the
+ * caller owns the device workspace and the stream; calls are asynchronous unless stated.
+ * ------------------------------------------------------------------------------------------ */
+typedef enum { LBPF_SP_NEARLY_INCOMPRESSIBLE = 0, LBPF_SP_INCOMPRESSIBLE = 1 } lbpf_sp_model;
+typedef enum { LBPF_SP_RHO = 0, LBPF_SP_UX = 1, LBPF_SP_UY = 2, LBPF_SP_P = 3 } lbpf_sp_field;
+
+typedef struct lbpf_sp_params {
+    int32_t nx, ny;   /* same limits as lbpf_params */
+    int32_t model;    /* lbpf_sp_model */
+    int32_t pscheme;  /* incompressible model: 0 eq. (28), 1 eq. (29) */
+    int32_t full;     /* 1: force term as printed (see above); 0: the Remarks' reduced forms
+                       * (nearly incompressible: -uu S dropped) */
+    int32_t bc;       /* lbpf_bc */
+    double nu;        /* kinematic viscosity (> 0) */
+    double xi;        /* bulk viscosity (0: Stokes hypothesis) */
+    double rho0;      /* incompressible model: the constant rho~ */
+} lbpf_sp_params;
+
+typedef struct lbpf_sp lbpf_sp;
+
+lbpf_status lbpf_sp_workspace_size(const lbpf_sp_params* params, size_t* bytes);
+lbpf_status lbpf_sp_create(const lbpf_sp_params* params, void* workspace, size_t workspace_bytes,
+                           void* hip_stream, lbpf_sp** out);
+/* Initial state (device arrays [ny][nx] FP32, NULL = default): a0 the density (nearly
+ * incompressible, default 1) or the pressure (incompressible, default 0), u0, the source S and
+ * the force (F_x, F_y) (default 0). Populations start at the equilibrium of the initial fields;
+ * the histories (previous velocity, previous pressure) start at the initial fields. */
+lbpf_status lbpf_sp_init(lbpf_sp* sp, const float* a0, const float* ux0, const float* uy0,
+                         const float* S, const float* Fx, const float* Fy);
+lbpf_status lbpf_sp_step(lbpf_sp* sp, int64_t nsteps);
+/* rho (eq. 27aa; 1 in the incompressible model), u (eq. 27a) or p (rho c_s^2, or eq. 28/29)
+ * of the current state into dst (device [ny][nx] FP32). Async. */
+lbpf_status lbpf_sp_read(lbpf_sp* sp, int32_t field, float* dst);
+/* FP64 sums over the grid of rho~ = sum_i g_i + S/2, rho u_x and rho u_y into host out[3]
+ * (deterministic; synchronizes the stream). Per step the scheme changes them by exactly
+ * sum S (nearly incompressible model) and sum F. */
+lbpf_status lbpf_sp_sums(lbpf_sp* sp, double* out3);
+int64_t lbpf_sp_step_count(const lbpf_sp* sp);
+lbpf_status lbpf_sp_destroy(lbpf_sp* sp);
+const char* lbpf_sp_last_error(const lbpf_sp* sp);
+
 #ifdef __cplusplus
 }
 #endif

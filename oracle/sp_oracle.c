@@ -24,8 +24,11 @@
  *            terms of eq. (27) that Remark 3 neglects: d_t(p - rho_0 c_s^2) I, the -grad p
  *            part of F~ = F - grad(p - rho c_s^2) and -uu S~ (S~ = S since rho and rho~ are
  *            constant); full = 0 is Remark 3's force term.
- *            d_t p and grad p use the previous steps' pressures (p^{n-1} - p^{n-2} and
- *            eq. (30a) of p^{n-1}); before the first step both are the initial p.
+ *            grad p is eq. (30a) of the previous step's pressure (the initial p before the
+ *            first step). d_t p is the backward difference p^n - p^{n-1} at the current
+ *            level: G_0 is affine in it, so eq. (28) is solved for p^n in closed form. (A
+ *            lagged difference p^{n-1} - p^{n-2} feeds back into eq. (28) and grows without
+ *            bound; the current-level difference is stable.)
  *   fields   S(x) and F(x) are given per node and constant in time.
  *   init     g_i = g_i^eq of the initial fields.
  *   walls    halfway bounce-back below row 0 and above row ny-1 (bc 1); stencil ghosts mirror
@@ -63,7 +66,7 @@ typedef struct {
     double *g, *gs;              /* [NQ][ny][nx] populations after streaming / after collision */
     double *S, *Fx, *Fy;         /* source and force fields */
     double *ux_prev, *uy_prev;   /* model 0: velocity of the previous step (div u reading) */
-    double *p_prev, *p_prev2;    /* model 1: pressures of the two previous steps */
+    double *p_prev;              /* model 1: pressure of the previous step */
     double *rho, *ux, *uy, *p, *G; /* per-step work arrays; G is [NQ][ny][nx] */
     double *w1, *w2, *w3;        /* stencil scratch */
 } sp_state;
@@ -167,7 +170,7 @@ sp_state* sp_create(const sp_params* P) {
     s->g = calloc(SP_NQ * n, sizeof(double));
     s->gs = calloc(SP_NQ * n, sizeof(double));
     s->G = calloc(SP_NQ * n, sizeof(double));
-    double** one[] = {&s->S, &s->Fx, &s->Fy, &s->ux_prev, &s->uy_prev, &s->p_prev, &s->p_prev2,
+    double** one[] = {&s->S, &s->Fx, &s->Fy, &s->ux_prev, &s->uy_prev, &s->p_prev,
                       &s->rho, &s->ux, &s->uy, &s->p, &s->w1, &s->w2, &s->w3};
     for (size_t k = 0; k < sizeof(one) / sizeof(one[0]); ++k) *one[k] = calloc(n, sizeof(double));
     return s;
@@ -176,7 +179,7 @@ sp_state* sp_create(const sp_params* P) {
 void sp_destroy(sp_state* s) {
     if (!s) return;
     double* all[] = {s->g, s->gs, s->G, s->S, s->Fx, s->Fy, s->ux_prev, s->uy_prev, s->p_prev,
-                     s->p_prev2, s->rho, s->ux, s->uy, s->p, s->w1, s->w2, s->w3};
+                     s->rho, s->ux, s->uy, s->p, s->w1, s->w2, s->w3};
     for (size_t k = 0; k < sizeof(all) / sizeof(all[0]); ++k) free(all[k]);
     free(s);
 }
@@ -198,7 +201,7 @@ void sp_init(sp_state* s, const double* a0, const double* ux0, const double* uy0
         s->Fy[k] = Fy ? Fy[k] : 0.0;
         s->ux_prev[k] = ux;
         s->uy_prev[k] = uy;
-        s->p_prev[k] = s->p_prev2[k] = (s->P.model == 1) ? a : 0.0;
+        s->p_prev[k] = (s->P.model == 1) ? a : 0.0;
     }
     s->step = 0;
 }
@@ -248,18 +251,32 @@ static void sp_macroscopics(sp_state* s) {
             double S = s->S[k], Fx = s->Fx[k], Fy = s->Fy[k];
             double ux = mx + 0.5 * Fx, uy = my + 0.5 * Fy; /* eq. (27a), rho = 1 */
             double Q = 2.0 / SP_DIM * SP_CS2 - P->xi / (tau - 0.5);
-            double axx, axy, ayy, G[SP_NQ];
-            if (P->full)
-                sp_bracket(s->p_prev[k] - s->p_prev2[k], ux, uy, Fx - s->w1[k], Fy - s->w2[k], S, Q, S,
-                           &axx, &axy, &ayy);
-            else
+            double axx, axy, ayy, G[SP_NQ], p;
+            if (P->full) {
+                /* bracket without its d_t p I part, then eq. (28) with d_t p = p - p^{n-1}:
+                 * the force term at i = 0 is G_0 = G_0' + w_0 (0 - c_s^2 I) : (d_t p I) / (2 c_s^4)
+                 * = G_0' - w_0 d d_t p / (2 c_s^2); eq. (28), p = a [B + (tau - 1/2) G_0] with
+                 * a = c_s^2 / (1 - w_0), is then p = X - c (p - p^{n-1}), solved for p */
+                sp_bracket(0.0, ux, uy, Fx - s->w1[k], Fy - s->w2[k], S, Q, S, &axx, &axy, &ayy);
+                sp_force_distribution(S, Fx, Fy, axx, axy, ayy, G);
+                double X = sp_pressure_inc(g, S, ux, uy, tau, G[0], P->pscheme);
+                double c = (P->pscheme == 0)
+                               ? SP_CS2 / (1.0 - SP_W[0]) * (tau - 0.5) * SP_W[0] * SP_DIM / (2.0 * SP_CS2)
+                               : 0.0;
+                p = (X + c * s->p_prev[k]) / (1.0 + c);
+                double dtp = p - s->p_prev[k];
+                sp_bracket(dtp, ux, uy, Fx - s->w1[k], Fy - s->w2[k], S, Q, S, &axx, &axy, &ayy);
+                sp_force_distribution(S, Fx, Fy, axx, axy, ayy, G);
+            } else {
                 sp_bracket(0.0, ux, uy, Fx, Fy, 0.0, Q, S, &axx, &axy, &ayy);
-            sp_force_distribution(S, Fx, Fy, axx, axy, ayy, G);
+                sp_force_distribution(S, Fx, Fy, axx, axy, ayy, G);
+                p = sp_pressure_inc(g, S, ux, uy, tau, G[0], P->pscheme);
+            }
             for (int i = 0; i < SP_NQ; ++i) s->G[i * n + k] = G[i];
             s->rho[k] = 1.0;
             s->ux[k] = ux;
             s->uy[k] = uy;
-            s->p[k] = sp_pressure_inc(g, S, ux, uy, tau, G[0], P->pscheme);
+            s->p[k] = p;
         }
     }
 }
@@ -302,7 +319,6 @@ static void sp_one_step(sp_state* s) {
     for (size_t k = 0; k < n; ++k) {
         s->ux_prev[k] = s->ux[k];
         s->uy_prev[k] = s->uy[k];
-        s->p_prev2[k] = s->p_prev[k];
         s->p_prev[k] = s->p[k];
     }
     s->step += 1;

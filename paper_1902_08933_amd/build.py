@@ -20,7 +20,7 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang
                 "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 
-SOURCES = ["lbpf_kernels.hip", "lbpf_api.cpp", "lbpf_unet_kernels.hip", "lbpf_unet.cpp"]
+SOURCES = ["lbpf_kernels.hip", "lbpf_api.cpp", "lbpf_unet_kernels.hip", "lbpf_unet.cpp", "lbpf_sp.hip"]
 
 
 def _run(cmd, verbose):

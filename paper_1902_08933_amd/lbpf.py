@@ -557,3 +557,112 @@ class UNet:
                                               ctypes.c_void_p(target.data_ptr()), n, h, w, float(lr),
                                               ctypes.byref(loss)))
         return loss.value
+
+
+# ---- generalized single-phase model with a mass source (lbpf_sp_* of include/lbpf.h) --------
+
+class SpParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("model", ctypes.c_int32),
+                ("pscheme", ctypes.c_int32), ("full", ctypes.c_int32), ("bc", ctypes.c_int32),
+                ("nu", ctypes.c_double), ("xi", ctypes.c_double), ("rho0", ctypes.c_double)]
+
+
+SP_MODELS = {"nearly_incompressible": 0, "incompressible": 1}
+SP_FIELDS = {"rho": 0, "ux": 1, "uy": 2, "p": 3}
+SIGNATURES.update({
+    "lbpf_sp_workspace_size": (_S, [ctypes.POINTER(SpParams), ctypes.POINTER(ctypes.c_size_t)]),
+    "lbpf_sp_create": (_S, [ctypes.POINTER(SpParams), _V, ctypes.c_size_t, _V, ctypes.POINTER(_V)]),
+    "lbpf_sp_init": (_S, [_V, _V, _V, _V, _V, _V, _V]),
+    "lbpf_sp_step": (_S, [_V, ctypes.c_int64]),
+    "lbpf_sp_read": (_S, [_V, ctypes.c_int32, _V]),
+    "lbpf_sp_sums": (_S, [_V, _PD]),
+    "lbpf_sp_step_count": (ctypes.c_int64, [_V]),
+    "lbpf_sp_destroy": (_S, [_V]),
+    "lbpf_sp_last_error": (ctypes.c_char_p, [_V]),
+})
+
+
+def make_sp_params(cfg):
+    """SpParams from a workload dict (keys as in workloads.single_phase_source)."""
+    p = SpParams()
+    p.nx, p.ny = int(cfg["nx"]), int(cfg["ny"])
+    p.model = SP_MODELS[cfg["model"]]
+    p.pscheme = {"eq28": 0, "eq29": 1}[cfg.get("pscheme", "eq28")]
+    p.full = int(bool(cfg.get("full", True)))
+    p.bc = BCS[cfg.get("bc", "periodic")]
+    p.nu = float(cfg["nu"])
+    p.xi = float(cfg.get("xi", 0.0))
+    p.rho0 = float(cfg.get("rho0", 1.0))
+    return p
+
+
+class SinglePhase:
+    """One simulation of the generalized single-phase model on one GPU: init (density or
+    pressure, velocity, source and force fields), step N, read rho/u/p, FP64 sums."""
+
+    def __init__(self, cfg, device="cuda"):
+        import torch
+        self.torch = torch
+        self.lib = library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lbpf solver runs only on the GPU")
+        self.device = torch.device(device)
+        self.cfg = dict(cfg)
+        self.params = make_sp_params(cfg)
+        self.nx, self.ny = self.params.nx, self.params.ny
+        nb = ctypes.c_size_t()
+        st = self.lib.lbpf_sp_workspace_size(ctypes.byref(self.params), ctypes.byref(nb))
+        if st != 0:
+            raise LbpfError(st, (self.lib.lbpf_sp_last_error(None) or b"").decode())
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        h = ctypes.c_void_p()
+        st = self.lib.lbpf_sp_create(ctypes.byref(self.params), ctypes.c_void_p(self.workspace.data_ptr()),
+                                     ctypes.c_size_t(nb.value), ctypes.c_void_p(stream), ctypes.byref(h))
+        if st != 0:
+            raise LbpfError(st, (self.lib.lbpf_sp_last_error(None) or b"").decode())
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.lib.lbpf_sp_destroy(h)
+            self._h = None
+
+    def _c(self, st):
+        if st != 0:
+            raise LbpfError(st, (self.lib.lbpf_sp_last_error(self._h) or b"").decode())
+
+    def _as_field(self, a):
+        if a is None:
+            return None
+        t = self.torch.as_tensor(a, dtype=self.torch.float32, device=self.device).contiguous()
+        if tuple(t.shape) != (self.ny, self.nx):
+            raise ValueError(f"field shape {tuple(t.shape)} != {(self.ny, self.nx)}")
+        return t
+
+    def init(self, a0=None, ux=None, uy=None, S=None, Fx=None, Fy=None):
+        ts = [self._as_field(a) for a in (a0, ux, uy, S, Fx, Fy)]
+        self._c(self.lib.lbpf_sp_init(self._h, *[ctypes.c_void_p(t.data_ptr()) if t is not None else None
+                                                  for t in ts]))
+        self.torch.cuda.current_stream(self.device).synchronize()  # the inputs may be temporaries
+        return self
+
+    def step(self, n=1):
+        self._c(self.lib.lbpf_sp_step(self._h, int(n)))
+        return self
+
+    def read(self, field, out=None):
+        t = out if out is not None else self.torch.empty((self.ny, self.nx), dtype=self.torch.float32,
+                                                          device=self.device)
+        self._c(self.lib.lbpf_sp_read(self._h, SP_FIELDS[field], ctypes.c_void_p(t.data_ptr())))
+        return t
+
+    def sums(self):
+        out = (ctypes.c_double * 3)()
+        self._c(self.lib.lbpf_sp_sums(self._h, out))
+        return dict(rho_tilde=out[0], mom_x=out[1], mom_y=out[2])
+
+    @property
+    def step_count(self):
+        return int(self.lib.lbpf_sp_step_count(self._h))

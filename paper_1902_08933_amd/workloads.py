@@ -175,3 +175,36 @@ def batch_instances(count=256, seed=0, side_min=64, side_max=512):
             phi = layered_phi(s, s, 4.0)
         out.append((cfg, phi))
     return out
+
+
+def single_phase_source(nx=1024, ny=1024, model="incompressible", S0=1e-4, F0=0.0, nu=1.0 / 6.0,
+                        xi=0.0, full=True, bc="periodic", pscheme="eq28", seed=None):
+    """Single-phase flow driven by a mass source (Sec. 2): S = S0 sin(2 pi x/nx) cos(2 pi y/ny),
+    a uniform force F0 in x, fluid at rest. With `seed`, the initial density (or pressure),
+    velocity, source and force also carry small seeded smooth perturbations (parity cases).
+    Returns (cfg, fields) with fields a dict of [ny, nx] float64 arrays (a0, ux, uy, S, Fx, Fy)."""
+    cfg = dict(nx=nx, ny=ny, model=model, nu=nu, xi=xi, full=full, bc=bc, pscheme=pscheme, rho0=1.0)
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    S = S0 * np.sin(2 * np.pi * x / nx) * np.cos(2 * np.pi * y / ny)
+    Fx = np.full((ny, nx), float(F0))
+    Fy = np.zeros((ny, nx))
+    a0 = np.ones((ny, nx)) if model == "nearly_incompressible" else np.zeros((ny, nx))
+    ux = np.zeros((ny, nx))
+    uy = np.zeros((ny, nx))
+    if seed is not None:
+        rng = np.random.default_rng(seed)
+
+        def smooth(amp):
+            # a few random Fourier modes of the grid
+            f = np.zeros((ny, nx))
+            for _ in range(4):
+                kx, ky = rng.integers(1, 4, size=2)
+                ph = rng.uniform(0, 2 * np.pi, size=2)
+                f += np.sin(2 * np.pi * kx * x / nx + ph[0]) * np.cos(2 * np.pi * ky * y / ny + ph[1])
+            return amp * f / 4
+
+        a0 = a0 + smooth(1e-3)
+        ux, uy = smooth(1e-3), smooth(1e-3)
+        S = S + smooth(S0) + 0.2 * S0
+        Fx, Fy = Fx + smooth(1e-5), smooth(1e-5)
+    return cfg, dict(a0=a0, ux=ux, uy=uy, S=S, Fx=Fx, Fy=Fy)
