@@ -215,6 +215,44 @@ def surrogate_bench(train_steps=2000, cycles=3):
             "speedup": round(sum(r["lb_ms"] for r in rows) / sum(r["hybrid_ms"] for r in rows), 2)}
 
 
+# algorithmic bytes per node update of the single-phase step (FP32 values read + written):
+# incompressible with the full force term: g_0..8, S, F_x, F_y, p^{n-1} read; g, p^n written;
+# nearly incompressible: g, S, F, u^{n-1} read; g, u^n written
+SP_BYTES = {("incompressible", True): 4 * (13 + 10), ("incompressible", False): 4 * (12 + 9),
+            ("nearly_incompressible", True): 4 * (14 + 11), ("nearly_incompressible", False): 4 * (14 + 11)}
+
+
+def single_phase_bench(n=1024, steps=2000, warmup=100):
+    """The generalized single-phase model with a mass source (Sec. 2) on an n x n periodic grid
+    driven by S = 1e-4 sin(2 pi x/n) cos(2 pi y/n) and a uniform force: MLUPS and the fraction of
+    the HBM roofline at the step's algorithmic bytes."""
+    import numpy as np
+    import torch
+    from paper_1902_08933_amd import lbpf, workloads as W
+    out = {}
+    for model, full in (("incompressible", True), ("nearly_incompressible", True)):
+        cfg, f = W.single_phase_source(n, n, model=model, S0=1e-4, F0=1e-6, full=full)
+        sim = lbpf.SinglePhase(cfg).init(*(torch.from_numpy(f[k].astype(np.float32)).cuda()
+                                           for k in ("a0", "ux", "uy", "S", "Fx", "Fy")))
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        b = SP_BYTES[(model, full)]
+        gbs = b * n * n / (ms * 1e-3) / 1e9
+        sums = sim.sums()
+        out[model] = {"full_force_term": full, "ms_per_step": round(ms, 5),
+                      "MLUPS": round(n * n / (ms * 1e-3) / 1e6, 1), "bytes_per_node": b,
+                      "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                      "finite": bool(np.isfinite(sums["rho_tilde"]))}
+    out["workload"] = f"single-phase source flow {n}x{n} periodic, S0 1e-4, F 1e-6, nu 1/6"
+    return out
+
+
 def cpu_baseline(cfg, phi, steps):
     import numpy as np
     import oracle
@@ -238,6 +276,7 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-single-phase", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=80)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -301,6 +340,8 @@ def main():
         out["batched"] = batch_bench(args.batch_steps)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_bench()
+    if not args.no_single_phase:
+        out["single_phase"] = single_phase_bench()
     if not args.no_cpu_baseline:
         v, dt = cpu_baseline(cfg, phi, args.cpu_steps)
         out["cpu_baseline"] = {"value": round(v, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",

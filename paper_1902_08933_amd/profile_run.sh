@@ -7,6 +7,21 @@
 # Raw rocprofv3 output goes to gpurun_out/prof_<workload>/; PROFILE_OUT overrides profiles/.
 set -o pipefail
 W=${1:-spinodal1024}
+if [ "$W" = "sp1024" ]; then
+    # single-phase step with a mass source at 1024^2 (incompressible, full force term)
+    OUT=gpurun_out/prof_sp1024
+    PROF=${PROFILE_OUT:-profiles}
+    mkdir -p "$OUT" "$PROF"
+    export TMPDIR=/tmp
+    CMD="python3 -m paper_1902_08933_amd.profile_step --workload sp1024 --steps 100 --warmup 10"
+    echo "profile: kernel trace sp1024" && \
+    timeout -k 10 180 rocprofv3 --kernel-trace --stats -d "$OUT/trace" -o run -- $CMD > "$OUT/trace.log" 2>&1 && \
+    python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --cells 1048576 \
+        --kernel sp_step_kernel --alg-bytes-per-cell 92 --sources sp \
+        --command "bash paper_1902_08933_amd/profile_run.sh sp1024  (rocprofv3 --kernel-trace --stats -- $CMD)" \
+        --out "$PROF/sp_step_sp1024_trace.txt"
+    exit $?
+fi
 if [ "$W" = "unet1024" ]; then
     # surrogate forward pass at 1024^2: kernel trace of 1 + 10 forwards (214 GFLOP each)
     OUT=gpurun_out/prof_unet1024

@@ -25,6 +25,22 @@ def make(name, variant):
     raise SystemExit(f"unknown workload {name}")
 
 
+def run_sp(torch, n, steps, warmup):
+    """single-phase step with a mass source, incompressible, full force term"""
+    import numpy as np
+    cfg, f = workloads.single_phase_source(n, n, model="incompressible", S0=1e-4, F0=1e-6, full=True)
+    sim = lbpf.SinglePhase(cfg).init(*(torch.from_numpy(f[k].astype(np.float32)).cuda()
+                                       for k in ("a0", "ux", "uy", "S", "Fx", "Fy")))
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
 def run_steps(torch, cfg, phi, steps, warmup, tile):
     sim = lbpf.Simulation(cfg)
     if tile is not None:
@@ -73,6 +89,12 @@ def main():
                 print(f"probe {name} {a.copy_mib} MiB, {blocks} workgroups: {ms:.4f} ms, "
                       f"{moved * nbytes / ms / 1e6:.1f} GB/s", flush=True)
         return
+    if a.workload.startswith("sp"):
+        n = int(a.workload[2:])
+        ms = run_sp(torch, n, a.steps, a.warmup)
+        print(f"{a.workload}: {ms:.4f} ms/step, {n * n / (ms * 1e-3) / 1e6:.0f} MLUPS, "
+              f"{92 * n * n / (ms * 1e-3) / 1e9:.0f} GB/s", flush=True)
+        return 0
     cfg, phi = make(a.workload, a.variant)
     cells = cfg["nx"] * cfg["ny"]
     if a.autotune:

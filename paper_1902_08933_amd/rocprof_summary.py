@@ -20,6 +20,7 @@ KERNEL_FILES = {
     "step": [os.path.join(HERE, "csrc", n) for n in ("lbpf_kernels.hip", "lbpf_cell.hpp", "lbpf_model.hpp")],
     "unet": [os.path.join(HERE, "csrc", n) for n in ("lbpf_unet_kernels.hip", "lbpf_unet_ops.hpp",
                                                      "lbpf_unet.cpp")],
+    "sp": [os.path.join(HERE, "csrc", "lbpf_sp.hip")],
 }
 
 
