@@ -230,7 +230,10 @@ static lbpf_status forward(lbpf_unet* u, const float* in, int n, int h, int w, f
     const bool keep = pred == nullptr;
     auto W = [&](int i) { return u->wbf + L[i].woff; };
     auto B = [&](int i) { return u->w32 + L[i].boff; };
-    UCHK(unet_pack_input(in, u->cfg.in_ch, u->act[X0], np0, st));
+    // the first layer reads the FP32 input itself; the packed bf16 copy is needed only by the
+    // weight gradient of that layer (and for inputs of more than 4 fields)
+    const bool direct_in = !keep && u->cfg.in_ch <= 4;
+    if (!direct_in) UCHK(unet_pack_input(in, u->cfg.in_ch, u->act[X0], np0, st));
     // encoder: E_l goes into the second part of the concat buffer of its level, and its 2x2
     // average pool P_{l+1} (the next layer's input) is written by the same kernel
     auto enc = [&](int i, Buf xin, int cin, int sx, Buf out, int so, int oo, Buf pool, int cout,
@@ -238,6 +241,7 @@ static lbpf_status forward(lbpf_unet* u, const float* in, int n, int h, int w, f
         ConvArgs a{};
         a.x = u->act[xin]; a.xs = sx; a.xo = 0;
         a.Cin = cin; a.w = W(i); a.bias = B(i);
+        if (i == 0 && direct_in) { a.x = nullptr; a.xin = in; a.xin_c = u->cfg.in_ch; }
         a.y = u->act[out]; a.ys = so; a.yo = oo;
         if (pool != kNumBufs) { a.yp = u->act[pool]; a.yps = cout; a.ypo = 0; }
         a.Cout = cout; a.N = n; a.H = h >> lev; a.W = w >> lev;
@@ -264,6 +268,17 @@ static lbpf_status forward(lbpf_unet* u, const float* in, int n, int h, int w, f
     };
     if ((s = dec(4, E3, c[3], U2, su2, D2, c[2], 2))) return s;
     if ((s = dec(5, D2, c[2], U1, su1, D1, c[1], 1))) return s;
+    if (!keep && c[0] <= 32) {
+        // inference: D0 stays on chip; its workgroups apply the 1x1 head and write the prediction
+        ConvArgs a{};
+        a.x = u->act[U0]; a.xs = su0; a.xo = c[1];
+        a.xl = u->act[D1]; a.xls = c[1]; a.xlo = 0; a.Cl = c[1];
+        a.Cin = su0; a.w = W(6); a.bias = B(6);
+        a.hw = W(7); a.hb = B(7); a.res = in; a.pred = pred; a.rc = u->cfg.in_ch;
+        a.Cout = c[0]; a.N = n; a.H = h; a.W = w;
+        UCHK(unet_conv(3, true, a, st));
+        return LBPF_OK;
+    }
     if ((s = dec(6, D1, c[1], U0, su0, D0, c[0], 0))) return s;
     ConvArgs a{};
     a.x = u->act[D0]; a.xs = c[0]; a.xo = 0;

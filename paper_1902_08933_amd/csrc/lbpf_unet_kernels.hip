@@ -89,7 +89,8 @@ template <int KS, int COT>
 constexpr int conv_lds_elems() {
     constexpr int PR = kConvTR + KS - 1, PC = kConvTC + KS - 1;
     constexpr int in = PR * PC * kConvCKP + COT * KS * KS * kConvCKP;
-    constexpr int out = kConvTR * kConvTC * (COT + 8);
+    // output tile (bf16, padded rows) followed by the fused head's FP32 outputs [pixel][16]
+    constexpr int out = kConvTR * kConvTC * (COT + 8) + kConvTR * kConvTC * 16 * 2;
     return in > out ? in : out;
 }
 
@@ -99,108 +100,19 @@ __device__ __forceinline__ int wrap_coord(int v, int m) {
     return r < 0 ? r + m : r;
 }
 
-template <int KS, bool RELU, int COT>
-__global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs a) {
-    constexpr int TR = kConvTR, TC = kConvTC, CK = kConvCK, CKP = kConvCKP;
-    constexpr int HALO = KS - 1, PR = TR + HALO, PC = TC + HALO, T = KS * KS;
-    constexpr int PIECES = CK / 8;                  // 16-byte pieces per pixel and chunk
-    constexpr int NPATCH = PR * PC * PIECES;
-    constexpr int NWT = COT * T * PIECES;
-    constexpr int PP = (NPATCH + 255) / 256, PW = (NWT + 255) / 256;
-    constexpr int MF = TR / 4, NF = COT / 16, COTP = COT + 8;
-    extern __shared__ __attribute__((aligned(16))) bf16 conv_lds[];
-    bf16* s_x = conv_lds;
-    bf16* s_w = conv_lds + PR * PC * CKP;
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int H = a.H, W = a.W, Cin = a.Cin, Cl = a.Cl, Cout = a.Cout;
-    const int tiles_x = (W + TC - 1) / TC, tiles_y = (H + TR - 1) / TR;
-    const int tile = blockIdx.x;
-    const int tx0 = (tile % tiles_x) * TC, ty0 = ((tile / tiles_x) % tiles_y) * TR;
-    const int n = tile / (tiles_x * tiles_y);
-    const int co0 = blockIdx.y * COT;
-    const int h0 = HALO / 2, Hl = H >> 1, Wl = W >> 1;
-
-    short8_t rp[PP], rw[PW];
-    auto fetch = [&](int kc) {
-#pragma unroll
-        for (int i = 0; i < PP; ++i) {
-            const int piece = tid + 256 * i;
-            short8_t v = {0, 0, 0, 0, 0, 0, 0, 0};
-            if (piece < NPATCH) {
-                const int q = piece % PIECES, pix = piece / PIECES;
-                const int sy = wrap_coord(ty0 + pix / PC - h0, H), sx = wrap_coord(tx0 + pix % PC - h0, W);
-                const int ci = kc + 8 * q;
-                if (ci < Cl)
-                    v = *reinterpret_cast<const short8_t*>(
-                        a.xl + ((size_t)(n * Hl + (sy >> 1)) * Wl + (sx >> 1)) * a.xls + a.xlo + ci);
-                else if (ci < Cin)
-                    v = *reinterpret_cast<const short8_t*>(
-                        a.x + ((size_t)(n * H + sy) * W + sx) * a.xs + a.xo + (ci - Cl));
-            }
-            rp[i] = v;
-        }
-#pragma unroll
-        for (int i = 0; i < PW; ++i) {
-            const int piece = tid + 256 * i;
-            short8_t v = {0, 0, 0, 0, 0, 0, 0, 0};
-            if (piece < NWT) {
-                const int q = piece % PIECES, r = piece / PIECES;
-                const int co = co0 + r / T, ci = kc + 8 * q;
-                if (co < Cout && ci < Cin)
-                    v = *reinterpret_cast<const short8_t*>(a.w + ((size_t)co * T + r % T) * Cin + ci);
-            }
-            rw[i] = v;
-        }
-    };
-    auto publish = [&]() {
-#pragma unroll
-        for (int i = 0; i < PP; ++i) {
-            const int piece = tid + 256 * i;
-            if (piece < NPATCH)
-                *reinterpret_cast<short8_t*>(s_x + (piece / PIECES) * CKP + 8 * (piece % PIECES)) = rp[i];
-        }
-#pragma unroll
-        for (int i = 0; i < PW; ++i) {
-            const int piece = tid + 256 * i;
-            if (piece < NWT)
-                *reinterpret_cast<short8_t*>(s_w + (piece / PIECES) * CKP + 8 * (piece % PIECES)) = rw[i];
-        }
-    };
-
-    float4_t acc[MF][NF];
-#pragma unroll
-    for (int f = 0; f < MF; ++f)
-#pragma unroll
-        for (int j = 0; j < NF; ++j) acc[f][j] = {0.f, 0.f, 0.f, 0.f};
-    const int m = lane & 15, kq = 8 * (lane >> 4);
-    fetch(0);
-    for (int kc = 0; kc < Cin; kc += CK) {
-        __syncthreads();
-        publish();
-        __syncthreads();
-        if (kc + CK < Cin) fetch(kc + CK);
-#pragma unroll
-        for (int tap = 0; tap < T; ++tap) {
-            const int dy = KS == 3 ? tap / 3 - 1 : 0, dx = KS == 3 ? tap % 3 - 1 : 0;
-            short8_t b[NF];
-#pragma unroll
-            for (int j = 0; j < NF; ++j)
-                b[j] = *reinterpret_cast<const short8_t*>(s_w + ((16 * j + m) * T + tap) * CKP + kq);
-#pragma unroll
-            for (int f = 0; f < MF; ++f) {
-                const int row = wave * MF + f;
-                const short8_t av = *reinterpret_cast<const short8_t*>(
-                    s_x + ((row + dy + h0) * PC + (m + dx + h0)) * CKP + kq);
-#pragma unroll
-                for (int j = 0; j < NF; ++j) acc[f][j] = mfma32(av, b[j], acc[f][j]);
-            }
-        }
-    }
-
-    // epilogue. D fragment: lane (16 * g + c) holds pixels 4g .. 4g+3 of the row, channel c.
-    __syncthreads();  // LDS is reused for the output tile
-    bf16* s_o = conv_lds;
+// Epilogue shared by the convolution kernels: bias, activation and the outputs of ConvArgs
+// (bf16 tile through LDS, its 2x2 pool, FP32 copy, prediction, fused head) for a tile of
+// TR x TC pixels at (tx0, ty0) of image n and output channels co0 .. co0 + COT - 1, from the
+// accumulators of the 4 waves (wave w: rows MF w .. MF w + MF - 1). The caller has finished
+// with its LDS; s_o is the start of the workgroup's LDS.
+template <bool RELU, int COT, int MF>
+__device__ __forceinline__ void conv_epilogue(const ConvArgs& a, const float4_t (&acc)[MF][COT / 16],
+                                              bf16* s_o, int tx0, int ty0, int n, int co0) {
+    constexpr int TR = kConvTR, TC = kConvTC, NF = COT / 16, COTP = COT + 8;
+    static_assert(TR == 4 * MF, "four waves of MF rows");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, m = lane & 15;
+    const int H = a.H, W = a.W, Cout = a.Cout;
+    // D fragment: lane (16 * g + c) holds pixels 4g .. 4g+3 of the row, channel c
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
         const int co = co0 + 16 * j + m;
@@ -213,17 +125,53 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs a) {
                 const int px = 4 * (lane >> 4) + e, xx = tx0 + px;
                 float v = acc[f][j][e] + bb;
                 if (RELU) v = fmaxf(v, 0.0f);
-                if (a.y || a.yp) s_o[(py * TC + px) * COTP + 16 * j + m] = f2bf(v);
+                if (a.y || a.yp || a.hw) s_o[(py * TC + px) * COTP + 16 * j + m] = f2bf(v);
                 if (yy < H && xx < W && co < Cout) {
                     const size_t p = (size_t)(n * H + yy) * W + xx;
                     if (a.yf) a.yf[p * Cout + co] = v;
-                    if (a.pred && co < a.rc) a.pred[p * a.rc + co] = a.res[p * a.rc + co] + v;
+                    if (a.pred && !a.hw && co < a.rc) a.pred[p * a.rc + co] = a.res[p * a.rc + co] + v;
                 }
             }
         }
     }
-    if (!a.y && !a.yp) return;
+    if (!a.y && !a.yp && !a.hw) return;
     __syncthreads();
+    if (a.hw) {
+        // fused 1x1 head on the bf16 outputs of this tile (all Cout <= 32 channels are in s_o):
+        // per 16-pixel row one 16x16x32 MFMA, A = pixels x channels, B = channels x head outputs
+        const int g = lane >> 4;
+        short8_t hwf = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (m < a.rc && 8 * g + e < Cout) hwf[e] = (short)a.hw[m * Cout + 8 * g + e];
+        const float hbias = (a.hb && m < a.rc) ? a.hb[m] : 0.0f;
+        float* s_h = reinterpret_cast<float*>(s_o + TR * TC * COTP);
+#pragma unroll
+        for (int f = 0; f < MF; ++f) {
+            const int py = wave * MF + f, yy = ty0 + py;
+            short8_t av = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (8 * g < Cout) av = *reinterpret_cast<const short8_t*>(s_o + (py * TC + m) * COTP + 8 * g);
+            const float4_t d = mfma32(av, hwf, float4_t{0.f, 0.f, 0.f, 0.f});
+            // D: lane (m + 16 g) holds pixels 4g .. 4g+3 of the row, head output m
+#pragma unroll
+            for (int e = 0; e < 4; ++e) s_h[(py * TC + 4 * g + e) * 16 + m] = d[e] + hbias;
+            (void)yy;
+        }
+        __syncthreads();
+        // prediction = input + head, one pixel per thread with 16-byte accesses for 4 fields
+        for (int pix = tid; pix < TR * TC; pix += 256) {
+            const int yy = ty0 + pix / TC, xx = tx0 + pix % TC;
+            if (yy >= H || xx >= W) continue;
+            const size_t p = (size_t)(n * H + yy) * W + xx;
+            if (a.rc == 4) {
+                const float4 r = *reinterpret_cast<const float4*>(a.res + p * 4);
+                const float4 hv = *reinterpret_cast<const float4*>(s_h + pix * 16);
+                *reinterpret_cast<float4*>(a.pred + p * 4) = make_float4(r.x + hv.x, r.y + hv.y, r.z + hv.z, r.w + hv.w);
+            } else {
+                for (int c = 0; c < a.rc; ++c) a.pred[p * a.rc + c] = a.res[p * a.rc + c] + s_h[pix * 16 + c];
+            }
+        }
+    }
     if (a.y) {
         for (int piece = tid; piece < TR * TC * (COT / 8); piece += 256) {
             const int q = piece % (COT / 8), pix = piece / (COT / 8);
@@ -253,6 +201,183 @@ __global__ __launch_bounds__(256) void conv_tile_kernel(const ConvArgs a) {
             *reinterpret_cast<short8_t*>(a.yp + ((size_t)(n * Hp + yy) * Wp + xx) * a.yps + a.ypo + co) = r;
         }
     }
+}
+
+// First layer of the network: the input is FP32 NHWC with xin_c <= 4 fields. The K dimension of
+// the implicit GEMM is ordered (tap, field), so the 9 x 4 = 36 products of a 3x3 convolution
+// fill two 16x16x32 MFMA steps (zero beyond tap 8) instead of one step per tap with the fields
+// padded to 32 channels. The input patch is converted to bf16 into LDS (8 bytes per pixel);
+// the weights of the workgroup's channels stay in registers.
+template <bool RELU, int COT>
+__global__ __launch_bounds__(256, 2) void conv_first_kernel(const ConvArgs a) {
+    constexpr int TR = kConvTR, TC = kConvTC, PR = TR + 2, PC = TC + 2;
+    constexpr int MF = TR / 4, NF = COT / 16;
+    extern __shared__ __attribute__((aligned(16))) bf16 conv_lds[];
+    bf16* s_x = conv_lds;  // [PR * PC][4]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, m = lane & 15, g = lane >> 4;
+    const int H = a.H, W = a.W, Cout = a.Cout, cin = a.xin_c, wcin = a.Cin;
+    const int tiles_x = (W + TC - 1) / TC, tiles_y = (H + TR - 1) / TR;
+    const int tile = blockIdx.x;
+    const int tx0 = (tile % tiles_x) * TC, ty0 = ((tile / tiles_x) % tiles_y) * TR;
+    const int n = tile / (tiles_x * tiles_y);
+    const int co0 = blockIdx.y * COT;
+    for (int pix = tid; pix < PR * PC; pix += 256) {
+        const int sy = wrap_coord(ty0 + pix / PC - 1, H), sx = wrap_coord(tx0 + pix % PC - 1, W);
+        const float* src = a.xin + ((size_t)(n * H + sy) * W + sx) * cin;
+        short4_t v = {0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < cin) v[c] = (short)f2bf(src[c]);
+        *reinterpret_cast<short4_t*>(s_x + pix * 4) = v;
+    }
+    // B[k][co] with k = 4 tap + field: lane (m + 16 g) holds k = 32 s + 8 g + e, i.e. taps
+    // 8 s + 2 g (e < 4) and 8 s + 2 g + 1 (e >= 4), field e % 4
+    short8_t b[2][NF];
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            const int co = co0 + 16 * j + m;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int t = 8 * st + 2 * g + (e >> 2), c = e & 3;
+                b[st][j][e] = (co < Cout && t < 9 && c < cin) ? (short)a.w[((size_t)co * 9 + t) * wcin + c] : (short)0;
+            }
+        }
+    __syncthreads();
+    float4_t acc[MF][NF];
+#pragma unroll
+    for (int f = 0; f < MF; ++f)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) acc[f][j] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int f = 0; f < MF; ++f) {
+        const int row = wave * MF + f;
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+            const int t0 = 8 * st + 2 * g, t1 = t0 + 1;
+            short4_t x0 = {0, 0, 0, 0}, x1 = {0, 0, 0, 0};
+            if (t0 < 9) x0 = *reinterpret_cast<const short4_t*>(s_x + ((row + t0 / 3) * PC + m + t0 % 3) * 4);
+            if (t1 < 9) x1 = *reinterpret_cast<const short4_t*>(s_x + ((row + t1 / 3) * PC + m + t1 % 3) * 4);
+            const short8_t av = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
+#pragma unroll
+            for (int j = 0; j < NF; ++j) acc[f][j] = mfma32(av, b[st][j], acc[f][j]);
+        }
+    }
+    __syncthreads();  // LDS is reused for the output tile
+    conv_epilogue<RELU, COT, MF>(a, acc, conv_lds, tx0, ty0, n, co0);
+}
+
+template <int KS, bool RELU, int COT>
+__global__ __launch_bounds__(256, 2) void conv_tile_kernel(const ConvArgs a) {
+    constexpr int TR = kConvTR, TC = kConvTC, CK = kConvCK, CKP = kConvCKP;
+    constexpr int HALO = KS - 1, PR = TR + HALO, PC = TC + HALO, T = KS * KS;
+    constexpr int PIECES = CK / 8;                  // 16-byte pieces per pixel and chunk
+    constexpr int NPATCH = PR * PC * PIECES;
+    constexpr int NWT = COT * T * PIECES;
+    constexpr int PP = (NPATCH + 255) / 256, PW = (NWT + 255) / 256;
+    constexpr int MF = TR / 4, NF = COT / 16, COTP = COT + 8;
+    extern __shared__ __attribute__((aligned(16))) bf16 conv_lds[];
+    bf16* s_x = conv_lds;
+    bf16* s_w = conv_lds + PR * PC * CKP;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int H = a.H, W = a.W, Cin = a.Cin, Cl = a.Cl, Cout = a.Cout;
+    const int tiles_x = (W + TC - 1) / TC, tiles_y = (H + TR - 1) / TR;
+    const int tile = blockIdx.x;
+    const int tx0 = (tile % tiles_x) * TC, ty0 = ((tile / tiles_x) % tiles_y) * TR;
+    const int n = tile / (tiles_x * tiles_y);
+    const int co0 = blockIdx.y * COT;
+    const int h0 = HALO / 2, Hl = H >> 1, Wl = W >> 1;
+
+    // weights are prefetched into registers with the patch when that keeps two waves per SIMD
+    // (COT <= 32); the COT = 64 variant loads them while publishing (they are L2-resident)
+    constexpr bool PFW = COT <= 32;
+    constexpr int PWR = PFW ? PW : 1;
+    short8_t rp[PP], rw[PWR];
+    auto fetch_w = [&](int i, int kc) {
+        const int piece = tid + 256 * i;
+        short8_t v = {0, 0, 0, 0, 0, 0, 0, 0};
+        const int q = piece % PIECES, r = piece / PIECES;
+        const int co = co0 + r / T, ci = kc + 8 * q;
+        if (piece < NWT && co < Cout && ci < Cin)
+            v = *reinterpret_cast<const short8_t*>(a.w + ((size_t)co * T + r % T) * Cin + ci);
+        return v;
+    };
+    auto fetch = [&](int kc) {
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int piece = tid + 256 * i;
+            short8_t v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (piece < NPATCH) {
+                const int q = piece % PIECES, pix = piece / PIECES;
+                const int sy = wrap_coord(ty0 + pix / PC - h0, H), sx = wrap_coord(tx0 + pix % PC - h0, W);
+                const int ci = kc + 8 * q;
+                if (ci < Cl)
+                    v = *reinterpret_cast<const short8_t*>(
+                        a.xl + ((size_t)(n * Hl + (sy >> 1)) * Wl + (sx >> 1)) * a.xls + a.xlo + ci);
+                else if (ci < Cin)
+                    v = *reinterpret_cast<const short8_t*>(
+                        a.x + ((size_t)(n * H + sy) * W + sx) * a.xs + a.xo + (ci - Cl));
+            }
+            rp[i] = v;
+        }
+        if (PFW) {
+#pragma unroll
+            for (int i = 0; i < PWR; ++i) rw[i] = fetch_w(i, kc);
+        }
+    };
+    // the patch (and with PFW the weights) come from the registers fetched during the previous
+    // chunk; otherwise the weights (a few tens of KB, shared by every workgroup and resident in
+    // L2) are loaded here, so that no registers hold them across the MFMA loop
+    auto publish = [&](int kc) {
+#pragma unroll
+        for (int i = 0; i < PP; ++i) {
+            const int piece = tid + 256 * i;
+            if (piece < NPATCH)
+                *reinterpret_cast<short8_t*>(s_x + (piece / PIECES) * CKP + 8 * (piece % PIECES)) = rp[i];
+        }
+#pragma unroll
+        for (int i = 0; i < PW; ++i) {
+            const int piece = tid + 256 * i;
+            if (piece < NWT)
+                *reinterpret_cast<short8_t*>(s_w + (piece / PIECES) * CKP + 8 * (piece % PIECES)) =
+                    PFW ? rw[PFW ? i : 0] : fetch_w(i, kc);
+        }
+    };
+
+    float4_t acc[MF][NF];
+#pragma unroll
+    for (int f = 0; f < MF; ++f)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) acc[f][j] = {0.f, 0.f, 0.f, 0.f};
+    const int m = lane & 15, kq = 8 * (lane >> 4);
+    fetch(0);
+    for (int kc = 0; kc < Cin; kc += CK) {
+        __syncthreads();
+        publish(kc);
+        __syncthreads();
+        if (kc + CK < Cin) fetch(kc + CK);
+#pragma unroll
+        for (int tap = 0; tap < T; ++tap) {
+            const int dy = KS == 3 ? tap / 3 - 1 : 0, dx = KS == 3 ? tap % 3 - 1 : 0;
+            short8_t b[NF];
+#pragma unroll
+            for (int j = 0; j < NF; ++j)
+                b[j] = *reinterpret_cast<const short8_t*>(s_w + ((16 * j + m) * T + tap) * CKP + kq);
+#pragma unroll
+            for (int f = 0; f < MF; ++f) {
+                const int row = wave * MF + f;
+                const short8_t av = *reinterpret_cast<const short8_t*>(
+                    s_x + ((row + dy + h0) * PC + (m + dx + h0)) * CKP + kq);
+#pragma unroll
+                for (int j = 0; j < NF; ++j) acc[f][j] = mfma32(av, b[j], acc[f][j]);
+            }
+        }
+    }
+
+    __syncthreads();  // LDS is reused for the output tile
+    conv_epilogue<RELU, COT, MF>(a, acc, conv_lds, tx0, ty0, n, co0);
 }
 
 // dgrad weights: W'[ci][tap'][co] = W[co][KS*KS-1-tap'][ci], so that the data gradient of a
@@ -628,17 +753,48 @@ static hipError_t launch_conv_t(const ConvArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <bool R, int C>
+static hipError_t launch_first_t(const ConvArgs& a, hipStream_t st) {
+    constexpr size_t lds = (size_t)conv_lds_elems<1, C>() * sizeof(bf16);
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)&conv_first_kernel<R, C>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const long long tiles = (long long)a.N * ((a.H + kConvTR - 1) / kConvTR) * ((a.W + kConvTC - 1) / kConvTC);
+    dim3 grid((unsigned)tiles, (unsigned)((a.Cout + C - 1) / C));
+    hipLaunchKernelGGL((conv_first_kernel<R, C>), grid, dim3(256), lds, st, a);
+    return hipGetLastError();
+}
+
 hipError_t unet_conv(int ks, bool relu, const ConvArgs& a, hipStream_t st) {
+    if (a.xin) {
+        const bool ok = ks == 3 && a.xin_c >= 1 && a.xin_c <= 4 && a.Cl == 0 && !a.hw &&
+                        (!a.y || (a.Cout % 8 == 0 && a.ys % 8 == 0 && a.yo % 8 == 0)) &&
+                        (!a.yp || (a.Cout % 8 == 0 && a.yps % 8 == 0 && a.ypo % 8 == 0 &&
+                                   a.H % 2 == 0 && a.W % 2 == 0)) &&
+                        (!a.pred || a.res) && a.N >= 1 && a.H >= 1 && a.W >= 1;
+        if (!ok) return hipErrorInvalidValue;
+        if (a.Cout <= 32) return relu ? launch_first_t<true, 32>(a, st) : launch_first_t<false, 32>(a, st);
+        return relu ? launch_first_t<true, 64>(a, st) : launch_first_t<false, 64>(a, st);
+    }
     const bool aligned = a.Cin % 8 == 0 && a.xs % 8 == 0 && a.xo % 8 == 0 &&
                          (a.Cl == 0 || (a.Cl % 8 == 0 && a.xls % 8 == 0 && a.xlo % 8 == 0 &&
                                         a.H % 2 == 0 && a.W % 2 == 0)) &&
                          (!a.y || (a.Cout % 8 == 0 && a.ys % 8 == 0 && a.yo % 8 == 0)) &&
                          (!a.yp || (a.Cout % 8 == 0 && a.yps % 8 == 0 && a.ypo % 8 == 0 &&
                                     a.H % 2 == 0 && a.W % 2 == 0)) &&
-                         (!a.pred || (a.res && a.rc <= a.Cout));
+                         (!a.pred || (a.res && a.rc <= a.Cout)) &&
+                         (!a.hw || (a.pred && a.res && a.Cout <= 32 && a.rc >= 1 && a.rc <= 16));
     if (!aligned || (ks != 1 && ks != 3) || a.Cl > a.Cin || a.N < 1 || a.H < 1 || a.W < 1)
         return hipErrorInvalidValue;
-    const int cot = a.Cout <= 16 ? 16 : (a.Cout <= 32 ? 32 : 64);
+    int cot = a.Cout <= 16 ? 16 : (a.Cout <= 32 ? 32 : 64);
+    if (a.hw) cot = 32;  // the fused head needs every output channel in one workgroup
+    // fewer than ~2 workgroups per CU with 64 channels each: take 32 (more workgroups)
+    const long long tiles = (long long)a.N * ((a.H + kConvTR - 1) / kConvTR) * ((a.W + kConvTC - 1) / kConvTC);
+    if (cot == 64 && tiles * ((a.Cout + 63) / 64) < 512) cot = 32;
 #define LBPF_CONV(KS_, C_) return relu ? launch_conv_t<KS_, true, C_>(a, st) : launch_conv_t<KS_, false, C_>(a, st)
     if (ks == 3) {
         if (cot == 16) LBPF_CONV(3, 16);

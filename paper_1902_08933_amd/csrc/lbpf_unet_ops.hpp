@@ -19,6 +19,9 @@ typedef uint16_t bf16;
 // Outputs (each optional): y (bf16, post-activation), its 2x2 average pool yp (bf16,
 // N x H/2 x W/2, the mean of the four bf16 values, H and W even), yf (FP32 [p][Cout]), and
 // the prediction epilogue pred[p][c] = res[p][c] + v[p, c] for c < rc (FP32, rc channels).
+// With hw set (a 3x3 layer whose Cout fits one workgroup, Cout <= 32), the epilogue instead
+// applies a 1x1 head to the bf16-rounded outputs: pred[p][c] = res[p][c] + hb[c] +
+// sum_ci hw[c][ci] bf16(v[p, ci]) for c < rc (hw: [>= rc][Cout] bf16, hb: FP32).
 // Alignment: Cin, Cl, strides and offsets multiples of 8 (16-byte pieces); H, W even if Cl > 0.
 struct ConvArgs {
     const bf16* x;
@@ -36,6 +39,12 @@ struct ConvArgs {
     const float* res;
     float* pred;
     int rc;
+    const bf16* hw;
+    const float* hb;
+    // first layer: instead of x, the FP32 input NHWC with xin_c <= 4 fields (3x3 only); Cin is
+    // then the channel stride of the weights
+    const float* xin;
+    int xin_c;
     int Cout, N, H, W;
 };
 
