@@ -20,7 +20,8 @@ _PD = ctypes.POINTER(ctypes.c_double)
 class SpParams(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("model", ctypes.c_int32),
                 ("pscheme", ctypes.c_int32), ("full", ctypes.c_int32), ("bc", ctypes.c_int32),
-                ("nu", _D), ("xi", _D), ("rho0", _D)]
+                ("nu", _D), ("xi", _D), ("rho0", _D), ("drag", _D), ("scheme", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 _lib = None
@@ -77,6 +78,8 @@ def make_params(cfg):
     p.nu = float(cfg["nu"])
     p.xi = float(cfg.get("xi", 0.0))
     p.rho0 = float(cfg.get("rho0", 1.0))
+    p.drag = float(cfg.get("drag", 0.0))
+    p.scheme = {"eq24": 0, "remark4": 1}[cfg.get("scheme", "eq24")]
     return p
 
 

@@ -29,7 +29,13 @@
  *            level: G_0 is affine in it, so eq. (28) is solved for p^n in closed form. (A
  *            lagged difference p^{n-1} - p^{n-2} feeds back into eq. (28) and grows without
  *            bound; the current-level difference is stable.)
- *   fields   S(x) and F(x) are given per node and constant in time.
+ *   fields   S(x) and F(x) are given per node and constant in time; with drag lambda the
+ *            force is F = F_ext - lambda rho u, a force that depends on u (the case Remark 4 is
+ *            written for): under eq. (24) the velocity of eq. (27a) is then implicit and, the
+ *            dependence being linear, solved in closed form.
+ *   Remark 4 (scheme 1, model 0 only) evolves f~ of eq. (21bb) itself with the explicit
+ *            discretization of D_i G_i: rho~ = sum f~, rho u = sum c f~; G_i(x + c_i) across a
+ *            wall link is G_i(x); before the first step G(t - 1) = G(t).
  *   init     g_i = g_i^eq of the initial fields.
  *   walls    halfway bounce-back below row 0 and above row ny-1 (bc 1); stencil ghosts mirror
  *            the first fluid row.
@@ -56,6 +62,10 @@ typedef struct {
     double nu;       /* kinematic viscosity */
     double xi;       /* bulk viscosity */
     double rho0;     /* model 1: the constant rho~ */
+    double drag;     /* model 0: lambda >= 0, the force is F = F_ext - lambda rho u (it depends on u) */
+    int32_t scheme;  /* model 0: 0 eq. (24) with g = f~ - G/2 (eq. 23a); 1 Remark 4, the
+                        explicit D_i G_i scheme on f~ itself */
+    int32_t pad;
 } sp_params;
 
 typedef struct {
@@ -68,6 +78,7 @@ typedef struct {
     double *ux_prev, *uy_prev;   /* model 0: velocity of the previous step (div u reading) */
     double *p_prev;              /* model 1: pressure of the previous step */
     double *rho, *ux, *uy, *p, *G; /* per-step work arrays; G is [NQ][ny][nx] */
+    double *G_prev;              /* Remark 4: the force distribution of the previous step */
     double *w1, *w2, *w3;        /* stencil scratch */
 } sp_state;
 
@@ -157,6 +168,8 @@ int sp_params_valid(const sp_params* P) {
     if (P->nx < 3 || P->ny < 3) return 0;
     if (P->model != 0 && P->model != 1) return 0;
     if (!(P->nu > 0.0)) return 0;
+    if (!(P->drag >= 0.0) || (P->drag != 0.0 && P->model != 0)) return 0;
+    if (P->scheme != 0 && (P->scheme != 1 || P->model != 0)) return 0;
     return 1;
 }
 
@@ -170,6 +183,7 @@ sp_state* sp_create(const sp_params* P) {
     s->g = calloc(SP_NQ * n, sizeof(double));
     s->gs = calloc(SP_NQ * n, sizeof(double));
     s->G = calloc(SP_NQ * n, sizeof(double));
+    s->G_prev = calloc(SP_NQ * n, sizeof(double));
     double** one[] = {&s->S, &s->Fx, &s->Fy, &s->ux_prev, &s->uy_prev, &s->p_prev,
                       &s->rho, &s->ux, &s->uy, &s->p, &s->w1, &s->w2, &s->w3};
     for (size_t k = 0; k < sizeof(one) / sizeof(one[0]); ++k) *one[k] = calloc(n, sizeof(double));
@@ -178,7 +192,7 @@ sp_state* sp_create(const sp_params* P) {
 
 void sp_destroy(sp_state* s) {
     if (!s) return;
-    double* all[] = {s->g, s->gs, s->G, s->S, s->Fx, s->Fy, s->ux_prev, s->uy_prev, s->p_prev,
+    double* all[] = {s->g, s->gs, s->G, s->G_prev, s->S, s->Fx, s->Fy, s->ux_prev, s->uy_prev, s->p_prev,
                      s->rho, s->ux, s->uy, s->p, s->w1, s->w2, s->w3};
     for (size_t k = 0; k < sizeof(all) / sizeof(all[0]); ++k) free(all[k]);
     free(s);
@@ -224,8 +238,21 @@ static void sp_macroscopics(sp_state* s) {
                 my += SP_CY[i] * g[i];
             }
             double S = s->S[k], Fx = s->Fx[k], Fy = s->Fy[k];
-            double rho = sum + 0.5 * S;                                 /* eq. (27aa), rho~ = rho */
-            double ux = (mx + 0.5 * Fx) / rho, uy = (my + 0.5 * Fy) / rho; /* eq. (27a) */
+            double rho, ux, uy;
+            if (P->scheme == 0) {
+                /* eq. (27aa) with rho~ = rho, and eq. (27a) with F = F_ext - lambda rho u, which
+                 * is implicit in u; linear, so solved: rho u (1 + lambda/2) = sum c g + F_ext/2 */
+                rho = sum + 0.5 * S;
+                ux = (mx + 0.5 * Fx) / (rho * (1.0 + 0.5 * P->drag));
+                uy = (my + 0.5 * Fy) / (rho * (1.0 + 0.5 * P->drag));
+            } else {
+                /* Remark 4 evolves f~ itself: rho~ = sum f~, rho u = sum c f~ (after eq. 21bb) */
+                rho = sum;
+                ux = mx / rho;
+                uy = my / rho;
+            }
+            Fx -= P->drag * rho * ux;
+            Fy -= P->drag * rho * uy;
             double Q = 2.0 / SP_DIM * rho * SP_CS2 - P->xi / (tau - 0.5);
             double divu = s->w1[k] + s->w2[k];
             double axx, axy, ayy, G[SP_NQ];
@@ -293,8 +320,22 @@ static void sp_one_step(sp_state* s) {
         else sp_equilibrium_inc(P->rho0, s->p[k], s->ux[k], s->uy[k], geq);
         for (int i = 0; i < SP_NQ; ++i) {
             double gi = s->g[i * n + k];
-            /* eq. (24), dt = 1 */
-            s->gs[i * n + k] = gi - (gi - geq[i]) / tau + (1.0 - 1.0 / (2.0 * tau)) * s->G[i * n + k];
+            if (P->scheme == 0) {
+                /* eq. (24), dt = 1 */
+                s->gs[i * n + k] = gi - (gi - geq[i]) / tau + (1.0 - 1.0 / (2.0 * tau)) * s->G[i * n + k];
+            } else {
+                /* Remark 4: f~* = f~ - (f~ - f^eq)/tau + G_i(x, t) + [G_i(x + c_i, t) - G_i(x, t - 1)] / 2;
+                 * G_i(x + c_i) of a link that leaves the domain through a wall is taken at x;
+                 * before the first step G(t - 1) = G(t) */
+                int x = (int)(k % nx), j = (int)(k / nx);
+                int xn = ((x + SP_CX[i]) % nx + nx) % nx, jn = j + SP_CY[i];
+                size_t kn;
+                if (P->bc == 0) kn = (size_t)(((jn % ny) + ny) % ny) * nx + xn;
+                else kn = (jn < 0 || jn >= ny) ? k : (size_t)jn * nx + xn;
+                double Gc = s->G[i * n + k], Gn = s->G[i * n + kn];
+                double Gp = s->step == 0 ? Gc : s->G_prev[i * n + k];
+                s->gs[i * n + k] = gi - (gi - geq[i]) / tau + Gc + 0.5 * (Gn - Gp);
+            }
         }
     }
     for (int j = 0; j < ny; ++j)
@@ -321,6 +362,7 @@ static void sp_one_step(sp_state* s) {
         s->uy_prev[k] = s->uy[k];
         s->p_prev[k] = s->p[k];
     }
+    memcpy(s->G_prev, s->G, SP_NQ * n * sizeof(double));
     s->step += 1;
 }
 
@@ -344,12 +386,12 @@ void sp_read_force_distribution(sp_state* s, double* out) {
     memcpy(out, s->G, SP_NQ * s->n * sizeof(double));
 }
 
-/* sum over the grid of sum_i g_i + S/2, i.e. of rho~ by eq. (27aa) */
+/* sum over the grid of rho~: sum_i g_i + S/2 by eq. (27aa), sum_i f~_i under Remark 4 */
 double sp_sum_rho_tilde(const sp_state* s) {
     double acc = 0.0;
     for (size_t k = 0; k < s->n; ++k) {
         for (int i = 0; i < SP_NQ; ++i) acc += s->g[i * s->n + k];
-        acc += 0.5 * s->S[k];
+        if (s->P.scheme == 0) acc += 0.5 * s->S[k];  /* eq. (27aa); Remark 4: rho~ = sum f~ */
     }
     return acc;
 }

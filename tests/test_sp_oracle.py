@@ -166,3 +166,86 @@ def test_incompressible_full_form_is_stable(tau):
     d = np.abs(a.read("p") - b.read("p")).max()
     print(f"tau {tau}: perturbation after 400 steps {d:.2e}")
     assert d < 1e-9
+
+
+# ---- a force that depends on u, and Remark 4's explicit D_i G_i scheme -----------------------
+
+def uniform_drag(scheme, lam, steps, u0=1e-3):
+    nx = ny = 4
+    cfg = dict(nx=nx, ny=ny, model="nearly_incompressible", nu=1.0 / 6.0, drag=lam, scheme=scheme)
+    o = sp.SpOracle(cfg).init(ux=np.full((ny, nx), u0))
+    us = []
+    for _ in range(steps + 1):
+        us.append(o.read("ux")[0, 0])
+        o.step(1)
+    return np.array(us)
+
+
+def test_drag_time_discretizations_are_exact_recurrences():
+    # uniform fluid under F = -lambda rho u: eq. (24) with the implicit velocity of eq. (27a)
+    # advances the momentum by the trapezoidal rule, u_{n+1} = u_n (1 - lambda/2)/(1 + lambda/2);
+    # Remark 4 by second-order Adams-Bashforth, m_{n+1} = m_n + (3 F_n - F_{n-1})/2 with
+    # F_{-1} = F_0
+    lam, n = 0.05, 60
+    u = uniform_drag("eq24", lam, n)
+    r = (1 - lam / 2) / (1 + lam / 2)
+    np.testing.assert_allclose(u, u[0] * r ** np.arange(n + 1), rtol=1e-10)
+    u = uniform_drag("remark4", lam, n)
+    ref = [u[0], u[0] * (1 - lam)]
+    for _ in range(n - 1):
+        ref.append(ref[-1] - lam * (3 * ref[-1] - ref[-2]) / 2)
+    np.testing.assert_allclose(u, np.array(ref), rtol=1e-10)  # round-off of 60 steps ~1e-12
+
+
+@pytest.mark.parametrize("scheme", ["eq24", "remark4"])
+def test_drag_decay_is_second_order_in_time(scheme):
+    # at fixed time T = 2 / lambda_0 the error against exp(-lambda t) drops 4x when lambda halves
+    def err(lam):
+        n = int(round(2.0 / lam))
+        u = uniform_drag(scheme, lam, n)
+        return abs(u[-1] / u[0] - math.exp(-lam * n))
+    e1, e2 = err(0.1), err(0.05)
+    print(f"{scheme}: decay error {e1:.3e} (lambda 0.1), {e2:.3e} (0.05)")
+    assert 3.5 < e1 / e2 < 4.5
+
+
+def test_remark4_global_balances():
+    # total rho~ grows by sum S per step; total momentum by (3 sum F_n - sum F_{n-1}) / 2, with
+    # F = F_ext - lambda rho u evaluated on the state of each step
+    nx, ny, lam = 12, 10, 0.02
+    S = 1e-3 * RNG.normal(size=(ny, nx)) + 2e-4
+    Fx = 1e-4 * RNG.normal(size=(ny, nx))
+    Fy = 1e-4 * RNG.normal(size=(ny, nx))
+    cfg = dict(nx=nx, ny=ny, model="nearly_incompressible", nu=0.1, drag=lam, scheme="remark4")
+    o = sp.SpOracle(cfg).init(1 + 1e-3 * RNG.normal(size=(ny, nx)), 1e-3 * RNG.normal(size=(ny, nx)),
+                              1e-3 * RNG.normal(size=(ny, nx)), S, Fx, Fy)
+
+    def totals():
+        rho, ux, uy = o.read("rho"), o.read("ux"), o.read("uy")
+        F = np.array([(Fx - lam * rho * ux).sum(), (Fy - lam * rho * uy).sum()])
+        return o.sum_rho_tilde(), np.array([(rho * ux).sum(), (rho * uy).sum()]), F
+    m0, M0, F0 = totals()
+    Fprev = F0
+    for _ in range(15):
+        o.step(1)
+        m1, M1, F1 = totals()
+        assert abs(m1 - m0 - S.sum()) < 1e-12
+        np.testing.assert_allclose(M1 - M0, (3 * F0 - Fprev) / 2, rtol=1e-9, atol=1e-16)
+        Fprev, m0, M0, F0 = F0, m1, M1, F1
+
+
+def test_remark4_channel_flow_second_order():
+    def channel(ny, G=1e-6, tau=1.0):
+        nu = (tau - 0.5) / 3.0
+        cfg = dict(nx=3, ny=ny, model="nearly_incompressible", nu=nu, bc="walls_y", scheme="remark4")
+        o = sp.SpOracle(cfg).init(Fx=np.full((ny, 3), G))
+        o.step(int(25 * ny * ny / nu / math.pi ** 2))
+        u = o.read("ux")[:, 0]
+        h = ny / 2.0
+        y = np.arange(ny) + 0.5 - h
+        ua = G / (2 * nu) * (h * h - y * y)
+        return np.abs(u - ua).max() / ua.max()
+    e8, e16 = channel(8), channel(16)
+    print(f"Remark 4 channel: error {e8:.3e} (ny 8), {e16:.3e} (ny 16)")
+    assert e16 < 2e-2
+    assert 3.0 < e8 / e16 < 5.0
