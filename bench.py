@@ -218,8 +218,11 @@ def surrogate_bench(train_steps=2000, cycles=3):
 # algorithmic bytes per node update of the single-phase step (FP32 values read + written):
 # incompressible with the full force term: g_0..8, S, F_x, F_y, p^{n-1} read; g, p^n written;
 # nearly incompressible: g, S, F, u^{n-1} read; g, u^n written
+# Remark 4 (two passes): G pass reads f~, S, F, u^{n-1} and writes G, u; the collision reads f~,
+# G(x), G(t-1) (G at the neighbours comes from L2) and writes f~
 SP_BYTES = {("incompressible", True): 4 * (13 + 10), ("incompressible", False): 4 * (12 + 9),
-            ("nearly_incompressible", True): 4 * (14 + 11), ("nearly_incompressible", False): 4 * (14 + 11)}
+            ("nearly_incompressible", True): 4 * (14 + 11), ("nearly_incompressible", False): 4 * (14 + 11),
+            ("remark4", True): 4 * ((14 + 11) + (27 + 9))}
 
 
 def single_phase_bench(n=1024, steps=2000, warmup=100):
@@ -230,8 +233,11 @@ def single_phase_bench(n=1024, steps=2000, warmup=100):
     import torch
     from paper_1902_08933_amd import lbpf, workloads as W
     out = {}
-    for model, full in (("incompressible", True), ("nearly_incompressible", True)):
-        cfg, f = W.single_phase_source(n, n, model=model, S0=1e-4, F0=1e-6, full=full)
+    for name, model, full, scheme in (("incompressible", "incompressible", True, "eq24"),
+                                      ("nearly_incompressible", "nearly_incompressible", True, "eq24"),
+                                      ("remark4", "nearly_incompressible", True, "remark4")):
+        cfg, f = W.single_phase_source(n, n, model=model, S0=1e-4, F0=1e-6, full=full, scheme=scheme,
+                                       drag=0.01 if scheme == "remark4" else 0.0)
         sim = lbpf.SinglePhase(cfg).init(*(torch.from_numpy(f[k].astype(np.float32)).cuda()
                                            for k in ("a0", "ux", "uy", "S", "Fx", "Fy")))
         sim.step(warmup)
@@ -242,10 +248,10 @@ def single_phase_bench(n=1024, steps=2000, warmup=100):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
-        b = SP_BYTES[(model, full)]
+        b = SP_BYTES[(name if scheme == "remark4" else model, full)]
         gbs = b * n * n / (ms * 1e-3) / 1e9
         sums = sim.sums()
-        out[model] = {"full_force_term": full, "ms_per_step": round(ms, 5),
+        out[name] = {"full_force_term": full, "scheme": scheme, "drag": cfg["drag"], "ms_per_step": round(ms, 5),
                       "MLUPS": round(n * n / (ms * 1e-3) / 1e6, 1), "bytes_per_node": b,
                       "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                       "finite": bool(np.isfinite(sums["rho_tilde"]))}

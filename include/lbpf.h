@@ -316,6 +316,14 @@ typedef struct lbpf_sp_params {
     double nu;        /* kinematic viscosity (> 0) */
     double xi;        /* bulk viscosity (0: Stokes hypothesis) */
     double rho0;      /* incompressible model: the constant rho~ */
+    double drag;      /* nearly incompressible model: lambda >= 0 makes the force
+                       * F = F_ext - lambda rho u, a force that depends on u; eq. (27a) is then
+                       * implicit and, being linear, solved in closed form */
+    int32_t scheme;   /* nearly incompressible model: 0 eq. (24) on g = f~ - G/2 (eq. 23a);
+                       * 1 Remark 4, the explicit discretization of D_i G_i on f~ itself
+                       * (rho~ = sum f~, rho u = sum c f~; stores G of the previous step;
+                       * G_i(x + c_i) across a wall is taken at x; two launches per step) */
+    int32_t pad;
 } lbpf_sp_params;
 
 typedef struct lbpf_sp lbpf_sp;

@@ -36,7 +36,7 @@ __device__ __forceinline__ constexpr float wq(int q) { return q == 0 ? kW0 : (q 
 // incompressible with the full force term: the previous pressure, copies 0 and 1), then the
 // FP64 reduction area.
 constexpr int kPlaneGA = 0, kPlaneGB = 9, kPlaneS = 18, kPlaneFx = 19, kPlaneFy = 20;
-constexpr int kPlaneHist = 21, kNumPlanes = 25;
+constexpr int kPlaneHist = 21, kPlaneG = 25, kNumPlanes = 25, kNumPlanesR4 = 43;  // + G, 2 copies
 constexpr int kRedBlocks = 1024;
 constexpr long kPad = 4160;  // floats between planes, as for the two-phase solver
 
@@ -49,6 +49,8 @@ struct SpModel {
     float rho0;
     int pscheme;
     float pc, ipc;             // eq. (28) with d_t p = p - p^{n-1}: c = 0.8 (tau - 1/2), 1/(1 + c)
+    float drag;                // lambda: F = F_ext - lambda rho u (model 0)
+    int scheme;                // model 0: 0 eq. (24), 1 Remark 4 (explicit D_i G_i)
 };
 
 __device__ __forceinline__ int wrapi(int v, int n) {
@@ -98,12 +100,26 @@ __device__ __forceinline__ Macro sp_macro(const SpModel& m, const float (&g)[kQ]
     const float mx = ((g[1] - g[3]) + (g[5] - g[7])) + (g[8] - g[6]);
     const float my = ((g[2] - g[4]) + (g[5] - g[7])) + (g[6] - g[8]);
     if (MODEL == 0) {
-        // eq. (27aa) with rho~ = rho: rho = sum_i g_i + S/2 = 1 + sum_i (g_i - w_i) + S/2
-        r.drho = sum + 0.5f * S;
-        r.rho = 1.0f + r.drho;
-        const float irho = __builtin_amdgcn_rcpf(r.rho);
-        r.ux = (mx + 0.5f * Fx) * irho;  // eq. (27a)
-        r.uy = (my + 0.5f * Fy) * irho;
+        if (m.scheme == 0) {
+            // eq. (27aa) with rho~ = rho: rho = sum_i g_i + S/2 = 1 + sum_i (g_i - w_i) + S/2;
+            // eq. (27a) with F = F_ext - lambda rho u, solved: rho u (1 + lambda/2) = m + F_ext/2
+            r.drho = sum + 0.5f * S;
+            r.rho = 1.0f + r.drho;
+            const float irho = __builtin_amdgcn_rcpf(r.rho * (1.0f + 0.5f * m.drag));
+            r.ux = (mx + 0.5f * Fx) * irho;
+            r.uy = (my + 0.5f * Fy) * irho;
+        } else {
+            // Remark 4 evolves f~ itself: rho~ = sum f~, rho u = sum c f~
+            r.drho = sum;
+            r.rho = 1.0f + r.drho;
+            const float irho = __builtin_amdgcn_rcpf(r.rho);
+            r.ux = mx * irho;
+            r.uy = my * irho;
+        }
+        Fx -= m.drag * r.rho * r.ux;
+        Fy -= m.drag * r.rho * r.uy;
+        r.Fx = Fx;
+        r.Fy = Fy;
         r.p = r.rho * (1.0f / 3.0f);
         float dxx, dxy, dyx, dyy;
         grad30a<BC>(m, hx, x, y, dxx, dxy);
@@ -211,6 +227,83 @@ __global__ __launch_bounds__(256) void sp_step_kernel(SpModel m, const float* __
     }
 }
 
+// Remark 4 (nearly incompressible model): first pass, the force distribution G_i(x, t) of every
+// node (eq. 27, with the macroscopics of f~) into the G planes, and the velocity into the
+// history for the next step's div u.
+template <bool FULL, int BC>
+__global__ __launch_bounds__(256) void sp_r4_force_kernel(SpModel m, const float* __restrict__ gin,
+                                                          const float* __restrict__ Sf,
+                                                          const float* __restrict__ Fxf,
+                                                          const float* __restrict__ Fyf,
+                                                          const float* __restrict__ hx_in,
+                                                          const float* __restrict__ hy_in,
+                                                          float* __restrict__ h_out0,
+                                                          float* __restrict__ h_out1,
+                                                          float* __restrict__ Gout) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= m.nx || y >= m.ny) return;
+    const long long P = m.plane, c = (long long)y * m.pitch + x;
+    float g[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) g[q] = gin[q * P + c];
+    const Macro r = sp_macro<0, FULL, BC>(m, g, Sf[c], Fxf[c], Fyf[c], hx_in, hy_in, x, y, c);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const int cx = kCX[q], cy = kCY[q];
+        const float cxx = cx * cx - (1.0f / 3.0f), cyy = cy * cy - (1.0f / 3.0f), cxy = (float)(cx * cy);
+        Gout[q * P + c] = wq(q) * (r.S + 3.0f * (cx * r.Fx + cy * r.Fy) +
+                                   4.5f * (cxx * r.axx + 2.0f * cxy * r.axy + cyy * r.ayy));
+    }
+    h_out0[c] = r.ux;
+    h_out1[c] = r.uy;
+}
+
+// Remark 4, second pass: f~* = f~ - (f~ - f^eq)/tau + G_i(x, t) + [G_i(x + c_i, t) - G_i(x, t-1)]/2
+// and push to x + c_i. G_i(x + c_i) across a wall link is G_i(x); before the first step
+// G(t-1) = G(t) (Gprev == Gcur).
+template <int BC>
+__global__ __launch_bounds__(256) void sp_r4_collide_kernel(SpModel m, const float* __restrict__ gin,
+                                                            float* __restrict__ gout,
+                                                            const float* __restrict__ Gcur,
+                                                            const float* __restrict__ Gprev) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= m.nx || y >= m.ny) return;
+    const long long P = m.plane, c = (long long)y * m.pitch + x;
+    float g[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) g[q] = gin[q * P + c];
+    const float sum = (((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]))) + g[8];
+    const float mx = ((g[1] - g[3]) + (g[5] - g[7])) + (g[8] - g[6]);
+    const float my = ((g[2] - g[4]) + (g[5] - g[7])) + (g[6] - g[8]);
+    const float drho = sum, rho = 1.0f + drho, irho = __builtin_amdgcn_rcpf(rho);
+    const float ux = mx * irho, uy = my * irho, u2 = ux * ux + uy * uy;
+    const int xp = (x + 1 == m.nx) ? 0 : x + 1, xm = (x == 0) ? m.nx - 1 : x - 1;
+    const int yp = (y + 1 == m.ny) ? 0 : y + 1, ym = (y == 0) ? m.ny - 1 : y - 1;
+    const bool wall_top = BC == 1 && y == m.ny - 1, wall_bot = BC == 1 && y == 0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+        const float w = wq(q);
+        const int cx = kCX[q], cy = kCY[q];
+        const float cu = cx * ux + cy * uy;
+        const float geq = drho * w + rho * w * (3.0f * cu + 4.5f * cu * cu - 1.5f * u2);
+        int dx = cx > 0 ? xp : (cx < 0 ? xm : x);
+        int dy = cy > 0 ? yp : (cy < 0 ? ym : y);
+        const bool wall = (cy > 0 && wall_top) || (cy < 0 && wall_bot);
+        const long long cn = wall ? c : (long long)dy * m.pitch + dx;
+        const float Gc = Gcur[q * P + c], Gn = Gcur[q * P + cn], Gp = Gprev[q * P + c];
+        const float gst = g[q] - (g[q] - geq) * m.omega + Gc + 0.5f * (Gn - Gp);
+        int dq = q;
+        if (wall) {
+            dx = x;
+            dy = y;
+            dq = kOpp[q];
+        }
+        gout[dq * P + (long long)dy * m.pitch + dx] = gst;
+    }
+}
+
 // Macroscopic field of the current state (no collision): 0 rho, 1 ux, 2 uy, 3 p
 template <int MODEL, bool FULL, int BC>
 __global__ __launch_bounds__(256) void sp_field_kernel(SpModel m, const float* __restrict__ gin,
@@ -287,10 +380,18 @@ __global__ __launch_bounds__(256) void sp_sum_partial_kernel(SpModel m, const fl
             my += kCY[q] * v;
         }
         const double S = Sf[c];
-        a0 += (MODEL == 0 ? 1.0 : (double)m.rho0) + s + 0.5 * S;
-        // rho u = sum_i c_i g_i + F/2 (eq. 27a; rho = 1 in model 1)
-        a1 += mx + 0.5 * (double)Fxf[c];
-        a2 += my + 0.5 * (double)Fyf[c];
+        if (MODEL == 0 && m.scheme == 1) {
+            // Remark 4: rho~ = sum f~, rho u = sum c f~
+            a0 += 1.0 + s;
+            a1 += mx;
+            a2 += my;
+        } else {
+            a0 += (MODEL == 0 ? 1.0 : (double)m.rho0) + s + 0.5 * S;
+            // rho u = (sum_i c_i g_i + F_ext/2) / (1 + lambda/2) (eq. 27a; rho = 1 in model 1)
+            const double d = 1.0 + 0.5 * (double)m.drag;
+            a1 += (mx + 0.5 * (double)Fxf[c]) / d;
+            a2 += (my + 0.5 * (double)Fyf[c]) / d;
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
         a0 += __shfl_xor(a0, o);
@@ -353,6 +454,10 @@ static const char* sp_validate(const lbpf_sp_params* p) {
     if (!(p->nu > 0.0) || !std::isfinite(p->nu)) return "nu must be > 0";
     if (!std::isfinite(p->xi) || p->xi < 0.0) return "xi must be finite and >= 0";
     if (!std::isfinite(p->rho0)) return "rho0 must be finite";
+    if (!std::isfinite(p->drag) || p->drag < 0.0) return "drag must be finite and >= 0";
+    if (p->drag != 0.0 && p->model != LBPF_SP_NEARLY_INCOMPRESSIBLE) return "drag is defined for the nearly incompressible model";
+    if (p->scheme != 0 && p->scheme != 1) return "scheme must be 0 (eq. 24) or 1 (Remark 4)";
+    if (p->scheme == 1 && p->model != LBPF_SP_NEARLY_INCOMPRESSIBLE) return "Remark 4's scheme is defined for the nearly incompressible model";
     const long long pitch = (p->nx + 63) / 64 * 64;
     if ((long long)p->ny * pitch + kPad >= (1LL << 30)) return "grid too large (a plane must hold fewer than 2^30 floats)";
     return nullptr;
@@ -360,13 +465,15 @@ static const char* sp_validate(const lbpf_sp_params* p) {
 
 static long long sp_plane(const lbpf_sp_params* p) { return (long long)p->ny * ((p->nx + 63) / 64 * 64) + kPad; }
 
+static int sp_num_planes(const lbpf_sp_params* p) { return p->scheme == 1 ? kNumPlanesR4 : kNumPlanes; }
+
 static size_t sp_ws_bytes(const lbpf_sp_params* p) {
-    return (size_t)sp_plane(p) * kNumPlanes * sizeof(float) + (size_t)(3 * kRedBlocks + 8) * sizeof(double);
+    return (size_t)sp_plane(p) * sp_num_planes(p) * sizeof(float) + (size_t)(3 * kRedBlocks + 8) * sizeof(double);
 }
 
 static float* sp_plane_ptr(lbpf_sp* s, int k) { return reinterpret_cast<float*>(s->ws) + (size_t)k * s->m.plane; }
 static double* sp_red(lbpf_sp* s) {
-    return reinterpret_cast<double*>(s->ws + (size_t)s->m.plane * kNumPlanes * sizeof(float));
+    return reinterpret_cast<double*>(s->ws + (size_t)s->m.plane * sp_num_planes(&s->params) * sizeof(float));
 }
 
 // History planes at step n: the previous step's velocity (nearly incompressible) or pressure
@@ -405,6 +512,21 @@ static void sp_launch_step(lbpf_sp* s, const SpHist& h, dim3 grid) {
                        sp_plane_ptr(s, kPlaneS), sp_plane_ptr(s, kPlaneFx), sp_plane_ptr(s, kPlaneFy),
                        h.hx, h.hy, h.o0, h.o1);
 }
+// Remark 4: G of this step into G copy (n & 1), then the collision reading it and the other copy
+template <bool FULL, int BC>
+static void sp_launch_r4(lbpf_sp* s, const SpHist& h, dim3 grid) {
+    const int a = s->cur, b = 1 - a;
+    const int gc = (int)(s->step & 1);
+    float* Gc = sp_plane_ptr(s, kPlaneG + 9 * gc);
+    const float* Gp = s->step == 0 ? Gc : sp_plane_ptr(s, kPlaneG + 9 * (1 - gc));
+    const float* gin = sp_plane_ptr(s, a ? kPlaneGB : kPlaneGA);
+    hipLaunchKernelGGL((sp_r4_force_kernel<FULL, BC>), grid, dim3(256), 0, s->stream, s->m, gin,
+                       sp_plane_ptr(s, kPlaneS), sp_plane_ptr(s, kPlaneFx), sp_plane_ptr(s, kPlaneFy),
+                       h.hx, h.hy, h.o0, h.o1, Gc);
+    hipLaunchKernelGGL((sp_r4_collide_kernel<BC>), grid, dim3(256), 0, s->stream, s->m, gin,
+                       sp_plane_ptr(s, b ? kPlaneGB : kPlaneGA), (const float*)Gc, Gp);
+}
+
 template <int MODEL, bool FULL, int BC>
 static void sp_launch_field(lbpf_sp* s, const SpHist& h, dim3 grid, int field, float* dst) {
     hipLaunchKernelGGL((sp_field_kernel<MODEL, FULL, BC>), grid, dim3(256), 0, s->stream, s->m,
@@ -466,6 +588,8 @@ lbpf_status lbpf_sp_create(const lbpf_sp_params* params, void* workspace, size_t
     const double pc = params->pscheme == 0 ? 0.8 * (tau - 0.5) : 0.0;  // (3/5)(tau - 1/2)(4/9) 3
     m.pc = (float)pc;
     m.ipc = (float)(1.0 / (1.0 + pc));
+    m.drag = (float)params->drag;
+    m.scheme = params->scheme;
     s->ws = static_cast<char*>(workspace);
     s->ws_bytes = workspace_bytes;
     s->stream = static_cast<hipStream_t>(hip_stream);
@@ -499,7 +623,15 @@ lbpf_status lbpf_sp_step(lbpf_sp* s, int64_t nsteps) {
     const dim3 grid = sp_grid(s);
     for (int64_t t = 0; t < nsteps; ++t) {
         const SpHist h = sp_hist(s);
-        LBPF_SP_DISPATCH(sp_launch_step, s, h, grid);
+        if (s->params.scheme == 1) {
+            if (s->params.full) {
+                if (s->params.bc) sp_launch_r4<true, 1>(s, h, grid); else sp_launch_r4<true, 0>(s, h, grid);
+            } else {
+                if (s->params.bc) sp_launch_r4<false, 1>(s, h, grid); else sp_launch_r4<false, 0>(s, h, grid);
+            }
+        } else {
+            LBPF_SP_DISPATCH(sp_launch_step, s, h, grid);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return spfail(s, LBPF_E_HIP, "step kernel: %s", hipGetErrorString(e));
         s->cur = 1 - s->cur;

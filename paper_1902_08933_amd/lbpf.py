@@ -564,7 +564,8 @@ class UNet:
 class SpParams(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("model", ctypes.c_int32),
                 ("pscheme", ctypes.c_int32), ("full", ctypes.c_int32), ("bc", ctypes.c_int32),
-                ("nu", ctypes.c_double), ("xi", ctypes.c_double), ("rho0", ctypes.c_double)]
+                ("nu", ctypes.c_double), ("xi", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("drag", ctypes.c_double), ("scheme", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 SP_MODELS = {"nearly_incompressible": 0, "incompressible": 1}
@@ -593,6 +594,8 @@ def make_sp_params(cfg):
     p.nu = float(cfg["nu"])
     p.xi = float(cfg.get("xi", 0.0))
     p.rho0 = float(cfg.get("rho0", 1.0))
+    p.drag = float(cfg.get("drag", 0.0))
+    p.scheme = {"eq24": 0, "remark4": 1}[cfg.get("scheme", "eq24")]
     return p
 
 

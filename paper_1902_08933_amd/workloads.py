@@ -178,12 +178,15 @@ def batch_instances(count=256, seed=0, side_min=64, side_max=512):
 
 
 def single_phase_source(nx=1024, ny=1024, model="incompressible", S0=1e-4, F0=0.0, nu=1.0 / 6.0,
-                        xi=0.0, full=True, bc="periodic", pscheme="eq28", seed=None):
+                        xi=0.0, full=True, bc="periodic", pscheme="eq28", seed=None, drag=0.0,
+                        scheme="eq24"):
     """Single-phase flow driven by a mass source (Sec. 2): S = S0 sin(2 pi x/nx) cos(2 pi y/ny),
-    a uniform force F0 in x, fluid at rest. With `seed`, the initial density (or pressure),
+    a uniform force F0 in x (minus drag * rho u if drag > 0), fluid at rest; scheme "eq24" or
+    "remark4" (Remark 4's explicit D_i G_i scheme, nearly incompressible model). With `seed`, the initial density (or pressure),
     velocity, source and force also carry small seeded smooth perturbations (parity cases).
     Returns (cfg, fields) with fields a dict of [ny, nx] float64 arrays (a0, ux, uy, S, Fx, Fy)."""
-    cfg = dict(nx=nx, ny=ny, model=model, nu=nu, xi=xi, full=full, bc=bc, pscheme=pscheme, rho0=1.0)
+    cfg = dict(nx=nx, ny=ny, model=model, nu=nu, xi=xi, full=full, bc=bc, pscheme=pscheme, rho0=1.0,
+               drag=drag, scheme=scheme)
     y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
     S = S0 * np.sin(2 * np.pi * x / nx) * np.cos(2 * np.pi * y / ny)
     Fx = np.full((ny, nx), float(F0))

@@ -18,6 +18,9 @@ CASES = [
     dict(model="incompressible", full=True, bc="periodic"),
     dict(model="incompressible", full=False, bc="periodic", pscheme="eq29"),
     dict(model="incompressible", full=True, bc="walls_y", xi=0.1),
+    dict(model="nearly_incompressible", full=True, bc="periodic", drag=0.05),
+    dict(model="nearly_incompressible", full=True, bc="periodic", scheme="remark4", drag=0.02),
+    dict(model="nearly_incompressible", full=False, bc="walls_y", scheme="remark4"),
 ]
 
 
@@ -62,11 +65,12 @@ def test_parity_after_100_steps(case):
     assert eu < 1e-5
 
 
-@pytest.mark.parametrize("model", ["nearly_incompressible", "incompressible"])
-def test_device_sums_follow_the_exact_balances(model):
+@pytest.mark.parametrize("model,scheme", [("nearly_incompressible", "eq24"), ("incompressible", "eq24"),
+                                          ("nearly_incompressible", "remark4")])
+def test_device_sums_follow_the_exact_balances(model, scheme):
     import torch
     from paper_1902_08933_amd import lbpf
-    cfg, fld = W.single_phase_source(96, 80, model=model, S0=1e-4, F0=2e-6, seed=7)
+    cfg, fld = W.single_phase_source(96, 80, model=model, S0=1e-4, F0=2e-6, seed=7, scheme=scheme)
     fld = {k: f32(v) for k, v in fld.items()}
     gpu = lbpf.SinglePhase(cfg).init(*(torch.from_numpy(fld[k].astype(np.float32)).cuda()
                                        for k in ("a0", "ux", "uy", "S", "Fx", "Fy")))
@@ -74,7 +78,8 @@ def test_device_sums_follow_the_exact_balances(model):
     n = 200
     gpu.step(n)
     s1 = gpu.sums()
-    # sum rho u grows by sum F per step (both models); sum rho~ by sum S (Remark 1 only)
+    # sum rho u grows by sum F per step (both models; with a constant force also under
+    # Remark 4, whose Adams-Bashforth increment is then sum F); sum rho~ by sum S (model 0)
     assert abs(s1["mom_x"] - s0["mom_x"] - n * fld["Fx"].sum()) < 1e-4 * abs(n * fld["Fx"].sum())
     assert abs(s1["mom_y"] - s0["mom_y"] - n * fld["Fy"].sum()) < 1e-4 * abs(n * fld["Fx"].sum())
     if model == "nearly_incompressible":
