@@ -4,7 +4,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "lbpf_oracle.c"), os.path.join(HERE, "sp_oracle.c")]
+SRCS = [os.path.join(HERE, "lbpf_oracle.c"), os.path.join(HERE, "sp_oracle.c"),
+        os.path.join(HERE, "d3q15_oracle.c")]
 LIB = os.path.join(HERE, "liblbpf_oracle.so")
 
 

@@ -22,6 +22,21 @@ if [ "$W" = "sp1024" ]; then
         --out "$PROF/sp_step_sp1024_trace.txt"
     exit $?
 fi
+if [ "$W" = "r4_1024" ]; then
+    # single-phase Remark 4 scheme with drag at 1024^2: G pass (100 B/node) and collision (144 B/node)
+    OUT=gpurun_out/prof_r4_1024
+    PROF=${PROFILE_OUT:-profiles}
+    mkdir -p "$OUT" "$PROF"
+    export TMPDIR=/tmp
+    CMD="python3 -m paper_1902_08933_amd.profile_step --workload r4_1024 --steps 100 --warmup 10"
+    echo "profile: kernel trace r4_1024" && \
+    timeout -k 10 180 rocprofv3 --kernel-trace --stats -d "$OUT/trace" -o run -- $CMD > "$OUT/trace.log" 2>&1 && \
+    python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --cells 1048576 \
+        --kernel sp_r4_collide_kernel --alg-bytes-per-cell 144 --sources sp \
+        --command "bash paper_1902_08933_amd/profile_run.sh r4_1024  (rocprofv3 --kernel-trace --stats -- $CMD)" \
+        --out "$PROF/sp_remark4_r4_1024_trace.txt"
+    exit $?
+fi
 if [ "$W" = "unet1024" ]; then
     # surrogate forward pass at 1024^2: kernel trace of 1 + 10 forwards (214 GFLOP each)
     OUT=gpurun_out/prof_unet1024

@@ -2,6 +2,7 @@
 
 python -m paper_1902_08933_amd.profile_step --workload spinodal4096 --steps 20
 python -m paper_1902_08933_amd.profile_step --workload spinodal1024 --sweep
+python -m paper_1902_08933_amd.profile_step --workload r4_1024   (Remark 4 scheme, single phase)
 python -m paper_1902_08933_amd.profile_step --copy-mib 2048 --steps 10   (bandwidth probe:
     copy / read / write of a known byte count, the reference for the HBM roofline and for
     scaling the FETCH_SIZE / WRITE_SIZE counters)
@@ -25,10 +26,15 @@ def make(name, variant):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_sp(torch, n, steps, warmup):
-    """single-phase step with a mass source, incompressible, full force term"""
+def run_sp(torch, n, steps, warmup, remark4=False):
+    """single-phase step with a mass source and the full force term: the incompressible model, or
+    (remark4) the nearly incompressible model on the explicit D_i G_i scheme with a linear drag"""
     import numpy as np
-    cfg, f = workloads.single_phase_source(n, n, model="incompressible", S0=1e-4, F0=1e-6, full=True)
+    if remark4:
+        cfg, f = workloads.single_phase_source(n, n, model="nearly_incompressible", S0=1e-4, F0=1e-6,
+                                               full=True, scheme="remark4", drag=0.01)
+    else:
+        cfg, f = workloads.single_phase_source(n, n, model="incompressible", S0=1e-4, F0=1e-6, full=True)
     sim = lbpf.SinglePhase(cfg).init(*(torch.from_numpy(f[k].astype(np.float32)).cuda()
                                        for k in ("a0", "ux", "uy", "S", "Fx", "Fy")))
     sim.step(warmup)
@@ -89,11 +95,13 @@ def main():
                 print(f"probe {name} {a.copy_mib} MiB, {blocks} workgroups: {ms:.4f} ms, "
                       f"{moved * nbytes / ms / 1e6:.1f} GB/s", flush=True)
         return
-    if a.workload.startswith("sp"):
-        n = int(a.workload[2:])
-        ms = run_sp(torch, n, a.steps, a.warmup)
+    if a.workload.startswith("sp") or a.workload.startswith("r4_"):
+        r4 = a.workload.startswith("r4_")
+        n = int(a.workload[3:] if r4 else a.workload[2:])
+        ms = run_sp(torch, n, a.steps, a.warmup, remark4=r4)
+        b = 244 if r4 else 92
         print(f"{a.workload}: {ms:.4f} ms/step, {n * n / (ms * 1e-3) / 1e6:.0f} MLUPS, "
-              f"{92 * n * n / (ms * 1e-3) / 1e9:.0f} GB/s", flush=True)
+              f"{b * n * n / (ms * 1e-3) / 1e9:.0f} GB/s", flush=True)
         return 0
     cfg, phi = make(a.workload, a.variant)
     cells = cfg["nx"] * cfg["ny"]

@@ -211,3 +211,53 @@ def single_phase_source(nx=1024, ny=1024, model="incompressible", S0=1e-4, F0=0.
         S = S + smooth(S0) + 0.2 * S0
         Fx, Fy = Fx + smooth(1e-5), smooth(1e-5)
     return cfg, dict(a0=a0, ux=ux, uy=uy, S=S, Fx=Fx, Fy=Fy)
+
+
+# ---- three-dimensional workloads (D3Q15 solver): arrays shaped [nz, ny, nx] ----------------
+
+BASE3D = dict(BASE, bc="periodic", force_z=0.0)
+
+
+def spinodal3d(n=256, variant="qim", seed=0, rho_ratio=3.0, sigma=0.03, W=4.0, M_phi=0.1,
+               tau_h=1.0, nu_B=1.0 / 6.0, nu_ratio=0.1, mean=0.5, amplitude=0.005, nz=None,
+               ny=None):
+    """Spinodal decomposition in a periodic n x n x n box (nz, ny override two sides): the
+    two-dimensional spinodal workload's parameters, phi = mean + U[-amplitude, amplitude]."""
+    nz = n if nz is None else nz
+    ny = n if ny is None else ny
+    cfg = dict(BASE3D, name="spinodal3d", nx=n, ny=ny, nz=nz, variant=variant, rho_A=rho_ratio,
+               rho_B=1.0, nu_A=nu_B * nu_ratio, nu_B=nu_B, sigma=sigma, W=W, M_phi=M_phi,
+               tau_h=tau_h, seed=seed)
+    rng = np.random.default_rng(seed)
+    phi = mean + rng.uniform(-amplitude, amplitude, size=(nz, ny, n))
+    return cfg, phi
+
+
+def sphere_phi(nx, ny, nz, R, W, centre=None, cylinder=False):
+    """phi = 1/2 + 1/2 tanh(2 (R - r) / W) around the centre with the periodic (minimum-image)
+    distance; cylinder=True measures r in the x-y plane only (a column along z)."""
+    c = (nx / 2.0, ny / 2.0, nz / 2.0) if centre is None else centre
+    d = []
+    for n_, c_, shape in ((nx, c[0], (1, 1, nx)), (ny, c[1], (1, ny, 1)), (nz, c[2], (nz, 1, 1))):
+        a = np.abs(np.arange(n_, dtype=np.float64) - c_)
+        d.append(np.minimum(a, n_ - a).reshape(shape))
+    r2 = d[0] ** 2 + d[1] ** 2 + (0.0 if cylinder else d[2] ** 2)
+    r = np.sqrt(np.broadcast_to(r2, (nz, ny, nx)))
+    return 0.5 + 0.5 * np.tanh(2.0 * (R - r) / W)
+
+
+def static_droplet3d(n=32, R=8.0, variant="qim", rho_ratio=10.0, sigma=0.01, tau=0.8,
+                     tau_h=0.8, M_phi=0.02, W=4.0, cylinder=False):
+    """Static droplet of phase A in an n^3 periodic box (the two-dimensional static-droplet
+    parameters, F_s = -phi grad mu); cylinder=True gives a column of radius R along z."""
+    cfg = dict(BASE3D, name="static_droplet3d", nx=n, ny=n, nz=n, variant=variant,
+               fsurf="neg_phi_grad_mu", rho_A=rho_ratio, rho_B=1.0, nu_A=nu_from_tau(tau),
+               nu_B=nu_from_tau(tau), sigma=sigma, W=W, M_phi=M_phi, tau_h=tau_h, R=R)
+    return cfg, sphere_phi(n, n, n, R, W, cylinder=cylinder)
+
+
+def plane_phi3d(nx, ny, nz, W, z0=None):
+    """Flat interface normal to z at height z0 (equilibrium profile of eq. 9), A above."""
+    z0 = nz / 2.0 if z0 is None else z0
+    z = np.arange(nz, dtype=np.float64)[:, None, None] - z0
+    return np.broadcast_to(0.5 + 0.5 * np.tanh(2.0 * z / W), (nz, ny, nx)).copy()
