@@ -349,6 +349,75 @@ int64_t lbpf_sp_step_count(const lbpf_sp* sp);
 lbpf_status lbpf_sp_destroy(lbpf_sp* sp);
 const char* lbpf_sp_last_error(const lbpf_sp* sp);
 
+/* ============================================================================================
+ * Three-dimensional two-phase solver on the D3Q15 lattice (Sec. 2.2, velocity matrix after
+ * eq. 25: w_0 = 2/9, w_1-6 = 1/9, w_7-14 = 1/72, c_s^2 = 1/3). Same method as lbpf_ctx (eq. (24)
+ * with eqs. (33), (34) at d = 3, (27a), (28) / (29); eq. (10) with eqs. (11), (14), (18); the
+ * closure of Sec. 3.1; eqs. (30a)-(30b) over the fourteen D3Q15 neighbours), same conventions
+ * (caller-owned device workspace, caller's stream, status codes, one host thread per handle).
+ * Grids are [nz][ny][nx] with x fastest. Boundaries: fully periodic, or periodic in x and y with
+ * halfway bounce-back walls half a cell below plane z = 0 and above plane z = nz - 1 (stencil
+ * ghosts mirror the first fluid plane); buoyancy acts along -z: F_z = -(rho - rho_A) g.
+ * ============================================================================================ */
+typedef enum { LBPF3D_BC_PERIODIC = 0, LBPF3D_BC_WALLS_Z = 1 } lbpf3d_bc;
+
+/* Fields of lbpf3d_read: phi (eq. 18), rho (eq. 3aa), u (eq. 27a), p (eq. 28 / 29), mu (eq. 8) */
+typedef enum {
+    LBPF3D_FIELD_PHI = 0, LBPF3D_FIELD_RHO = 1, LBPF3D_FIELD_UX = 2, LBPF3D_FIELD_UY = 3,
+    LBPF3D_FIELD_UZ = 4, LBPF3D_FIELD_P = 5, LBPF3D_FIELD_MU = 6
+} lbpf3d_field;
+
+typedef struct lbpf3d_params {
+    int32_t nx, ny, nz;     /* 3 <= side < 2^24 and nz * ny * pitch(nx) + 4160 < 2^30,
+                             * pitch(nx) = nx rounded up to a multiple of 64 */
+    int32_t variant;        /* lbpf_variant */
+    int32_t pscheme;        /* lbpf_pscheme (the simplified G_0 uses d = 3) */
+    int32_t fsurf;          /* lbpf_fsurf */
+    int32_t visc;           /* lbpf_visc */
+    int32_t bc;             /* lbpf3d_bc */
+    int32_t clamp_props;    /* nonzero: phi clamped to [0,1] in rho(phi), nu(phi) */
+    int32_t pad;
+    double rho_A, rho_B, nu_A, nu_B, sigma, W, M_phi, tau_h; /* as in lbpf_params */
+    double force_x, force_y, force_z; /* constant body-force density */
+    double gravity;         /* buoyancy F_z = -(rho - rho_A) * gravity */
+} lbpf3d_params;
+
+typedef struct lbpf3d lbpf3d;
+
+/* Bytes of device workspace (72 planes of nz * ny * pitch(nx) + 4160 floats: two copies of
+ * g_1..14 and of h_0 hi, h_1..14, h_0 lo, two pressure copies, (phi u), seven field planes;
+ * then the FP64 reduction area). LBPF_E_INVALID for invalid params. */
+lbpf_status lbpf3d_workspace_size(const lbpf3d_params* params, size_t* bytes);
+/* Validate params (as lbpf_create, plus nz) and bind a handle to a caller-owned device
+ * workspace (256-byte aligned, at least lbpf3d_workspace_size bytes, else LBPF_E_NOMEM) and
+ * stream. On failure *out is NULL and lbpf3d_last_error(NULL) says why. */
+lbpf_status lbpf3d_create(const lbpf3d_params* params, void* workspace, size_t workspace_bytes,
+                          void* hip_stream, lbpf3d** out);
+/* Initial state from device arrays [nz][ny][nx] FP32 (ux, uy, uz, p may be NULL for zero):
+ * h = h^eq(phi0, mu0, u0) (eq. 11, mu0 by eq. 8), g = g^eq(p0, rho(phi0), u0) (eq. 33); the
+ * (phi u) and pressure histories start at phi0 u0 and p0. Resets the step count. Async. */
+lbpf_status lbpf3d_init(lbpf3d* c, const float* phi, const float* ux, const float* uy,
+                        const float* uz, const float* p);
+/* Advance nsteps >= 0 steps, one launch each. Async. */
+lbpf_status lbpf3d_step(lbpf3d* c, int64_t nsteps);
+/* One lbpf3d_field of the current state into a device array [nz][ny][nx] FP32. Async. */
+lbpf_status lbpf3d_read(lbpf3d* c, int32_t field, float* dst);
+/* FP64 sums over the grid (sum phi of the stored h, sum rho), max |u| and the count of
+ * non-finite stored values; synchronizes the stream; LBPF_E_UNSTABLE when that count is > 0. */
+lbpf_status lbpf3d_diagnostics(lbpf3d* c, lbpf_diag* out);
+/* Launch shapes: TX x TY tile of the x-y plane per workgroup (TX * TY threads), CZ planes per
+ * chunk. Every shape gives bit-identical results. */
+int32_t lbpf3d_shape_count(void);
+lbpf_status lbpf3d_shape_info(int32_t shape, int32_t* tx, int32_t* ty, int32_t* cz);
+lbpf_status lbpf3d_set_shape(lbpf3d* c, int32_t shape);
+int32_t lbpf3d_get_shape(const lbpf3d* c);
+/* Time each shape for `steps` steps on the current state (which advances) and keep the
+ * fastest; *best_shape receives it. Synchronizes the stream. */
+lbpf_status lbpf3d_autotune(lbpf3d* c, int32_t steps, int32_t* best_shape);
+int64_t lbpf3d_step_count(const lbpf3d* c);
+lbpf_status lbpf3d_destroy(lbpf3d* c);
+const char* lbpf3d_last_error(const lbpf3d* c);
+
 #ifdef __cplusplus
 }
 #endif

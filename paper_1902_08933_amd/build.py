@@ -20,7 +20,8 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang
                 "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 
-SOURCES = ["lbpf_kernels.hip", "lbpf_api.cpp", "lbpf_unet_kernels.hip", "lbpf_unet.cpp", "lbpf_sp.hip"]
+SOURCES = ["lbpf_kernels.hip", "lbpf_api.cpp", "lbpf_unet_kernels.hip", "lbpf_unet.cpp", "lbpf_sp.hip",
+           "lbpf_d3q15.hip"]
 
 
 def _run(cmd, verbose):

@@ -669,3 +669,154 @@ class SinglePhase:
     @property
     def step_count(self):
         return int(self.lib.lbpf_sp_step_count(self._h))
+
+
+# ---- three-dimensional solver (D3Q15) ------------------------------------------------------
+
+class Params3D(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("pscheme", ctypes.c_int32), ("fsurf", ctypes.c_int32),
+                ("visc", ctypes.c_int32), ("bc", ctypes.c_int32), ("clamp_props", ctypes.c_int32),
+                ("pad", ctypes.c_int32)] + \
+               [(k, ctypes.c_double) for k in ("rho_A", "rho_B", "nu_A", "nu_B", "sigma", "W",
+                                               "M_phi", "tau_h", "force_x", "force_y", "force_z",
+                                               "gravity")]
+
+
+FIELDS3D = {"phi": 0, "rho": 1, "ux": 2, "uy": 3, "uz": 4, "p": 5, "mu": 6}
+BCS3D = {"periodic": 0, "walls_z": 1}
+_P3 = ctypes.POINTER(Params3D)
+_I32P = ctypes.POINTER(ctypes.c_int32)
+SIGNATURES.update({
+    "lbpf3d_workspace_size": (_S, [_P3, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbpf3d_create": (_S, [_P3, _V, ctypes.c_size_t, _V, ctypes.POINTER(_V)]),
+    "lbpf3d_init": (_S, [_V, _V, _V, _V, _V, _V]),
+    "lbpf3d_step": (_S, [_V, ctypes.c_int64]),
+    "lbpf3d_read": (_S, [_V, ctypes.c_int32, _V]),
+    "lbpf3d_diagnostics": (_S, [_V, ctypes.POINTER(Diag)]),
+    "lbpf3d_shape_count": (ctypes.c_int32, []),
+    "lbpf3d_shape_info": (_S, [ctypes.c_int32, _I32P, _I32P, _I32P]),
+    "lbpf3d_set_shape": (_S, [_V, ctypes.c_int32]),
+    "lbpf3d_get_shape": (ctypes.c_int32, [_V]),
+    "lbpf3d_autotune": (_S, [_V, ctypes.c_int32, _I32P]),
+    "lbpf3d_step_count": (ctypes.c_int64, [_V]),
+    "lbpf3d_destroy": (_S, [_V]),
+    "lbpf3d_last_error": (ctypes.c_char_p, [_V]),
+})
+
+
+def make_params3d(cfg):
+    p = Params3D()
+    p.nx, p.ny, p.nz = int(cfg["nx"]), int(cfg["ny"]), int(cfg["nz"])
+    p.variant = VARIANTS[cfg.get("variant", "qim")]
+    p.pscheme = PSCHEMES[cfg.get("pscheme", "eq28")]
+    p.fsurf = FSURF[cfg.get("fsurf", "mu_grad_phi")]
+    p.visc = VISC[cfg.get("visc", "inverse_linear")]
+    p.bc = BCS3D[cfg.get("bc", "periodic")]
+    p.clamp_props = int(bool(cfg.get("clamp_props", False)))
+    for k in ("rho_A", "rho_B", "nu_A", "nu_B", "sigma", "W", "M_phi", "tau_h"):
+        setattr(p, k, float(cfg[k]))
+    for k in ("force_x", "force_y", "force_z", "gravity"):
+        setattr(p, k, float(cfg.get(k, 0.0)))
+    return p
+
+
+def shapes3d():
+    lib = library()
+    out = []
+    for s in range(lib.lbpf3d_shape_count()):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        lib.lbpf3d_shape_info(s, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        out.append((a.value, b.value, c.value))
+    return out
+
+
+class Simulation3D:
+    """One D3Q15 two-phase simulation on one GPU: init fields [nz, ny, nx], step N, read fields,
+    FP64 diagnostics."""
+
+    def __init__(self, cfg, device="cuda"):
+        import torch
+        self.torch = torch
+        self.lib = library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lbpf solver runs only on the GPU")
+        self.device = torch.device(device)
+        self.cfg = dict(cfg)
+        self.params = make_params3d(cfg)
+        self.shape = (self.params.nz, self.params.ny, self.params.nx)
+        nb = ctypes.c_size_t()
+        st = self.lib.lbpf3d_workspace_size(ctypes.byref(self.params), ctypes.byref(nb))
+        if st != 0:
+            raise LbpfError(st, (self.lib.lbpf3d_last_error(None) or b"").decode())
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        h = ctypes.c_void_p()
+        st = self.lib.lbpf3d_create(ctypes.byref(self.params), ctypes.c_void_p(self.workspace.data_ptr()),
+                                    ctypes.c_size_t(nb.value), ctypes.c_void_p(stream), ctypes.byref(h))
+        if st != 0:
+            raise LbpfError(st, (self.lib.lbpf3d_last_error(None) or b"").decode())
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.lib.lbpf3d_destroy(h)
+            self._h = None
+
+    def _c(self, st):
+        if st != 0:
+            raise LbpfError(st, (self.lib.lbpf3d_last_error(self._h) or b"").decode())
+
+    def _as_field(self, a):
+        if a is None:
+            return None
+        t = self.torch.as_tensor(a, dtype=self.torch.float32, device=self.device).contiguous()
+        if tuple(t.shape) != self.shape:
+            raise ValueError(f"field shape {tuple(t.shape)} != {self.shape}")
+        return t
+
+    def init(self, phi, ux=None, uy=None, uz=None, p=None):
+        ts = [self._as_field(a) for a in (phi, ux, uy, uz, p)]
+        self._c(self.lib.lbpf3d_init(self._h, *[ctypes.c_void_p(t.data_ptr()) if t is not None else None
+                                                 for t in ts]))
+        self.torch.cuda.current_stream(self.device).synchronize()  # the inputs may be temporaries
+        return self
+
+    def step(self, n=1):
+        self._c(self.lib.lbpf3d_step(self._h, int(n)))
+        return self
+
+    def read(self, field, out=None):
+        t = out if out is not None else self.torch.empty(self.shape, dtype=self.torch.float32,
+                                                          device=self.device)
+        if tuple(t.shape) != self.shape or t.dtype != self.torch.float32 or not t.is_contiguous():
+            raise ValueError("output must be a contiguous float32 tensor of the grid's shape")
+        self._c(self.lib.lbpf3d_read(self._h, FIELDS3D[field], ctypes.c_void_p(t.data_ptr())))
+        return t
+
+    def diagnostics(self, check=True):
+        d = Diag()
+        st = self.lib.lbpf3d_diagnostics(self._h, ctypes.byref(d))
+        if check:
+            self._c(st)
+        return dict(sum_phi=d.sum_phi, sum_rho=d.sum_rho, max_u=d.max_u, nonfinite=d.nonfinite,
+                    step=d.step, status=st)
+
+    def set_shape(self, s):
+        self._c(self.lib.lbpf3d_set_shape(self._h, int(s)))
+        return self
+
+    @property
+    def launch_shape(self):
+        return int(self.lib.lbpf3d_get_shape(self._h))
+
+    def autotune(self, trial_steps=5):
+        """Time every launch shape (the state advances by the steps taken); keep the fastest."""
+        best = ctypes.c_int32()
+        self._c(self.lib.lbpf3d_autotune(self._h, int(trial_steps), ctypes.byref(best)))
+        return best.value
+
+    @property
+    def step_count(self):
+        return int(self.lib.lbpf3d_step_count(self._h))

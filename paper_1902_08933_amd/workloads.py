@@ -218,11 +218,13 @@ def single_phase_source(nx=1024, ny=1024, model="incompressible", S0=1e-4, F0=0.
 BASE3D = dict(BASE, bc="periodic", force_z=0.0)
 
 
-def spinodal3d(n=256, variant="qim", seed=0, rho_ratio=3.0, sigma=0.03, W=4.0, M_phi=0.1,
+def spinodal3d(n=256, variant="qim", seed=0, rho_ratio=3.0, sigma=0.03, W=4.0, M_phi=0.01,
                tau_h=1.0, nu_B=1.0 / 6.0, nu_ratio=0.1, mean=0.5, amplitude=0.005, nz=None,
                ny=None):
     """Spinodal decomposition in a periodic n x n x n box (nz, ny override two sides): the
-    two-dimensional spinodal workload's parameters, phi = mean + U[-amplitude, amplitude]."""
+    two-dimensional spinodal workload's parameters, phi = mean + U[-amplitude, amplitude],
+    except the mobility M_phi = 0.01 (the two-dimensional 0.1 makes the quasi-incompressible
+    three-dimensional scheme unstable: velocities grow within tens of steps, in FP64 as well)."""
     nz = n if nz is None else nz
     ny = n if ny is None else ny
     cfg = dict(BASE3D, name="spinodal3d", nx=n, ny=ny, nz=nz, variant=variant, rho_A=rho_ratio,

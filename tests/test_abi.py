@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "lbpf.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbpf_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lbpf[0-9a-z]*_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -98,3 +98,54 @@ def test_tile_shapes_listed(lib):
     assert len(shapes) >= 4
     for tx, rows, nt in shapes:
         assert nt % tx == 0 and nt // tx >= 2 and rows % (nt // tx) == 0
+
+
+def test_params3d_struct_layout_matches_header():
+    # 10 int32 fields then 12 doubles, no padding
+    assert ctypes.sizeof(lbpf.Params3D) == 10 * 4 + 12 * 8
+
+
+def _cfg3d(**kw):
+    c = dict(nx=64, ny=48, nz=40, rho_A=3, rho_B=1, nu_A=0.01, nu_B=0.1, sigma=0.03, W=4,
+             M_phi=0.01, tau_h=1)
+    c.update(kw)
+    return c
+
+
+def test_workspace3d_size(lib):
+    n = ctypes.c_size_t()
+    p = lbpf.make_params3d(_cfg3d())
+    assert lib.lbpf3d_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    plane = 40 * 48 * 64 + 4160
+    assert n.value >= 72 * plane * 4
+
+
+@pytest.mark.parametrize("bad", [dict(nz=2), dict(nx=1 << 24), dict(tau_h=0.5), dict(nu_A=0.0),
+                                 dict(bc=2), dict(nx=1024, ny=1024, nz=1024), dict(W=0.0)])
+def test_invalid_3d_parameters_rejected(lib, bad):
+    cfg = _cfg3d(**{k: v for k, v in bad.items() if k != "bc"})
+    p = lbpf.make_params3d(cfg)
+    if "bc" in bad:
+        p.bc = bad["bc"]
+    n = ctypes.c_size_t()
+    assert lib.lbpf3d_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
+    assert lib.lbpf3d_last_error(None)
+    h = ctypes.c_void_p()
+    assert lib.lbpf3d_create(ctypes.byref(p), ctypes.c_void_p(256), ctypes.c_size_t(1 << 40), None,
+                             ctypes.byref(h)) == -1
+    assert not h.value
+
+
+def test_create3d_rejects_small_or_null_workspace(lib):
+    p = lbpf.make_params3d(_cfg3d())
+    h = ctypes.c_void_p()
+    assert lib.lbpf3d_create(ctypes.byref(p), None, ctypes.c_size_t(1 << 40), None, ctypes.byref(h)) == -1
+    assert lib.lbpf3d_create(ctypes.byref(p), ctypes.c_void_p(256), ctypes.c_size_t(1024), None,
+                             ctypes.byref(h)) == -3
+    assert not h.value
+
+
+def test_shapes3d_listed(lib):
+    shapes = lbpf.shapes3d()
+    assert len(shapes) >= 4 and all(tx * ty in (256, 512) for tx, ty, _ in shapes)
+    assert lib.lbpf3d_shape_info(len(shapes), None, None, None) == -1

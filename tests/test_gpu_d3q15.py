@@ -1,0 +1,143 @@
+"""Parity of the HIP D3Q15 solver with the FP64 CPU oracle, element by element on the same seeded
+inputs, through the C ABI.
+
+Tolerances as for the two-dimensional solver: relative L2 <= 1e-5 on phi and on
+u = (u_x, u_y, u_z) after 100 steps, relative drift of sum(phi) <= 1e-6; the pressure is held
+to 1e-4. At the benchmark size (256^3) the oracle cannot run the whole grid: the fields read
+after two steps depend only on the initial field within a radius of 9 nodes (the initial
+state uses phi0 at radius 1; a step pulls post-collision populations from radius 1 whose
+collisions use the state at radius 2, so 3 per step; the read uses the state at radius 2), so
+an oracle run on a 40^3 periodic crop reproduces the crop's inner 20^3 nodes exactly (one node
+of margin), and those are compared.
+"""
+import numpy as np
+import pytest
+
+import oracle.d3q15 as O
+from paper_1902_08933_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_PHI, TOL_U, TOL_P, TOL_DRIFT = 1e-5, 1e-5, 1e-4, 1e-6
+FIELDS = ("phi", "ux", "uy", "uz", "p", "rho", "mu")
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def gpu_sim(cfg, phi, shape=None):
+    import torch
+    from paper_1902_08933_amd import lbpf
+    sim = lbpf.Simulation3D(cfg)
+    if shape is not None:
+        sim.set_shape(shape)
+    sim.init(torch.from_numpy(np.ascontiguousarray(phi, dtype=np.float32)).cuda())
+    return sim
+
+
+def gpu_fields(sim, names=FIELDS):
+    return {f: sim.read(f).double().cpu().numpy() for f in names}
+
+
+def case(name):
+    if name == "spinodal_40x20x24_qim":
+        return W.spinodal3d(n=40, ny=20, nz=24, seed=5, amplitude=0.05)
+    if name == "spinodal_40x20x24_im_eq29":
+        c, p = W.spinodal3d(n=40, ny=20, nz=24, seed=6, amplitude=0.05, variant="im")
+        return dict(c, pscheme="eq29"), p
+    if name == "droplet_24_walls_gravity_paper_g0":
+        c, p = W.static_droplet3d(n=24, R=6.0, rho_ratio=5.0)
+        return dict(c, bc="walls_z", fsurf="mu_grad_phi", gravity=2e-6, force_x=1e-6, force_y=-5e-7,
+                    pscheme="eq28_paper_g0"), p
+    if name == "droplet_20x36x18_step_visc_clamp":
+        c, _ = W.static_droplet3d(n=20, R=5.0, rho_ratio=3.0)
+        c = dict(c, nx=20, ny=36, nz=18, visc="step", clamp_props=True, nu_A=0.05, nu_B=0.15)
+        return c, W.sphere_phi(20, 36, 18, 5.0, 4.0)
+    if name == "tiny_5x4x3_walls":
+        c, p = W.spinodal3d(n=5, ny=4, nz=3, seed=9, amplitude=0.2, variant="im")
+        return dict(c, bc="walls_z", force_z=1e-5), p
+    raise KeyError(name)
+
+
+CASES = ["spinodal_40x20x24_qim", "spinodal_40x20x24_im_eq29", "droplet_24_walls_gravity_paper_g0",
+         "droplet_20x36x18_step_visc_clamp", "tiny_5x4x3_walls"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_parity_100_steps(name):
+    cfg, phi = case(name)
+    phi = phi.astype(np.float32).astype(np.float64)  # the input both sides consume
+    print(f"d3q15 parity {name}", flush=True)
+    o = O.Oracle3D(cfg).init(phi)
+    o.step(100)
+    sim = gpu_sim(cfg, phi)
+    sim.step(100)
+    g = gpu_fields(sim)
+    ref = {f: o.read(f) for f in FIELDS}
+    e_phi = rel(g["phi"], ref["phi"])
+    U = np.stack([g[k] for k in ("ux", "uy", "uz")])
+    Ur = np.stack([ref[k] for k in ("ux", "uy", "uz")])
+    e_u = rel(U, Ur)
+    e_p = rel(g["p"], ref["p"])
+    print(f"  phi {e_phi:.2e}  u {e_u:.2e}  p {e_p:.2e}  |u|max {np.abs(Ur).max():.2e}", flush=True)
+    assert e_phi <= TOL_PHI and e_u <= TOL_U and e_p <= TOL_P
+    assert rel(g["rho"], ref["rho"]) <= TOL_PHI
+    d = sim.diagnostics()
+    assert abs(d["sum_phi"] - o.sum_phi()) / abs(o.sum_phi()) < 1e-8
+    assert d["step"] == 100 and d["nonfinite"] == 0
+
+
+def test_every_launch_shape_is_bit_identical():
+    from paper_1902_08933_amd import lbpf
+    cfg, phi = case("spinodal_40x20x24_qim")
+    cfg = dict(cfg, bc="walls_z")
+    ref = None
+    for s in range(len(lbpf.shapes3d())):
+        sim = gpu_sim(cfg, phi, shape=s)
+        sim.step(12)
+        f = gpu_fields(sim, ("phi", "ux", "uz", "p"))
+        if ref is None:
+            ref = f
+        else:
+            for k in f:
+                assert np.array_equal(f[k], ref[k]), (s, k)
+
+
+def test_order_parameter_drift_and_diagnostics():
+    # 64^3 spinodal, 1000 steps: FP64 sum of the stored order parameter
+    cfg, phi = W.spinodal3d(n=64, seed=1)
+    sim = gpu_sim(cfg, phi)
+    s0 = sim.diagnostics()["sum_phi"]
+    assert abs(s0 - phi.astype(np.float32).astype(np.float64).sum()) / s0 < 1e-7
+    sim.step(1000)
+    d = sim.diagnostics()
+    assert abs(d["sum_phi"] - s0) / s0 <= TOL_DRIFT
+    assert d["nonfinite"] == 0 and 0 < d["max_u"] < 0.1
+    rho = sim.read("rho").double().cpu().numpy()
+    assert abs(d["sum_rho"] - rho.sum()) / rho.sum() < 1e-6
+
+
+def test_full_size_sampled_against_oracle_crop():
+    # the benchmark workload (256^3 spinodal, autotuned launch shape), two steps; an oracle run
+    # on the 40^3 periodic crop around the grid corner (the crop wraps across all three periodic
+    # boundaries of the full grid) gives the exact values of its inner 20^3 nodes
+    cfg, phi = W.spinodal3d(n=256, seed=0)
+    sim = gpu_sim(cfg, phi)
+    shape = sim.autotune(2)
+    print(f"d3q15 full size: autotuned shape {shape}", flush=True)
+    sim = gpu_sim(cfg, phi, shape=shape)
+    sim.step(2)
+    g = gpu_fields(sim, ("phi", "ux", "uy", "uz", "p"))
+    idx = np.arange(-20, 20) % 256
+    crop = phi[np.ix_(idx, idx, idx)]
+    o = O.Oracle3D(dict(cfg, nx=40, ny=40, nz=40)).init(crop)
+    o.step(2)
+    inner = np.arange(10, 30)
+    sel = np.ix_(idx[inner], idx[inner], idx[inner])
+    for f, tol in (("phi", TOL_PHI), ("ux", TOL_U), ("uy", TOL_U), ("uz", TOL_U), ("p", TOL_P)):
+        ref = o.read(f)[np.ix_(inner, inner, inner)]
+        e = rel(g[f][sel], ref)
+        print(f"  {f} {e:.2e}", flush=True)
+        assert e <= tol, f
