@@ -21,15 +21,15 @@ BYTES_PER_CELL = 168   # f_1..8, h_0 hi, h_1..8, h_0 lo, p, (phi u)_x, (phi u)_y
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 
 
-def traffic_summary_path(workload):
-    return os.path.join(ROOT, "profiles", f"fused_step_{workload}_pmc.txt")
+def traffic_summary_path(workload, prefix="fused_step"):
+    return os.path.join(ROOT, "profiles", f"{prefix}_{workload}_pmc.txt")
 
 
-def measured_traffic(workload, cells, tile):
+def measured_traffic(workload, cells, tile, prefix="fused_step", sources="step"):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken on the
-    current kernel source with the same strip shape; otherwise None."""
+    current kernel source with the same strip (launch) shape; otherwise None."""
     from paper_1902_08933_amd.rocprof_summary import kernel_source_hash
-    path = traffic_summary_path(workload)
+    path = traffic_summary_path(workload, prefix)
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -37,7 +37,7 @@ def measured_traffic(workload, cells, tile):
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     c = re.search(r"cells:\s*([0-9]+)", text)
     k = re.search(r"--tile (\d+)", text)
-    if not (m and t and c and k) or m.group(1) != kernel_source_hash() or int(c.group(1)) != cells:
+    if not (m and t and c and k) or m.group(1) != kernel_source_hash(sources) or int(c.group(1)) != cells:
         return None
     if int(k.group(1)) != tile:
         return None
@@ -259,6 +259,42 @@ def single_phase_bench(n=1024, steps=2000, warmup=100):
     return out
 
 
+D3Q15_BYTES = 4 * 2 * (14 + 16 + 1 + 3)  # g_1..14, h_0 hi, h_1..14, h_0 lo, p, (phi u): read + written
+
+
+def d3q15_bench(n=256, steps=200, warmup=20):
+    """The D3Q15 two-phase step on an n^3 periodic spinodal (QIM, rho ratio 3, M_phi 0.01):
+    MLUPS and the fraction of the HBM roofline at 272 algorithmic bytes per node, launch shape
+    from the library's autotuner."""
+    import numpy as np
+    import torch
+    from paper_1902_08933_amd import lbpf, workloads as W
+    cfg, phi = W.spinodal3d(n=n, seed=0)
+    sim = lbpf.Simulation3D(cfg).init(torch.from_numpy(phi.astype(np.float32)).cuda())
+    shape = sim.autotune(3)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    cells = n ** 3
+    gbs = D3Q15_BYTES * cells / (ms * 1e-3) / 1e9
+    d = sim.diagnostics()
+    tx, ty, cz = lbpf.shapes3d()[shape]
+    return {"workload": f"spinodal {n}^3 periodic, D3Q15, QIM, rho ratio 3, nu ratio 0.1, sigma 0.03, "
+                        "W 4, M_phi 0.01, tau_h 1",
+            "steps": steps, "ms_per_step": round(ms, 5), "MLUPS": round(cells / (ms * 1e-3) / 1e6, 1),
+            "bytes_per_node": D3Q15_BYTES, "achieved_GBs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "launch_shape": {"tx": tx, "ty": ty, "cz": cz, "index": shape, "chosen_by": "autotuner"},
+            "traffic": measured_traffic(f"d3q15_{n}", cells, shape, prefix="fused_step3d", sources="d3q15"),
+            "sum_phi_final": d["sum_phi"]}
+
+
 def cpu_baseline(cfg, phi, steps):
     import numpy as np
     import oracle
@@ -283,6 +319,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-single-phase", action="store_true")
+    ap.add_argument("--no-d3q15", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=80)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -348,6 +385,8 @@ def main():
         out["surrogate"] = surrogate_bench()
     if not args.no_single_phase:
         out["single_phase"] = single_phase_bench()
+    if not args.no_d3q15:
+        out["d3q15"] = d3q15_bench()
     if not args.no_cpu_baseline:
         v, dt = cpu_baseline(cfg, phi, args.cpu_steps)
         out["cpu_baseline"] = {"value": round(v, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",

@@ -95,7 +95,7 @@ __device__ __forceinline__ int mirror_z(int z, int nz) {
     return z;
 }
 
-template <int TX, int TY>
+template <int TX, int TY, int PF>
 struct Lds3 {
     static constexpr int PX = TX + 4, PN = PX * (TY + 4);  // phi planes, halo 2
     static constexpr int MX = TX + 2, MN = MX * (TY + 2);  // mu and pressure planes, halo 1
@@ -104,22 +104,35 @@ struct Lds3 {
     float phl[RP * PN];
     float mu[RM * MN];
     float p[RQ * MN];
+    // PF: the owned node's sixteen h values of the next two planes, [slot][q][thread] (each
+    // thread reads back only what it wrote, so the stash needs no barrier)
+    float own[PF ? 2 * kHP * TX * TY : 1];
 };
 
-// phi = sum_i h_i (eq. 18) as an FP32 pair, from the sixteen stored h planes at one node
-template <int BC>
-__device__ __forceinline__ void phi_at(const Model3& m, const float* __restrict__ hin, int x, int y,
-                                       int z, float& hi, float& lo) {
-    const unsigned c = node3(m, src_z<BC>(z, m.nz), wrap(y, m.ny), wrap(x, m.nx));
-    float h[kHP];
-#pragma unroll
-    for (int q = 0; q < kHP; ++q) h[q] = *pl(hin, m.plane, q, c);
+// phi = sum_i h_i (eq. 18) as an FP32 pair from the sixteen stored h values of a node
+__device__ __forceinline__ void phi_pair16(const float (&h)[kHP], float& hi, float& lo) {
     float s = 0.0f;
 #pragma unroll
     for (int q = 1; q <= 14; ++q) s += h[q];
     float e;
     two_sum(h[0], s, hi, e);
     lo = h[kH0Lo] + e;
+}
+
+// offset of the (possibly ghost) node (x, y, z): x, y wrapped, z wrapped or mirrored
+template <int BC>
+__device__ __forceinline__ unsigned src_node(const Model3& m, int x, int y, int z) {
+    return node3(m, src_z<BC>(z, m.nz), wrap(y, m.ny), wrap(x, m.nx));
+}
+
+template <int BC>
+__device__ __forceinline__ void phi_at(const Model3& m, const float* __restrict__ hin, int x, int y,
+                                       int z, float& hi, float& lo) {
+    const unsigned c = src_node<BC>(m, x, y, z);
+    float h[kHP];
+#pragma unroll
+    for (int q = 0; q < kHP; ++q) h[q] = *pl(hin, m.plane, q, c);
+    phi_pair16(h, hi, lo);
 }
 
 // eq. (8) with the Laplacian of eq. (30b) over the D3Q15 neighbours, on differences of phi
@@ -163,10 +176,9 @@ __device__ __forceinline__ void grad3(Dz dz, int bm, int bc, int bp, int o, int 
                            + (dz(bp + o - N + E, bm + o - N + E) + dz(bp + o - N - E, bm + o - N - E)));
 }
 
-template <int TX, int TY>
-__device__ __forceinline__ Stencil3 gather3(const Lds3<TX, TY>& S, int pm, int pc, int pp, int mm,
-                                            int mc, int mp, int qm, int qc, int qp, int tx, int ty) {
-    using L = Lds3<TX, TY>;
+template <class L>
+__device__ __forceinline__ Stencil3 gather3(const L& S, int pm, int pc, int pp, int mm, int mc,
+                                            int mp, int qm, int qc, int qp, int tx, int ty) {
     Stencil3 s;
     const int po = (ty + 2) * L::PX + tx + 2, mo = (ty + 1) * L::MX + tx + 1;
     s.phh = S.phh[pc + po];
@@ -338,7 +350,13 @@ __device__ __forceinline__ int xcd_order(int b, int nblk) {
     return xcd * per + (xcd < rem ? xcd : rem) + loc;
 }
 
-template <int TX, int TY, bool COLLIDE, int BC>
+// PF = 1 software-pipelines the loads: the next phi plane's populations (each thread loads its
+// own column's node and at most NHK halo nodes) and the next pressure plane are loaded into
+// registers before the current plane's update, so that their latency overlaps the collision
+// arithmetic; the owned node's h values, needed again two planes later for its collision, are
+// kept in a thread-private LDS stash instead of being read a second time. The arithmetic is the
+// same for PF = 0 and 1.
+template <int TX, int TY, bool COLLIDE, int BC, int PF>
 __global__ __launch_bounds__(TX * TY) void march3d_kernel(Model3 m, const float* __restrict__ gin,
                                                           float* __restrict__ gout,
                                                           const float* __restrict__ hin,
@@ -348,9 +366,10 @@ __global__ __launch_bounds__(TX * TY) void march3d_kernel(Model3 m, const float*
                                                           float* __restrict__ phiu,
                                                           float* __restrict__ fields, int ntx,
                                                           int nty, int cz) {
-    using L = Lds3<TX, TY>;
+    using L = Lds3<TX, TY, PF>;
     constexpr int NT = TX * TY, PX = L::PX, PN = L::PN, MX = L::MX, MN = L::MN;
-    __shared__ L S;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    L& S = *reinterpret_cast<L*>(lds_raw);
     const int nblk = gridDim.x;
     const int blk = xcd_order(blockIdx.x, nblk);
     const int tile = blk % (ntx * nty), chunk = blk / (ntx * nty);
@@ -386,10 +405,86 @@ __global__ __launch_bounds__(TX * TY) void march3d_kernel(Model3 m, const float*
             S.mu[b + j] = mu_at3<PX>(m, S.phh, S.phl, bm, bc, bp, j % MX + 1, j / MX + 1);
     };
 
-    // prologue: phi planes zs-2 .. zs+1, pressure planes zs-1, zs, mu planes zs-1, zs
-    for (int z = zs - 2; z <= zs + 1; ++z) publish_phi(z);
-    publish_p(zs - 1);
-    publish_p(zs);
+    // PF: the halo of a phi plane (PN - NT nodes: rows 0, 1, TY+2, TY+3 at full width, then
+    // columns 0, 1, TX+2, TX+3 of rows 2 .. TY+1) spread over the threads, NHK per thread
+    constexpr int NHALO = PN - NT, NHK = (NHALO + NT - 1) / NT, NPP = (MN + NT - 1) / NT;
+    auto halo_pos = [](int k, int& lx, int& ly) {
+        if (k < 4 * PX) {
+            const int r = k / PX;
+            ly = r < 2 ? r : TY + r;
+            lx = k % PX;
+        } else {
+            const int k2 = k - 4 * PX, c4 = k2 % 4;
+            ly = 2 + k2 / 4;
+            lx = c4 < 2 ? c4 : TX + c4;
+        }
+    };
+    float hin_own[PF ? kHP : 1];
+    float hq[PF ? NHK : 1][kHP];
+    float pq[PF ? NPP : 1];
+    auto load_halo = [&](int zf, int zp) {
+        if constexpr (PF != 0) {
+            const unsigned c0 = src_node<BC>(m, x0 + tx, y0 + ty, zf);
+#pragma unroll
+            for (int q = 0; q < kHP; ++q) hin_own[q] = *pl(hin, P, q, c0);
+#pragma unroll
+            for (int k = 0; k < NHK; ++k) {
+                const int j = tid + k * NT;
+                if (j < NHALO) {
+                    int lx, ly;
+                    halo_pos(j, lx, ly);
+                    const unsigned c = src_node<BC>(m, x0 + lx - 2, y0 + ly - 2, zf);
+#pragma unroll
+                    for (int q = 0; q < kHP; ++q) hq[k][q] = *pl(hin, P, q, c);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NPP; ++k) {
+                const int j = tid + k * NT;
+                if (j < MN) pq[k] = *pl(pin, P, 0, src_node<BC>(m, x0 + j % MX - 1, y0 + j / MX - 1, zp));
+            }
+        }
+    };
+    auto store_halo = [&](int zf, int zp) {
+        if constexpr (PF != 0) {
+            const int b = pslot(zf), bq = qslot(zp);
+            const int o = b + (ty + 2) * PX + tx + 2;
+            phi_pair16(hin_own, S.phh[o], S.phl[o]);
+            float* st = S.own + (zf & 1) * (kHP * NT) + tid;
+#pragma unroll
+            for (int q = 0; q < kHP; ++q) st[q * NT] = hin_own[q];
+#pragma unroll
+            for (int k = 0; k < NHK; ++k) {
+                const int j = tid + k * NT;
+                if (j < NHALO) {
+                    int lx, ly;
+                    halo_pos(j, lx, ly);
+                    phi_pair16(hq[k], S.phh[b + ly * PX + lx], S.phl[b + ly * PX + lx]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NPP; ++k) {
+                const int j = tid + k * NT;
+                if (j < MN) S.p[bq + j] = pq[k];
+            }
+        }
+    };
+
+    // prologue: phi planes zs-2 .. zs+1, pressure planes zs-1, zs, mu planes zs-1, zs (with PF,
+    // planes zs and zs+1 through the stash path, and the first iteration's loads in flight)
+    if (PF) {
+        publish_phi(zs - 2);
+        publish_phi(zs - 1);
+        load_halo(zs, zs - 1);
+        store_halo(zs, zs - 1);
+        load_halo(zs + 1, zs);
+        store_halo(zs + 1, zs);
+        load_halo(zs + 2, zs + 1);
+    } else {
+        for (int z = zs - 2; z <= zs + 1; ++z) publish_phi(z);
+        publish_p(zs - 1);
+        publish_p(zs);
+    }
     __syncthreads();
     compute_mu(zs - 1);
     compute_mu(zs);
@@ -397,7 +492,6 @@ __global__ __launch_bounds__(TX * TY) void march3d_kernel(Model3 m, const float*
     const int x = x0 + tx, y = y0 + ty;
     const bool col_active = x < m.nx && y < m.ny;
     for (int z = zs; z < ze; ++z) {
-        // the owned node's populations (read again from L2 after the phi pass two planes back)
         float g[kFP], h[kHP], pu[3];
         unsigned cell = 0;
         if (col_active) {
@@ -405,19 +499,30 @@ __global__ __launch_bounds__(TX * TY) void march3d_kernel(Model3 m, const float*
 #pragma unroll
             for (int q = 0; q < kFP; ++q) g[q] = *pl(gin, P, q, cell);
 #pragma unroll
-            for (int q = 0; q < kHP; ++q) h[q] = *pl(hin, P, q, cell);
-#pragma unroll
             for (int a = 0; a < 3; ++a) pu[a] = *pl(phiu, P, a, cell);
         }
-        publish_phi(z + 2);
-        publish_p(z + 1);
+        if (PF) {
+            // the owned node's h from the stash (written two iterations ago by this thread),
+            // read before this iteration's store reuses the slot
+            const float* st = S.own + (z & 1) * (kHP * NT) + tid;
+#pragma unroll
+            for (int q = 0; q < kHP; ++q) h[q] = st[q * NT];
+            store_halo(z + 2, z + 1);
+        } else {
+            if (col_active) {
+#pragma unroll
+                for (int q = 0; q < kHP; ++q) h[q] = *pl(hin, P, q, cell);
+            }
+            publish_phi(z + 2);
+            publish_p(z + 1);
+        }
         __syncthreads();
         compute_mu(z + 1);
         __syncthreads();
+        if (PF && z + 1 < ze) load_halo(z + 3, z + 2);
         if (col_active) {
-            const Stencil3 st = gather3<TX, TY>(S, pslot(z - 1), pslot(z), pslot(z + 1), mslot(z - 1),
-                                                mslot(z), mslot(z + 1), qslot(z - 1), qslot(z),
-                                                qslot(z + 1), tx, ty);
+            const Stencil3 st = gather3(S, pslot(z - 1), pslot(z), pslot(z + 1), mslot(z - 1), mslot(z),
+                                        mslot(z + 1), qslot(z - 1), qslot(z), qslot(z + 1), tx, ty);
             cell3<COLLIDE, BC>(m, x, y, z, cell, g, h, pu, st, gout, hout, pout, phiu, fields);
         }
     }
@@ -555,20 +660,30 @@ __global__ void compact3d_kernel(Model3 m, const float* __restrict__ src, float*
 }
 
 // ---- launch shapes -------------------------------------------------------------------------
-struct Shape3 { int tx, ty, cz; };
-static const Shape3 kShapes3[] = {{32, 8, 32}, {32, 8, 64}, {64, 4, 32}, {64, 8, 32},
-                                  {32, 16, 32}, {64, 8, 64}, {32, 8, 16}, {64, 4, 64}};
+struct Shape3 { int tx, ty, cz, pf; };
+static const Shape3 kShapes3[] = {{32, 8, 32, 0},  {32, 8, 64, 0},  {64, 4, 32, 0}, {64, 8, 32, 0},
+                                  {32, 16, 32, 0}, {64, 8, 64, 0},  {32, 8, 16, 0}, {64, 4, 64, 0},
+                                  {32, 8, 32, 1},  {32, 8, 16, 1},  {64, 4, 32, 1}, {64, 8, 32, 1},
+                                  {32, 16, 32, 1}, {64, 8, 16, 1},  {64, 4, 16, 1}, {32, 8, 8, 1}};
 constexpr int kNumShapes3 = sizeof(kShapes3) / sizeof(kShapes3[0]);
 constexpr int kDefaultShape3 = 0;
 
-template <int TX, int TY, bool C, int BC>
+template <int TX, int TY, bool C, int BC, int PF>
 static hipError_t launch_t(const Model3& m, int cz, const float* gin, float* gout, const float* hin,
                            float* hout, const float* pin, float* pout, float* phiu, float* fields,
                            hipStream_t st) {
     const int ntx = (m.nx + TX - 1) / TX, nty = (m.ny + TY - 1) / TY, nch = (m.nz + cz - 1) / cz;
     const long long nblk = (long long)ntx * nty * nch;
     if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((march3d_kernel<TX, TY, C, BC>), dim3((unsigned)nblk), dim3(TX * TY), 0, st, m,
+    const size_t lds = sizeof(Lds3<TX, TY, PF>);
+    static bool attr_set = false;  // dynamic LDS above 64 KiB is requested once per kernel
+    if (!attr_set) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&march3d_kernel<TX, TY, C, BC, PF>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((march3d_kernel<TX, TY, C, BC, PF>), dim3((unsigned)nblk), dim3(TX * TY), lds, st, m,
                        gin, gout, hin, hout, pin, pout, phiu, fields, ntx, nty, cz);
     return hipGetLastError();
 }
@@ -580,7 +695,8 @@ static hipError_t launch_shape(int s, const Model3& m, const float* gin, float* 
     const Shape3 sh = kShapes3[s];
 #define LBPF3D_CASE(TX, TY)                                                                         \
     if (sh.tx == TX && sh.ty == TY)                                                                 \
-        return launch_t<TX, TY, C, BC>(m, sh.cz, gin, gout, hin, hout, pin, pout, phiu, fields, st);
+        return sh.pf ? launch_t<TX, TY, C, BC, 1>(m, sh.cz, gin, gout, hin, hout, pin, pout, phiu, fields, st) \
+                     : launch_t<TX, TY, C, BC, 0>(m, sh.cz, gin, gout, hin, hout, pin, pout, phiu, fields, st);
     LBPF3D_CASE(32, 8)
     LBPF3D_CASE(64, 4)
     LBPF3D_CASE(64, 8)

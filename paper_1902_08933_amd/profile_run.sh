@@ -37,6 +37,39 @@ if [ "$W" = "r4_1024" ]; then
         --out "$PROF/sp_remark4_r4_1024_trace.txt"
     exit $?
 fi
+if [ "$W" = "d3q15_256" ]; then
+    # D3Q15 two-phase step at 256^3: autotuned launch shape, kernel trace, then HBM traffic
+    # (FETCH_SIZE, WRITE_SIZE, scaled by the same counters on the copy probe)
+    OUT=gpurun_out/prof_d3q15_256
+    PROF=${PROFILE_OUT:-profiles}
+    mkdir -p "$OUT" "$PROF"
+    export TMPDIR=/tmp
+    CELLS=16777216
+    SHAPE=$(timeout -k 10 120 python3 -m paper_1902_08933_amd.profile_step --workload d3q15_256 --autotune | tail -1) || exit 1
+    echo "profile: autotuned launch shape $SHAPE"
+    STEP="python3 -m paper_1902_08933_amd.profile_step --workload d3q15_256 --tile $SHAPE"
+    PROBE="python3 -m paper_1902_08933_amd.profile_step --copy-mib 1024 --steps 2 --probe-blocks 4096"
+    echo "profile: kernel trace d3q15_256" && \
+    timeout -k 10 180 rocprofv3 --kernel-trace --stats -d "$OUT/trace" -o run -- $STEP --steps 50 --warmup 5 > "$OUT/trace.log" 2>&1 && \
+    echo "profile: FETCH_SIZE d3q15_256" && \
+    timeout -s KILL 90 rocprofv3 --pmc FETCH_SIZE -d "$OUT/fetch" -o run -- $STEP --steps 5 --warmup 1 > "$OUT/fetch.log" 2>&1 && \
+    echo "profile: WRITE_SIZE d3q15_256" && \
+    timeout -s KILL 90 rocprofv3 --pmc WRITE_SIZE -d "$OUT/write" -o run -- $STEP --steps 5 --warmup 1 > "$OUT/write.log" 2>&1 && \
+    echo "profile: probe FETCH_SIZE" && \
+    timeout -s KILL 90 rocprofv3 --pmc FETCH_SIZE -d "$OUT/cfetch" -o run -- $PROBE > "$OUT/cfetch.log" 2>&1 && \
+    echo "profile: probe WRITE_SIZE" && \
+    timeout -s KILL 90 rocprofv3 --pmc WRITE_SIZE -d "$OUT/cwrite" -o run -- $PROBE > "$OUT/cwrite.log" 2>&1 && \
+    python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --cells $CELLS \
+        --kernel march3d_kernel --alg-bytes-per-cell 272 --sources d3q15 \
+        --command "bash paper_1902_08933_amd/profile_run.sh d3q15_256  (trace: rocprofv3 --kernel-trace --stats -- $STEP --steps 50 --warmup 5)" \
+        --out "$PROF/fused_step3d_d3q15_256_trace.txt" && \
+    python3 -m paper_1902_08933_amd.rocprof_summary --fetch "$OUT/fetch/run_results.db" --write "$OUT/write/run_results.db" \
+        --calib-fetch "$OUT/cfetch/run_results.db" --calib-write "$OUT/cwrite/run_results.db" --calib-bytes 1073741824 \
+        --cells $CELLS --kernel march3d_kernel --alg-bytes-per-cell 272 --sources d3q15 \
+        --command "bash paper_1902_08933_amd/profile_run.sh d3q15_256  (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE -- $STEP --steps 5 --warmup 1; calibration: same counters on $PROBE)" \
+        --out "$PROF/fused_step3d_d3q15_256_pmc.txt"
+    exit $?
+fi
 if [ "$W" = "unet1024" ]; then
     # surrogate forward pass at 1024^2: kernel trace of 1 + 10 forwards (214 GFLOP each)
     OUT=gpurun_out/prof_unet1024

@@ -3,6 +3,7 @@
 python -m paper_1902_08933_amd.profile_step --workload spinodal4096 --steps 20
 python -m paper_1902_08933_amd.profile_step --workload spinodal1024 --sweep
 python -m paper_1902_08933_amd.profile_step --workload r4_1024   (Remark 4 scheme, single phase)
+python -m paper_1902_08933_amd.profile_step --workload d3q15_256 --sweep   (D3Q15 two-phase step)
 python -m paper_1902_08933_amd.profile_step --copy-mib 2048 --steps 10   (bandwidth probe:
     copy / read / write of a known byte count, the reference for the HBM roofline and for
     scaling the FETCH_SIZE / WRITE_SIZE counters)
@@ -45,6 +46,26 @@ def run_sp(torch, n, steps, warmup, remark4=False):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def run_d3q15(torch, n, steps, warmup, shape=None, sweep=False):
+    """D3Q15 spinodal at n^3: the autotuned (or given) launch shape, ms per step; with sweep,
+    every shape"""
+    cfg, phi = workloads.spinodal3d(n=n, seed=0)
+    sim = lbpf.Simulation3D(cfg).init(torch.from_numpy(phi.astype("float32")).cuda())
+    shapes = range(len(lbpf.shapes3d())) if sweep else [sim.autotune(3) if shape is None else shape]
+    out = []
+    for s in shapes:
+        sim.set_shape(s)
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        out.append((s, e0.elapsed_time(e1) / steps))
+    return out
 
 
 def run_steps(torch, cfg, phi, steps, warmup, tile):
@@ -95,6 +116,19 @@ def main():
                 print(f"probe {name} {a.copy_mib} MiB, {blocks} workgroups: {ms:.4f} ms, "
                       f"{moved * nbytes / ms / 1e6:.1f} GB/s", flush=True)
         return
+    if a.workload.startswith("d3q15_"):
+        n = int(a.workload[len("d3q15_"):])
+        if a.autotune:
+            cfg, phi = workloads.spinodal3d(n=n, seed=0)
+            sim = lbpf.Simulation3D(cfg).init(torch.from_numpy(phi.astype("float32")).cuda())
+            print(sim.autotune(3), flush=True)
+            return 0
+        shapes = lbpf.shapes3d()
+        for s, ms in run_d3q15(torch, n, a.steps, a.warmup, shape=a.tile, sweep=a.sweep):
+            print(f"{a.workload} shape {s} {shapes[s]}: {ms:.4f} ms/step, "
+                  f"{n ** 3 / (ms * 1e-3) / 1e6:.0f} MLUPS, {272 * n ** 3 / (ms * 1e-3) / 1e9:.0f} GB/s",
+                  flush=True)
+        return 0
     if a.workload.startswith("sp") or a.workload.startswith("r4_"):
         r4 = a.workload.startswith("r4_")
         n = int(a.workload[3:] if r4 else a.workload[2:])

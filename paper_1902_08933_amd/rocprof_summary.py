@@ -21,6 +21,7 @@ KERNEL_FILES = {
     "unet": [os.path.join(HERE, "csrc", n) for n in ("lbpf_unet_kernels.hip", "lbpf_unet_ops.hpp",
                                                      "lbpf_unet.cpp")],
     "sp": [os.path.join(HERE, "csrc", "lbpf_sp.hip")],
+    "d3q15": [os.path.join(HERE, "csrc", n) for n in ("lbpf_d3q15.hip", "lbpf_cell.hpp")],
 }
 
 
