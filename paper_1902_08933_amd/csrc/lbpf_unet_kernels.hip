@@ -112,6 +112,13 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs& a, const float4_t 
     static_assert(TR == 4 * MF, "four waves of MF rows");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, m = lane & 15;
     const int H = a.H, W = a.W, Cout = a.Cout;
+    static_assert(TR * TC == 256, "the fused head's residual is one pixel per thread");
+    // the fused head's residual (4 fields) is read now, so that its latency overlaps the
+    // output tile's stores and barriers
+    float4 res4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int rpy = ty0 + tid / TC, rpx = tx0 + tid % TC;
+    const bool res_vec = a.hw && a.rc == 4 && rpy < H && rpx < W;
+    if (res_vec) res4 = *reinterpret_cast<const float4*>(a.res + ((size_t)(n * H + rpy) * W + rpx) * 4);
     // D fragment: lane (16 * g + c) holds pixels 4g .. 4g+3 of the row, channel c
 #pragma unroll
     for (int j = 0; j < NF; ++j) {
@@ -164,7 +171,7 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs& a, const float4_t 
             if (yy >= H || xx >= W) continue;
             const size_t p = (size_t)(n * H + yy) * W + xx;
             if (a.rc == 4) {
-                const float4 r = *reinterpret_cast<const float4*>(a.res + p * 4);
+                const float4 r = res4;  // pix == tid: this thread's prefetched residual
                 const float4 hv = *reinterpret_cast<const float4*>(s_h + pix * 16);
                 *reinterpret_cast<float4*>(a.pred + p * 4) = make_float4(r.x + hv.x, r.y + hv.y, r.z + hv.z, r.w + hv.w);
             } else {
@@ -221,15 +228,40 @@ __global__ __launch_bounds__(256, 2) void conv_first_kernel(const ConvArgs a) {
     const int tx0 = (tile % tiles_x) * TC, ty0 = ((tile / tiles_x) % tiles_y) * TR;
     const int n = tile / (tiles_x * tiles_y);
     const int co0 = blockIdx.y * COT;
+    // the workgroup's weights, fields 0..3 of every (channel, tap), staged once in LDS as
+    // [COT][9][4] bf16 (zero beyond Cout and beyond the input's fields)
+    bf16* s_wf = conv_lds + PR * PC * 4;
+    for (int r = tid; r < COT * 9; r += 256) {
+        const int co = co0 + r / 9, t = r % 9;
+        short4_t v = {0, 0, 0, 0};
+        if (co < Cout) {
+            const bf16* src = a.w + ((size_t)co * 9 + t) * wcin;
+            if (wcin % 4 == 0 && cin == 4 && (reinterpret_cast<uintptr_t>(a.w) & 7) == 0) {
+                v = *reinterpret_cast<const short4_t*>(src);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (c < cin) v[c] = (short)src[c];
+            }
+        }
+        *reinterpret_cast<short4_t*>(s_wf + r * 4) = v;
+    }
+    const bool vec_in = cin == 4 && (reinterpret_cast<uintptr_t>(a.xin) & 15) == 0;
     for (int pix = tid; pix < PR * PC; pix += 256) {
         const int sy = wrap_coord(ty0 + pix / PC - 1, H), sx = wrap_coord(tx0 + pix % PC - 1, W);
         const float* src = a.xin + ((size_t)(n * H + sy) * W + sx) * cin;
         short4_t v = {0, 0, 0, 0};
+        if (vec_in) {
+            const float4 f = *reinterpret_cast<const float4*>(src);
+            v = {(short)f2bf(f.x), (short)f2bf(f.y), (short)f2bf(f.z), (short)f2bf(f.w)};
+        } else {
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (c < cin) v[c] = (short)f2bf(src[c]);
+            for (int c = 0; c < 4; ++c)
+                if (c < cin) v[c] = (short)f2bf(src[c]);
+        }
         *reinterpret_cast<short4_t*>(s_x + pix * 4) = v;
     }
+    __syncthreads();
     // B[k][co] with k = 4 tap + field: lane (m + 16 g) holds k = 32 s + 8 g + e, i.e. taps
     // 8 s + 2 g (e < 4) and 8 s + 2 g + 1 (e >= 4), field e % 4
     short8_t b[2][NF];
@@ -237,14 +269,12 @@ __global__ __launch_bounds__(256, 2) void conv_first_kernel(const ConvArgs a) {
     for (int st = 0; st < 2; ++st)
 #pragma unroll
         for (int j = 0; j < NF; ++j) {
-            const int co = co0 + 16 * j + m;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int t = 8 * st + 2 * g + (e >> 2), c = e & 3;
-                b[st][j][e] = (co < Cout && t < 9 && c < cin) ? (short)a.w[((size_t)co * 9 + t) * wcin + c] : (short)0;
-            }
+            const int r = (16 * j + m) * 9, t0 = 8 * st + 2 * g;
+            const short4_t w0 = t0 < 9 ? *reinterpret_cast<const short4_t*>(s_wf + (r + t0) * 4) : short4_t{0, 0, 0, 0};
+            const short4_t w1 = t0 + 1 < 9 ? *reinterpret_cast<const short4_t*>(s_wf + (r + t0 + 1) * 4)
+                                           : short4_t{0, 0, 0, 0};
+            b[st][j] = short8_t{w0[0], w0[1], w0[2], w0[3], w1[0], w1[1], w1[2], w1[3]};
         }
-    __syncthreads();
     float4_t acc[MF][NF];
 #pragma unroll
     for (int f = 0; f < MF; ++f)
@@ -268,8 +298,13 @@ __global__ __launch_bounds__(256, 2) void conv_first_kernel(const ConvArgs a) {
     conv_epilogue<RELU, COT, MF>(a, acc, conv_lds, tx0, ty0, n, co0);
 }
 
-template <int KS, bool RELU, int COT>
-__global__ __launch_bounds__(256, 2) void conv_tile_kernel(const ConvArgs a) {
+// PFW: the next chunk's weights are fetched into registers with the patch, so that no global
+// latency is exposed when a chunk is published. It costs registers: COT = 32 then runs at two
+// workgroups per CU instead of three (taken when the grid is too small to fill three), and
+// COT = 64 at the register limit (a few spills) instead of loading its weights from L2 while
+// publishing (measured faster with the prefetch).
+template <int KS, bool RELU, int COT, bool PFW>
+__global__ __launch_bounds__(256, (COT <= 32 && !PFW ? 3 : 2)) void conv_tile_kernel(const ConvArgs a) {
     constexpr int TR = kConvTR, TC = kConvTC, CK = kConvCK, CKP = kConvCKP;
     constexpr int HALO = KS - 1, PR = TR + HALO, PC = TC + HALO, T = KS * KS;
     constexpr int PIECES = CK / 8;                  // 16-byte pieces per pixel and chunk
@@ -290,9 +325,6 @@ __global__ __launch_bounds__(256, 2) void conv_tile_kernel(const ConvArgs a) {
     const int co0 = blockIdx.y * COT;
     const int h0 = HALO / 2, Hl = H >> 1, Wl = W >> 1;
 
-    // weights are prefetched into registers with the patch when that keeps two waves per SIMD
-    // (COT <= 32); the COT = 64 variant loads them while publishing (they are L2-resident)
-    constexpr bool PFW = COT <= 32;
     constexpr int PWR = PFW ? PW : 1;
     short8_t rp[PP], rw[PWR];
     auto fetch_w = [&](int i, int kc) {
@@ -737,25 +769,35 @@ hipError_t unet_mfma_probe(int k32, const bf16* A, const bf16* B, float* D, hipS
     return hipGetLastError();
 }
 
-template <int KS, bool R, int C>
-static hipError_t launch_conv_t(const ConvArgs& a, hipStream_t st) {
+template <int KS, bool R, int C, bool PFW>
+static hipError_t launch_conv_pf(const ConvArgs& a, dim3 grid, hipStream_t st) {
     constexpr size_t lds = (size_t)conv_lds_elems<KS, C>() * sizeof(bf16);
     static bool attr = false;  // dynamic LDS above 64 KiB must be requested once per kernel
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)&conv_tile_kernel<KS, R, C>,
+        hipError_t e = hipFuncSetAttribute((const void*)&conv_tile_kernel<KS, R, C, PFW>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr = true;
     }
+    hipLaunchKernelGGL((conv_tile_kernel<KS, R, C, PFW>), grid, dim3(256), lds, st, a);
+    return hipGetLastError();
+}
+
+template <int KS, bool R, int C>
+static hipError_t launch_conv_t(const ConvArgs& a, hipStream_t st) {
     const long long tiles = (long long)a.N * ((a.H + kConvTR - 1) / kConvTR) * ((a.W + kConvTC - 1) / kConvTC);
     dim3 grid((unsigned)tiles, (unsigned)((a.Cout + C - 1) / C));
-    hipLaunchKernelGGL((conv_tile_kernel<KS, R, C>), grid, dim3(256), lds, st, a);
-    return hipGetLastError();
+    // COT = 32: three workgroups per CU without the weight prefetch pay off only when the grid
+    // has enough workgroups to fill them (three per CU)
+    const bool pfw = C >= 64 || (long long)grid.x * grid.y < 768;
+    return pfw ? launch_conv_pf<KS, R, C, true>(a, grid, st) : launch_conv_pf<KS, R, C, false>(a, grid, st);
 }
 
 template <bool R, int C>
 static hipError_t launch_first_t(const ConvArgs& a, hipStream_t st) {
     constexpr size_t lds = (size_t)conv_lds_elems<1, C>() * sizeof(bf16);
+    static_assert((kConvTR + 2) * (kConvTC + 2) * 4 + C * 9 * 4 <= conv_lds_elems<1, C>(),
+                  "patch and staged weights fit the first layer's LDS");
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)&conv_first_kernel<R, C>,
