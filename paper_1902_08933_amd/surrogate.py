@@ -152,3 +152,36 @@ def lb_reinit_cycle(sim, bufs, lb_every=500):
     lbpf.fields_to_nhwc(sim, FIELD_SHIFT, FIELD_SCALE, out=a[0])
     lbpf.init_from_nhwc(sim, a[0], FIELD_SHIFT, FIELD_SCALE, step=sim.step_count)
     sim.step(K_STEPS)
+
+
+def coarse_params(cfg):
+    """The same physics on a grid twice as coarse, in diffusive scaling (dx' = 2 dx, dt' = 4 dt):
+    nu and tau_h unchanged in lattice units, W' = W/2, sigma' = 2 sigma (sigma ~ rho L^3/T^2),
+    M' = M/4 (M beta, the order parameter's diffusivity, invariant), lattice velocity x2,
+    pressure x4; 500 fine steps are 125 coarse steps."""
+    return dict(cfg, nx=cfg["nx"] // 2, ny=cfg["ny"] // 2, W=cfg["W"] / 2, sigma=2 * cfg["sigma"],
+                M_phi=cfg["M_phi"] / 4)
+
+
+def coarse_lb_start(sim_fine, cfg_coarse):
+    """A coarse simulation started from the fine state: fields averaged over 2 x 2 nodes, velocity
+    and pressure rescaled (equilibrium populations of those fields)."""
+    import torch
+    def pool(t):
+        return torch.nn.functional.avg_pool2d(t[None, None], 2)[0, 0].contiguous()
+    f = {k: sim_fine.read(k) for k in ("phi", "ux", "uy", "p")}
+    return lbpf.Simulation(cfg_coarse).init(pool(f["phi"]), 2 * pool(f["ux"]), 2 * pool(f["uy"]),
+                                            4 * pool(f["p"]))
+
+
+def upsample2(c):
+    """bilinear, periodic: coarse node j is the mean of fine nodes 2j, 2j+1 (centre 2j + 1/2)"""
+    c = np.asarray(c, dtype=np.float64)
+    def axis(n):
+        pos = (np.arange(2 * n) - 0.5) / 2.0
+        j0 = np.floor(pos).astype(int)
+        return j0 % n, (j0 + 1) % n, pos - j0
+    a0, a1, wa = axis(c.shape[0])
+    b0, b1, wb = axis(c.shape[1])
+    r = (1 - wa)[:, None] * c[a0] + wa[:, None] * c[a1]
+    return (1 - wb)[None, :] * r[:, b0] + wb[None, :] * r[:, b1]
