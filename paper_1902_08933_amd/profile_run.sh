@@ -4,12 +4,14 @@
 #   profiles/fused_step_<workload>_pmc.txt    (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, each
 #                                              scaled by the counter's reading for the bandwidth probe)
 # Usage (from the repository root): bash paper_1902_08933_amd/profile_run.sh spinodal1024
-# Raw rocprofv3 output goes to gpurun_out/prof_<workload>/; PROFILE_OUT overrides profiles/.
+# Raw rocprofv3 output goes to $RAW_OUT/prof_<workload>/ (default RAW_OUT=prof_raw);
+# PROFILE_OUT overrides profiles/.
 set -o pipefail
 W=${1:-spinodal1024}
+RAW=${RAW_OUT:-prof_raw}
 if [ "$W" = "sp1024" ]; then
     # single-phase step with a mass source at 1024^2 (incompressible, full force term)
-    OUT=gpurun_out/prof_sp1024
+    OUT=$RAW/prof_sp1024
     PROF=${PROFILE_OUT:-profiles}
     mkdir -p "$OUT" "$PROF"
     export TMPDIR=/tmp
@@ -24,7 +26,7 @@ if [ "$W" = "sp1024" ]; then
 fi
 if [ "$W" = "r4_1024" ]; then
     # single-phase Remark 4 scheme with drag at 1024^2: G pass (100 B/node) and collision (144 B/node)
-    OUT=gpurun_out/prof_r4_1024
+    OUT=$RAW/prof_r4_1024
     PROF=${PROFILE_OUT:-profiles}
     mkdir -p "$OUT" "$PROF"
     export TMPDIR=/tmp
@@ -40,7 +42,7 @@ fi
 if [ "$W" = "d3q15_256" ]; then
     # D3Q15 two-phase step at 256^3: autotuned launch shape, kernel trace, then HBM traffic
     # (FETCH_SIZE, WRITE_SIZE, scaled by the same counters on the copy probe)
-    OUT=gpurun_out/prof_d3q15_256
+    OUT=$RAW/prof_d3q15_256
     PROF=${PROFILE_OUT:-profiles}
     mkdir -p "$OUT" "$PROF"
     export TMPDIR=/tmp
@@ -72,7 +74,7 @@ if [ "$W" = "d3q15_256" ]; then
 fi
 if [ "$W" = "unet1024" ]; then
     # surrogate forward pass at 1024^2: kernel trace of 1 + 10 forwards (214 GFLOP each)
-    OUT=gpurun_out/prof_unet1024
+    OUT=$RAW/prof_unet1024
     PROF=${PROFILE_OUT:-profiles}
     mkdir -p "$OUT" "$PROF"
     export TMPDIR=/tmp
@@ -87,7 +89,7 @@ if [ "$W" = "unet1024" ]; then
 fi
 N=${W#spinodal}
 CELLS=$((N * N))
-OUT=gpurun_out/prof_$W
+OUT=$RAW/prof_$W
 PROF=${PROFILE_OUT:-profiles}
 mkdir -p "$OUT" "$PROF"
 export TMPDIR=/tmp
