@@ -405,6 +405,11 @@ lbpf_status lbpf3d_read(lbpf3d* c, int32_t field, float* dst);
 /* FP64 sums over the grid (sum phi of the stored h, sum rho), max |u| and the count of
  * non-finite stored values; synchronizes the stream; LBPF_E_UNSTABLE when that count is > 0. */
 lbpf_status lbpf3d_diagnostics(lbpf3d* c, lbpf_diag* out);
+/* Laplace-law pressure jump of Sec. 4.2 in FP64, as lbpf_laplace_dp in 3D: P = p0 - kappa phi
+ * lap(phi) + kappa |grad phi|^2 / 2 + p, with the D3Q15 stencils on phi in FP64, averaged over
+ * nodes within R/2 of (xc, yc, zc) minus the average over r >= R + 3W (periodic distances in
+ * the periodic directions). LBPF_E_INVALID if either region is empty. Synchronizes the stream. */
+lbpf_status lbpf3d_laplace_dp(lbpf3d* c, double xc, double yc, double zc, double R, double* dP);
 /* Launch shapes: TX x TY tile of the x-y plane per workgroup (TX * TY threads), CZ planes per
  * chunk. Every shape gives bit-identical results. */
 int32_t lbpf3d_shape_count(void);

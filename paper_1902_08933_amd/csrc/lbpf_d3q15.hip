@@ -67,7 +67,7 @@ struct Model3 {
     int variant, pscheme, fsurf, visc, bc, clamp;
     float beta4, kappa, eta, gammaM, rhoA, rhoB, drho, inv_nuA, inv_nuB, muA, muB;
     float inv_tau_h, src_coef, fx, fy, fz, grav;
-    double d_rhoA, d_rhoB;
+    double d_rhoA, d_rhoB, d_beta, d_kappa;
 };
 
 // offset of node (x, y, z) in a plane: z * slab needs the full 32-bit product (a slab may hold
@@ -637,11 +637,13 @@ __global__ __launch_bounds__(256) void diag3d_partial_kernel(Model3 m, const flo
     }
 }
 
+// second pass: slot s of every partial reduced in a fixed order; bit s of maxmask takes the
+// maximum instead of the sum
 __global__ __launch_bounds__(256) void reduce3d_final_kernel(const double* __restrict__ part, int nblk,
-                                                             double* __restrict__ out) {
+                                                             unsigned maxmask, double* __restrict__ out) {
     __shared__ double sh[4];
     for (int s = 0; s < kRedSlots; ++s) {
-        const bool is_max = (s == 2);
+        const bool is_max = (maxmask >> s) & 1u;
         double v = 0.0;
         for (int b = threadIdx.x; b < nblk; b += 256) {
             const double w = part[(size_t)b * kRedSlots + s];
@@ -649,6 +651,63 @@ __global__ __launch_bounds__(256) void reduce3d_final_kernel(const double* __res
         }
         const double r = block_sum(v, sh, is_max);
         if (threadIdx.x == 0) out[s] = r;
+    }
+}
+
+// phi in FP64 of the (possibly ghost) node (x, y, z): h_0 hi + h_0 lo + sum_{i!=0} h_i (eq. 18)
+template <int BC>
+__device__ __forceinline__ double phi64_at(const Model3& m, const float* __restrict__ h, int x, int y, int z) {
+    const unsigned c = src_node<BC>(m, x, y, z);
+    double phi = (double)*pl(h, m.plane, 0, c) + (double)*pl(h, m.plane, kH0Lo, c);
+    for (int q = 1; q <= 14; ++q) phi += (double)*pl(h, m.plane, q, c);
+    return phi;
+}
+
+// Laplace pressure of Sec. 4.2 in FP64, P = p0 - kappa phi lap(phi) + kappa |grad phi|^2 / 2 + p
+// with p0 = phi psi' - psi, psi = beta phi^2 (phi - 1)^2, eqs. (30a)-(30b) over the D3Q15
+// neighbours on FP64 phi; per-block sums of P and counts over r <= r_in and r >= r_out from
+// (xc, yc, zc), distances periodic in x, y (and z when periodic)
+template <int BC>
+__global__ __launch_bounds__(256) void laplace3d_partial_kernel(Model3 m, const float* __restrict__ h,
+                                                                const float* __restrict__ fields,
+                                                                double xc, double yc, double zc,
+                                                                double r_in, double r_out,
+                                                                double* __restrict__ part) {
+    __shared__ double sh[4];
+    const long long n = (long long)m.nx * m.ny * m.nz;
+    double s_in = 0.0, c_in = 0.0, s_out = 0.0, c_out = 0.0;
+    for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
+        const int x = (int)(k % m.nx);
+        const long long r = k / m.nx;
+        const int y = (int)(r % m.ny), z = (int)(r / m.ny);
+        const double c = phi64_at<BC>(m, h, x, y, z);
+        double g[3] = {0.0, 0.0, 0.0}, lap = 0.0;
+        for (int i = 1; i < 15; ++i) {
+            const double w = i <= 6 ? 1.0 / 9.0 : 1.0 / 72.0;
+            const double v = phi64_at<BC>(m, h, x + kC[i][0], y + kC[i][1], z + kC[i][2]);
+            for (int a = 0; a < 3; ++a) g[a] += 3.0 * w * kC[i][a] * v;
+            lap += 6.0 * w * (v - c);
+        }
+        const double psi = m.d_beta * c * c * (c - 1.0) * (c - 1.0);
+        const double dpsi = 4.0 * m.d_beta * c * (c - 1.0) * (c - 0.5);
+        const double p = (double)*pl(fields, m.plane, 5, node3(m, z, y, x));
+        const double Pt = (c * dpsi - psi) - m.d_kappa * c * lap
+                        + 0.5 * m.d_kappa * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + p;
+        double dx = fabs(x - xc), dy = fabs(y - yc), dz = fabs(z - zc);
+        dx = fmin(dx, m.nx - dx);
+        dy = fmin(dy, m.ny - dy);
+        if (BC == 0) dz = fmin(dz, m.nz - dz);
+        const double rr = sqrt(dx * dx + dy * dy + dz * dz);
+        if (rr <= r_in) { s_in += Pt; c_in += 1.0; }
+        if (rr >= r_out) { s_out += Pt; c_out += 1.0; }
+    }
+    const double a = block_sum(s_in, sh, false);
+    const double b = block_sum(c_in, sh, false);
+    const double cc = block_sum(s_out, sh, false);
+    const double d = block_sum(c_out, sh, false);
+    if (threadIdx.x == 0) {
+        double* o = part + (size_t)blockIdx.x * kRedSlots;
+        o[0] = a; o[1] = b; o[2] = cc; o[3] = d;
     }
 }
 
@@ -834,7 +893,7 @@ lbpf_status lbpf3d_create(const lbpf3d_params* params, void* workspace, size_t w
     m.inv_tau_h = (float)(1.0 / p.tau_h);
     m.src_coef = (float)(1.0 - 0.5 / p.tau_h);
     m.fx = (float)p.force_x; m.fy = (float)p.force_y; m.fz = (float)p.force_z; m.grav = (float)p.gravity;
-    m.d_rhoA = p.rho_A; m.d_rhoB = p.rho_B;
+    m.d_rhoA = p.rho_A; m.d_rhoB = p.rho_B; m.d_beta = beta; m.d_kappa = kappa;
     *out = c;
     return LBPF_OK;
 }
@@ -900,7 +959,7 @@ lbpf_status lbpf3d_diagnostics(lbpf3d* c, lbpf_diag* out) {
                        plane3(c, cur ? kPlPB : kPlPA), plane3(c, kPlPhiU), plane3(c, kPlFields), c->red);
     if ((s = hip3(c, hipGetLastError(), "diag3d_partial_kernel")) != LBPF_OK) return s;
     double* fin = c->red + (size_t)kRedBlocks * kRedSlots;
-    hipLaunchKernelGGL(reduce3d_final_kernel, dim3(1), dim3(256), 0, c->stream, c->red, nblk, fin);
+    hipLaunchKernelGGL(reduce3d_final_kernel, dim3(1), dim3(256), 0, c->stream, c->red, nblk, 1u << 2, fin);
     if ((s = hip3(c, hipGetLastError(), "reduce3d_final_kernel")) != LBPF_OK) return s;
     double h[kRedSlots];
     if ((s = hip3(c, hipMemcpyAsync(h, fin, sizeof(h), hipMemcpyDeviceToHost, c->stream), "copy")) != LBPF_OK)
@@ -912,6 +971,37 @@ lbpf_status lbpf3d_diagnostics(lbpf3d* c, lbpf_diag* out) {
     out->nonfinite = (int64_t)h[3];
     out->step = c->step;
     return out->nonfinite ? fail3(c, LBPF_E_UNSTABLE, "non-finite value in the state") : LBPF_OK;
+}
+
+lbpf_status lbpf3d_laplace_dp(lbpf3d* c, double xc, double yc, double zc, double R, double* dP) {
+    if (!c) return LBPF_E_INVALID;
+    if (!dP) return fail3(c, LBPF_E_INVALID, "dP is NULL");
+    if (!(R > 0.0)) return fail3(c, LBPF_E_INVALID, "R must be > 0");
+    if (!c->initialized) return fail3(c, LBPF_E_STATE, "laplace_dp before init");
+    lbpf_status s = run3<false>(c, c->cur);
+    if (s != LBPF_OK) return s;
+    const Model3& m = c->m;
+    const long long n = (long long)m.nx * m.ny * m.nz;
+    const int nblk = (int)std::min<long long>(kRedBlocks, (n + 255) / 256);
+    const float* h = plane3(c, c->cur ? kPlHB : kPlHA);
+    const double r_in = 0.5 * R, r_out = R + 3.0 * c->prm.W;
+    if (m.bc == 0)
+        hipLaunchKernelGGL(laplace3d_partial_kernel<0>, dim3(nblk), dim3(256), 0, c->stream, m, h,
+                           plane3(c, kPlFields), xc, yc, zc, r_in, r_out, c->red);
+    else
+        hipLaunchKernelGGL(laplace3d_partial_kernel<1>, dim3(nblk), dim3(256), 0, c->stream, m, h,
+                           plane3(c, kPlFields), xc, yc, zc, r_in, r_out, c->red);
+    if ((s = hip3(c, hipGetLastError(), "laplace3d_partial_kernel")) != LBPF_OK) return s;
+    double* fin = c->red + (size_t)kRedBlocks * kRedSlots;
+    hipLaunchKernelGGL(reduce3d_final_kernel, dim3(1), dim3(256), 0, c->stream, c->red, nblk, 0u, fin);
+    if ((s = hip3(c, hipGetLastError(), "reduce3d_final_kernel")) != LBPF_OK) return s;
+    double r[kRedSlots];
+    if ((s = hip3(c, hipMemcpyAsync(r, fin, sizeof(r), hipMemcpyDeviceToHost, c->stream), "copy")) != LBPF_OK)
+        return s;
+    if ((s = hip3(c, hipStreamSynchronize(c->stream), "sync")) != LBPF_OK) return s;
+    if (r[1] < 1.0 || r[3] < 1.0) return fail3(c, LBPF_E_INVALID, "empty inner or outer region");
+    *dP = r[0] / r[1] - r[2] / r[3];
+    return LBPF_OK;
 }
 
 int32_t lbpf3d_shape_count(void) { return kNumShapes3; }

@@ -694,6 +694,8 @@ SIGNATURES.update({
     "lbpf3d_step": (_S, [_V, ctypes.c_int64]),
     "lbpf3d_read": (_S, [_V, ctypes.c_int32, _V]),
     "lbpf3d_diagnostics": (_S, [_V, ctypes.POINTER(Diag)]),
+    "lbpf3d_laplace_dp": (_S, [_V, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.POINTER(ctypes.c_double)]),
     "lbpf3d_shape_count": (ctypes.c_int32, []),
     "lbpf3d_shape_info": (_S, [ctypes.c_int32, _I32P, _I32P, _I32P]),
     "lbpf3d_set_shape": (_S, [_V, ctypes.c_int32]),
@@ -802,6 +804,11 @@ class Simulation3D:
             self._c(st)
         return dict(sum_phi=d.sum_phi, sum_rho=d.sum_rho, max_u=d.max_u, nonfinite=d.nonfinite,
                     step=d.step, status=st)
+
+    def laplace_dp(self, xc, yc, zc, R):
+        v = ctypes.c_double()
+        self._c(self.lib.lbpf3d_laplace_dp(self._h, float(xc), float(yc), float(zc), float(R), ctypes.byref(v)))
+        return v.value
 
     def set_shape(self, s):
         self._c(self.lib.lbpf3d_set_shape(self._h, int(s)))

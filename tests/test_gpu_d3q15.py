@@ -141,3 +141,37 @@ def test_full_size_sampled_against_oracle_crop():
         e = rel(g[f][sel], ref)
         print(f"  {f} {e:.2e}", flush=True)
         assert e <= tol, f
+
+
+def _dp_regions(P, n, R, Wd):
+    d = np.minimum(np.abs(np.arange(n) - n / 2), n - np.abs(np.arange(n) - n / 2))
+    r = np.sqrt(d[None, None, :] ** 2 + d[None, :, None] ** 2 + d[:, None, None] ** 2)
+    return P[r <= R / 2].mean() - P[r >= R + 3 * Wd].mean()
+
+
+def test_laplace_dp_matches_oracle():
+    # lbpf3d_laplace_dp against the oracle's FP64 pressure field of Sec. 4.2 on the same regions
+    n, R = 24, 5.0
+    cfg, phi = W.static_droplet3d(n=n, R=R, W=3.0)
+    phi = phi.astype(np.float32).astype(np.float64)
+    o = O.Oracle3D(cfg).init(phi)
+    o.step(200)
+    ref = _dp_regions(o.laplace_pressure(), n, R, cfg["W"])
+    sim = gpu_sim(cfg, phi)
+    sim.step(200)
+    got = sim.laplace_dp(n / 2, n / 2, n / 2, R)
+    print(f"  dP gpu {got:.6e} oracle {ref:.6e}", flush=True)
+    assert abs(got - ref) <= 1e-4 * abs(ref)
+
+
+def test_laplace_law_sphere_on_gpu():
+    # Sec. 4.2 in three dimensions at a size the oracle cannot afford: 64^3, R = 14, rho ratio
+    # 10, 4000 steps: dP = 2 sigma / R within 5 %
+    n, R = 64, 14.0
+    cfg, phi = W.static_droplet3d(n=n, R=R)
+    sim = gpu_sim(cfg, phi)
+    sim.step(4000)
+    dP = sim.laplace_dp(n / 2, n / 2, n / 2, R)
+    expect = 2 * cfg["sigma"] / R
+    print(f"  dP {dP:.5e} vs 2 sigma / R {expect:.5e}", flush=True)
+    assert abs(dP / expect - 1) < 0.05
