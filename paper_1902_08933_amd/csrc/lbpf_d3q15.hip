@@ -491,15 +491,35 @@ __global__ __launch_bounds__(TX * TY) void march3d_kernel(Model3 m, const float*
 
     const int x = x0 + tx, y = y0 + ty;
     const bool col_active = x < m.nx && y < m.ny;
+    // PF: the owned node's g and (phi u) of the next plane are loaded with the halo prefetch
+    // ((phi u) is updated in place, but only by this thread and only at the plane it updates)
+    float gn[PF ? kFP : 1], pun[PF ? 3 : 1];
+    auto load_own = [&](int zz) {
+        if constexpr (PF != 0) {
+            const unsigned c = node3(m, zz, y, x);
+#pragma unroll
+            for (int q = 0; q < kFP; ++q) gn[q] = *pl(gin, P, q, c);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) pun[a] = *pl(phiu, P, a, c);
+        }
+    };
+    if (PF && col_active) load_own(zs);
     for (int z = zs; z < ze; ++z) {
         float g[kFP], h[kHP], pu[3];
         unsigned cell = 0;
         if (col_active) {
             cell = node3(m, z, y, x);
+            if (PF) {
 #pragma unroll
-            for (int q = 0; q < kFP; ++q) g[q] = *pl(gin, P, q, cell);
+                for (int q = 0; q < kFP; ++q) g[q] = gn[PF ? q : 0];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) pu[a] = *pl(phiu, P, a, cell);
+                for (int a = 0; a < 3; ++a) pu[a] = pun[PF ? a : 0];
+            } else {
+#pragma unroll
+                for (int q = 0; q < kFP; ++q) g[q] = *pl(gin, P, q, cell);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) pu[a] = *pl(phiu, P, a, cell);
+            }
         }
         if (PF) {
             // the owned node's h from the stash (written two iterations ago by this thread),
@@ -519,7 +539,10 @@ __global__ __launch_bounds__(TX * TY) void march3d_kernel(Model3 m, const float*
         __syncthreads();
         compute_mu(z + 1);
         __syncthreads();
-        if (PF && z + 1 < ze) load_halo(z + 3, z + 2);
+        if (PF && z + 1 < ze) {
+            load_halo(z + 3, z + 2);
+            if (col_active) load_own(z + 1);
+        }
         if (col_active) {
             const Stencil3 st = gather3(S, pslot(z - 1), pslot(z), pslot(z + 1), mslot(z - 1), mslot(z),
                                         mslot(z + 1), qslot(z - 1), qslot(z), qslot(z + 1), tx, ty);
