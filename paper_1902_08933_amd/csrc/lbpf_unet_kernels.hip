@@ -836,6 +836,9 @@ hipError_t unet_conv(int ks, bool relu, const ConvArgs& a, hipStream_t st) {
     if (a.hw) cot = 32;  // the fused head needs every output channel in one workgroup
     // fewer than ~2 workgroups per CU with 64 channels each: take 32 (more workgroups)
     const long long tiles = (long long)a.N * ((a.H + kConvTR - 1) / kConvTR) * ((a.W + kConvTC - 1) / kConvTC);
+    // a single input chunk gains nothing from the weight prefetch of COT = 64: take 32 at three
+    // workgroups per CU when the grid fills them
+    if (cot == 64 && a.Cin <= kConvCK && tiles * ((a.Cout + 31) / 32) >= 768) cot = 32;
     if (cot == 64 && tiles * ((a.Cout + 63) / 64) < 512) cot = 32;
 #define LBPF_CONV(KS_, C_) return relu ? launch_conv_t<KS_, true, C_>(a, st) : launch_conv_t<KS_, false, C_>(a, st)
     if (ks == 3) {
