@@ -107,3 +107,38 @@ def test_steady_source_flow_matches_analytic():
           f"vs {(nu + xi) * S0:.5e}", flush=True)
     assert err < 2e-3
     assert abs(amp / ((nu + xi) * S0) - 1) < 0.01
+
+
+@pytest.mark.parametrize("model,scheme,drag", [("incompressible", "eq24", 0.0),
+                                               ("nearly_incompressible", "eq24", 0.0),
+                                               ("nearly_incompressible", "remark4", 0.01)])
+def test_full_size_sampled_against_oracle_crop(model, scheme, drag):
+    # the benchmark's 1024^2 source flow, three steps; an oracle run on the 48^2 periodic crop
+    # around the grid corner reproduces its inner 16^2 nodes exactly (three steps reach at most
+    # 3 nodes per step; checked on the CPU against a full-grid oracle run)
+    import torch
+    from paper_1902_08933_amd import lbpf
+    n = 1024
+    cfg, fld = W.single_phase_source(n, n, model=model, S0=1e-4, F0=1e-6, full=True, scheme=scheme,
+                                     drag=drag)
+    fld = {k: f32(v) for k, v in fld.items()}
+    gpu = lbpf.SinglePhase(cfg).init(*(torch.from_numpy(fld[k].astype(np.float32)).cuda()
+                                       for k in ("a0", "ux", "uy", "S", "Fx", "Fy")))
+    gpu.step(3)
+    g = {f: gpu.read(f).double().cpu().numpy() for f in ("rho", "ux", "uy", "p")}
+    idx = np.arange(-24, 24) % n
+    crop = {k: v[np.ix_(idx, idx)] for k, v in fld.items()}
+    orc = SPO.SpOracle(dict(cfg, nx=48, ny=48)).init(crop["a0"], crop["ux"], crop["uy"], crop["S"],
+                                                     crop["Fx"], crop["Fy"])
+    orc.step(3)
+    inner = np.arange(16, 32)
+    sel = np.ix_(idx[inner], idx[inner])
+    o = {f: orc.read(f)[np.ix_(inner, inner)] for f in ("rho", "ux", "uy", "p")}
+    eu = float(np.linalg.norm(np.hypot(g["ux"][sel] - o["ux"], g["uy"][sel] - o["uy"])) /
+               np.linalg.norm(np.hypot(o["ux"], o["uy"])))
+    print(f"{model} {scheme}: full-size u rel L2 {eu:.2e}", flush=True)
+    assert eu < 1e-5
+    if model == "incompressible":
+        assert rel(g["p"][sel], o["p"]) < 1e-5
+    else:
+        assert np.abs(g["rho"][sel] - o["rho"]).max() < 3e-7
