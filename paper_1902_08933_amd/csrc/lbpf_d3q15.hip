@@ -49,6 +49,11 @@ __device__ constexpr int kC[15][3] = {{0, 0, 0},   {1, 0, 0},   {0, 1, 0},  {0, 
                                       {-1, 1, 1},  {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {1, -1, -1}};
 __device__ constexpr int kOpp[15] = {0, 4, 5, 6, 1, 2, 3, 11, 12, 13, 14, 7, 8, 9, 10};
 constexpr float kW0 = 2.0f / 9.0f, kWA = 1.0f / 9.0f, kWC = 1.0f / 72.0f;
+// 3 w_i in the parts of the collision odd in c_i, which carry the momentum: FP32 values whose
+// lattice sum 2 (3 w_A) + 8 (3 w_C) is exactly 1 (the nearest FP32 values of 1/3 and 1/24 sum to
+// 1 + 3e-8, which would multiply the momentum by 1 + 3e-8 omega every step).
+constexpr float k3WA = 0x1.555556p-2f, k3WC = 0x1.555554p-5f;
+static_assert(2.0 * (double)k3WA + 8.0 * (double)k3WC == 1.0, "odd-part weights must sum to 1");
 
 constexpr int kFP = 14;    // g_1..g_14 -> planes 0..13
 constexpr int kHP = 16;    // h_0 hi, h_1..h_14, h_0 lo
@@ -285,10 +290,10 @@ __device__ __forceinline__ void cell3(const Model3& m, int x, int y, int z, unsi
         float hsum = 0.0f;
 #pragma unroll
         for (int q = 1; q <= 14; ++q) hsum += h16[q];
-        auto pair = [&](int qa, int qb, float w, float K, float cu, float cF, float cFt, float cpu,
-                        float cd) {
+        auto pair = [&](int qa, int qb, float w, float w3, float K, float cu, float cF, float cFt,
+                        float cpu, float cd) {
             const float ev = w * (omega * fmaf(r45, cu * cu, Eb) + fgain * fmaf(9.0f * cu, cFt, K));
-            const float od = (3.0f * w) * fmaf(wr, cu, fgain * cF);
+            const float od = w3 * fmaf(wr, cu, fgain * cF);
             gs[qa] = fmaf(g[qa], om1, ev) + od;
             gs[qb] = fmaf(g[qb], om1, ev) - od;
             const float hev = w * hem;
@@ -297,13 +302,13 @@ __device__ __forceinline__ void cell3(const Model3& m, int x, int y, int z, unsi
             hs[qb] = fmaf(h16[qb], ith1, hev) - hod;
         };
 #pragma unroll
-        for (int a = 0; a < 3; ++a) pair(1 + a, 4 + a, kWA, Kf, u[a], F[a], Ft[a], pu_new[a], dpu[a]);
+        for (int a = 0; a < 3; ++a) pair(1 + a, 4 + a, kWA, k3WA, Kf, u[a], F[a], Ft[a], pu_new[a], dpu[a]);
         auto dot = [](float sx, float sy, float sz, const float* v) { return (sx * v[0] + sy * v[1]) + sz * v[2]; };
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int qa = 7 + k, qb = 11 + k;
             const float sx = (float)kC[qa][0], sy = (float)kC[qa][1], sz = (float)kC[qa][2];
-            pair(qa, qb, kWC, Kc, dot(sx, sy, sz, u), dot(sx, sy, sz, F), dot(sx, sy, sz, Ft),
+            pair(qa, qb, kWC, k3WC, Kc, dot(sx, sy, sz, u), dot(sx, sy, sz, F), dot(sx, sy, sz, Ft),
                  dot(sx, sy, sz, pu_new), dot(sx, sy, sz, dpu));
         }
         const int nx = m.nx, ny = m.ny, nz = m.nz;

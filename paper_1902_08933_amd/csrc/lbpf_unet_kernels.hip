@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256, (COT <= 32 && !PFW ? 3 : 2)) void conv_tile_ke
     constexpr int NPATCH = PR * PC * PIECES;
     constexpr int NWT = COT * T * PIECES;
     constexpr int PP = (NPATCH + 255) / 256, PW = (NWT + 255) / 256;
-    constexpr int MF = TR / 4, NF = COT / 16, COTP = COT + 8;
+    constexpr int MF = TR / 4, NF = COT / 16;
     extern __shared__ __attribute__((aligned(16))) bf16 conv_lds[];
     bf16* s_x = conv_lds;
     bf16* s_w = conv_lds + PR * PC * CKP;

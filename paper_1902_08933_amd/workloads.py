@@ -248,6 +248,27 @@ def sphere_phi(nx, ny, nz, R, W, centre=None, cylinder=False):
     return 0.5 + 0.5 * np.tanh(2.0 * (R - r) / W)
 
 
+def layered_poiseuille3d(nxy=4, nz=100, mu_ratio=10.0, nu_B=0.1, G=1e-6, variant="qim",
+                         visc="inverse_linear", sigma=0.001, M_phi=0.1, W=4.0, tau_h=1.0):
+    """Layered Poiseuille flow (Sec. 4.3) in three dimensions: periodic in x and y, halfway
+    bounce-back walls in z, body force G along x, fluid A on top, equal densities,
+    mu_A/mu_B = mu_ratio; the channel coordinate z = k + 1/2 - nz/2 as in layered_phi."""
+    mu_B = nu_B
+    mu_A = mu_ratio * mu_B
+    cfg = dict(BASE3D, name="layered_poiseuille3d", nx=nxy, ny=nxy, nz=nz, bc="walls_z",
+               variant=variant, visc=visc, rho_A=1.0, rho_B=1.0, nu_A=mu_A, nu_B=nu_B,
+               sigma=sigma, W=W, M_phi=M_phi, tau_h=tau_h, force_x=G, mu_A=mu_A, mu_B=mu_B)
+    return cfg, plane_phi3d(nxy, nxy, nz, W, z0=nz / 2.0 - 0.5)
+
+
+def table2_viscosities(mu_ratio, nu_mean=0.1):
+    """Kinematic viscosities (nu_A, nu_B) for the layered channel at equal densities when only
+    the ratio is given: the geometric mean is held at nu_mean, so both relaxation times stay
+    moderate (at ratio 1000, tau = 10.0 and 0.509 instead of 300.5 and 0.8)."""
+    r = float(mu_ratio) ** 0.5
+    return nu_mean * r, nu_mean / r
+
+
 def static_droplet3d(n=32, R=8.0, variant="qim", rho_ratio=10.0, sigma=0.01, tau=0.8,
                      tau_h=0.8, M_phi=0.02, W=4.0, cylinder=False):
     """Static droplet of phase A in an n^3 periodic box (the two-dimensional static-droplet

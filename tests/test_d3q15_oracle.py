@@ -260,6 +260,31 @@ def test_planar_interface_is_stationary():
     assert np.abs(o.read("uz")).max() < 1e-6 and np.abs(o.read("ux")).max() < 1e-12
 
 
+def test_layered_poiseuille_table2():
+    # Sec. 4.3, eq. (37) and the printed error norm, between z walls at the printed height
+    # NZ = 100, viscosity ratio 10 (nu_B = 0.1), 40000 steps; Table 2 bounds the error the
+    # method reaches (1.30 %); measured 0.38 %, as in two dimensions. The flow is x- and
+    # y-invariant, so a 3 x 3 column stands in for the printed NX = 10.
+    from test_oracle_physics import load_golden
+    table = load_golden("table2_layered_poiseuille.txt")
+    ratio, nz, nu_B = 10.0, 100, 0.1
+    bound = table[table[:, 0] == ratio][0, 1]
+    h = nz / 2.0
+    mu_B, mu_A = nu_B, ratio * nu_B
+    G = 5e-5 * (mu_A + mu_B) / h ** 2
+    cfg, phi = W.layered_poiseuille3d(nxy=3, nz=nz, mu_ratio=ratio, nu_B=nu_B, G=G)
+    o = O.Oracle3D(cfg).init(phi)
+    o.step(40000)
+    u = o.read("ux")
+    ua = W.layered_analytic_ux(nz, G, mu_A, mu_B)
+    err = np.abs(u[:, 0, 0] - ua).sum() / np.abs(ua).sum()
+    assert err <= bound
+    assert np.abs(u - u[:, :1, :1]).max() < 1e-12 * np.abs(ua).max()
+    # the only normal flow is the small one across the interface while the tanh profile settles
+    # onto its discrete equilibrium (measured 1.3e-4 of the peak)
+    assert np.abs(o.read("uz")).max() < 1e-3 * np.abs(ua).max()
+
+
 def test_state_roundtrip_is_exact():
     cfg, phi = W.spinodal3d(n=8, seed=2, amplitude=0.1)
     a = O.Oracle3D(cfg).init(phi)
