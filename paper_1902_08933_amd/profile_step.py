@@ -9,6 +9,7 @@ python -m paper_1902_08933_amd.profile_step --copy-mib 2048 --steps 10   (bandwi
     scaling the FETCH_SIZE / WRITE_SIZE counters)
 """
 import argparse
+import re
 import sys
 
 from . import lbpf, workloads
@@ -129,9 +130,10 @@ def main():
                   f"{n ** 3 / (ms * 1e-3) / 1e6:.0f} MLUPS, {272 * n ** 3 / (ms * 1e-3) / 1e9:.0f} GB/s",
                   flush=True)
         return 0
-    if a.workload.startswith("sp") or a.workload.startswith("r4_"):
-        r4 = a.workload.startswith("r4_")
-        n = int(a.workload[3:] if r4 else a.workload[2:])
+    single = re.fullmatch(r"(sp|r4_)(\d+)", a.workload)  # "spinodal<N>" is the two-phase step
+    if single:
+        r4 = single.group(1) == "r4_"
+        n = int(single.group(2))
         ms = run_sp(torch, n, a.steps, a.warmup, remark4=r4)
         b = 244 if r4 else 92
         print(f"{a.workload}: {ms:.4f} ms/step, {n * n / (ms * 1e-3) / 1e6:.0f} MLUPS, "
