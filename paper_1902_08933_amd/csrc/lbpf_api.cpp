@@ -19,15 +19,13 @@
 namespace lbpf {
 int tile_count();
 void tile_shape(int i, int* tx, int* rows, int* nt);
-hipError_t launch_step(int tile, const Model& m, const float* fin, float* fout, const float* hin,
-                       float* hout, const float* pin, float* pout, float* phiu, hipStream_t st);
-hipError_t launch_fields(const Model& m, const float* fin, const float* hin, const float* pin,
-                         float* phiu, float* fields, hipStream_t st);
+hipError_t launch_step(int tile, const Model& m, const float* in, float* out, hipStream_t st);
+hipError_t launch_fields(const Model& m, const float* in, float* fields, hipStream_t st);
 hipError_t launch_init(const Model& m, const float* phi0, const float* ux0, const float* uy0,
-                       const float* p0, float* f, float* h, float* pp, float* phiu, hipStream_t st);
-hipError_t launch_diag(const Model& m, const float* f, const float* h, const float* pp,
-                       const float* phiu, const float* fields, double* red, hipStream_t st);
-hipError_t launch_laplace(const Model& m, const float* h, const float* fields, double* phi64,
+                       const float* p0, float* copy, hipStream_t st);
+hipError_t launch_diag(const Model& m, const float* copy, const float* fields, double* red,
+                       hipStream_t st);
+hipError_t launch_laplace(const Model& m, const float* copy, const float* fields, double* phi64,
                           double xc, double yc, double r_in, double r_out, double* red,
                           hipStream_t st);
 hipError_t launch_probe(int mode, const void* src, void* dst, size_t bytes, int blocks, hipStream_t st);
@@ -85,7 +83,8 @@ static const char* validate(const lbpf_params* p) {
     if (!p) return "params is NULL";
     if (p->nx < 3 || p->ny < 3) return "nx and ny must be >= 3";
     if (p->nx >= (1 << 24) || p->ny >= (1 << 24)) return "nx and ny must be below 2^24";
-    // kernels address a node inside a plane with a 32-bit byte offset
+    // kernels address a node inside a plane with a 32-bit byte offset (planes stored separately
+    // when the grid is too large to interleave them)
     if ((long long)p->ny * pitch_of(p->nx) + plane_pad() >= (1LL << 30))
         return "grid too large (a plane of ny * pitch nodes must hold fewer than 2^30 floats)";
     if (p->variant != LBPF_QIM && p->variant != LBPF_IM) return "variant must be LBPF_QIM or LBPF_IM";
@@ -114,10 +113,23 @@ static size_t plane_pad() {
     if (v < 0) v = 0;
     return (size_t)(v + 63) / 64 * 64;
 }
-static size_t plane_floats(const lbpf_params* p) { return (size_t)p->ny * pitch_of(p->nx) + plane_pad(); }
+// Layout of a population copy (see lbpf_model.hpp): planes interleaved by row unless
+// LBPF_STATE_LAYOUT=planar, or unless a copy of 21 interleaved planes would need per-lane offsets
+// of 2^30 floats or more. The choice must not change between lbpf_workspace_size() and
+// lbpf_create() of one simulation.
+static bool interleaved(const lbpf_params* p) {
+    const char* e = getenv("LBPF_STATE_LAYOUT");
+    if (e && strcmp(e, "planar") == 0) return false;
+    return (long long)p->ny * kCopyPlanes * pitch_of(p->nx) < (1LL << 30);
+}
+static size_t copy_floats(const lbpf_params* p) {
+    const size_t rows = (size_t)p->ny * pitch_of(p->nx);
+    return interleaved(p) ? kCopyPlanes * rows + plane_pad() : kCopyPlanes * (rows + plane_pad());
+}
+static size_t f64_floats(const lbpf_params* p) { return 2 * (size_t)p->ny * pitch_of(p->nx); }
 
 static size_t ws_bytes(const lbpf_params* p) {
-    return plane_floats(p) * sizeof(float) * kNumPlanes + kRedDoubles * sizeof(double);
+    return (2 * copy_floats(p) + f64_floats(p)) * sizeof(float) + kRedDoubles * sizeof(double);
 }
 
 // Model coefficients from the physical parameters:
@@ -127,8 +139,15 @@ static Model make_model(const lbpf_params* p) {
     Model m{};
     m.nx = p->nx;
     m.ny = p->ny;
-    m.pitch = pitch_of(p->nx);
-    m.plane = (long long)plane_floats(p);
+    m.xpitch = pitch_of(p->nx);
+    if (interleaved(p)) {
+        m.pitch = kCopyPlanes * m.xpitch;
+        m.plane = m.xpitch;
+    } else {
+        m.pitch = m.xpitch;
+        m.plane = (long long)p->ny * m.xpitch + (long long)plane_pad();
+    }
+    m.copy = (long long)copy_floats(p);
     m.variant = p->variant;
     m.pscheme = p->pscheme;
     m.fsurf = p->fsurf;
@@ -161,11 +180,12 @@ static Model make_model(const lbpf_params* p) {
     return m;
 }
 
-static float* plane(lbpf_ctx* c, int k) { return c->ws + (size_t)k * c->m.plane; }
-static float* fcur(lbpf_ctx* c) { return plane(c, c->cur ? kPlaneFB : kPlaneFA); }
-static float* hcur(lbpf_ctx* c) { return plane(c, c->cur ? kPlaneHB : kPlaneHA); }
-static float* pcur(lbpf_ctx* c) { return plane(c, c->cur ? kPlanePB : kPlanePA); }
-static double* red(lbpf_ctx* c) { return (double*)plane(c, kNumPlanes); }
+static float* copy_of(lbpf_ctx* c, int k) { return c->ws + (size_t)k * c->m.copy; }
+static float* cur_copy(lbpf_ctx* c) { return copy_of(c, c->cur); }
+// field scratch: the population copy not holding the state
+static float* fields(lbpf_ctx* c) { return copy_of(c, 1 - c->cur); }
+static double* phi64(lbpf_ctx* c) { return (double*)copy_of(c, 2); }
+static double* red(lbpf_ctx* c) { return (double*)(copy_of(c, 2) + 2 * (size_t)c->m.ny * c->m.xpitch); }
 
 static lbpf_status check_ctx(lbpf_ctx* c, bool need_init) {
     if (!c) return LBPF_E_INVALID;
@@ -214,8 +234,7 @@ static lbpf_status init_copy(lbpf_ctx* c, int copy, const float* phi, const floa
     if (lbpf_status s = check_ctx(c, false)) return s;
     if (!phi) return fail(c, LBPF_E_INVALID, "phi is NULL");
     c->cur = copy;
-    hipError_t e = launch_init(c->m, phi, ux, uy, p, fcur(c), hcur(c), pcur(c), plane(c, kPlanePhiU),
-                               c->stream);
+    hipError_t e = launch_init(c->m, phi, ux, uy, p, cur_copy(c), c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "init kernel");
     c->initialized = 1;
     c->step = 0;
@@ -231,10 +250,7 @@ lbpf_status lbpf_step(lbpf_ctx* c, int64_t nsteps) {
     if (nsteps < 0) return fail(c, LBPF_E_INVALID, "nsteps must be >= 0");
     for (int64_t t = 0; t < nsteps; ++t) {
         const int a = c->cur, b = 1 - a;
-        hipError_t e = launch_step(c->tile, c->m, plane(c, a ? kPlaneFB : kPlaneFA),
-                                   plane(c, b ? kPlaneFB : kPlaneFA), plane(c, a ? kPlaneHB : kPlaneHA),
-                                   plane(c, b ? kPlaneHB : kPlaneHA), plane(c, a ? kPlanePB : kPlanePA),
-                                   plane(c, b ? kPlanePB : kPlanePA), plane(c, kPlanePhiU), c->stream);
+        hipError_t e = launch_step(c->tile, c->m, copy_of(c, a), copy_of(c, b), c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "step kernel");
         c->cur = b;
         c->step += 1;
@@ -243,8 +259,7 @@ lbpf_status lbpf_step(lbpf_ctx* c, int64_t nsteps) {
 }
 
 static lbpf_status run_fields(lbpf_ctx* c) {
-    hipError_t e = launch_fields(c->m, fcur(c), hcur(c), pcur(c), plane(c, kPlanePhiU),
-                                 plane(c, kPlaneFields), c->stream);
+    hipError_t e = launch_fields(c->m, cur_copy(c), fields(c), c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "field kernel");
     return LBPF_OK;
 }
@@ -254,7 +269,7 @@ lbpf_status lbpf_read(lbpf_ctx* c, int32_t field, float* dst) {
     if (field < LBPF_FIELD_PHI || field > LBPF_FIELD_MU) return fail(c, LBPF_E_INVALID, "unknown field %d", field);
     if (!dst) return fail(c, LBPF_E_INVALID, "dst is NULL");
     if (lbpf_status s = run_fields(c)) return s;
-    const float* src = plane(c, kPlaneFields + field);
+    const float* src = fields(c) + (size_t)field * c->m.plane;
     hipError_t e = hipMemcpy2DAsync(dst, (size_t)c->m.nx * sizeof(float), src,
                                     (size_t)c->m.pitch * sizeof(float), (size_t)c->m.nx * sizeof(float),
                                     (size_t)c->m.ny, hipMemcpyDeviceToDevice, c->stream);
@@ -266,8 +281,7 @@ lbpf_status lbpf_diagnostics(lbpf_ctx* c, lbpf_diag* out) {
     if (lbpf_status s = check_ctx(c, true)) return s;
     if (!out) return fail(c, LBPF_E_INVALID, "out is NULL");
     if (lbpf_status s = run_fields(c)) return s;
-    hipError_t e = launch_diag(c->m, fcur(c), hcur(c), pcur(c), plane(c, kPlanePhiU),
-                               plane(c, kPlaneFields), red(c), c->stream);
+    hipError_t e = launch_diag(c->m, cur_copy(c), fields(c), red(c), c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "diagnostic kernels");
     double r[4];
     e = hipMemcpyAsync(r, red(c) + (size_t)kRedBlocks * kRedSlots, sizeof r, hipMemcpyDeviceToHost, c->stream);
@@ -289,7 +303,7 @@ lbpf_status lbpf_laplace_dp(lbpf_ctx* c, double xc, double yc, double R, double*
     if (!dP) return fail(c, LBPF_E_INVALID, "dP is NULL");
     if (!(R > 0.0)) return fail(c, LBPF_E_INVALID, "R must be > 0");
     if (lbpf_status s = run_fields(c)) return s;
-    hipError_t e = launch_laplace(c->m, hcur(c), plane(c, kPlaneFields), (double*)plane(c, kPlaneF64),
+    hipError_t e = launch_laplace(c->m, cur_copy(c), fields(c), phi64(c),
                                   xc, yc, 0.5 * R, R + 3.0 * c->params.W, red(c), c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "laplace kernels");
     double r[4];
@@ -302,14 +316,15 @@ lbpf_status lbpf_laplace_dp(lbpf_ctx* c, double xc, double yc, double R, double*
     return LBPF_OK;
 }
 
-// checkpoint layout: 64-byte header {magic, version, nx, ny, pitch, step}, then the planes
-// f_1..8, h (10 planes), p, (phi u)_x, (phi u)_y, each ny*pitch floats
+// checkpoint layout: 64-byte header {magic, version, nx, ny, row stride, step, plane stride,
+// copy floats}, then the population copy holding the state, as stored (f_1..8, h, p, (phi u)_x,y;
+// see lbpf_model.hpp). A checkpoint loads into a simulation of the same grid and layout.
 static const int64_t kMagic = 0x4650424C;  // "LBPF"
-static const int kStatePlanes = kFPlanes + kHPlanes + 1 + 2;
+static const int64_t kVersion = 2;
 
 lbpf_status lbpf_state_size(const lbpf_ctx* c, size_t* bytes) {
     if (!c || !bytes) return LBPF_E_INVALID;
-    *bytes = 64 + (size_t)kStatePlanes * c->m.plane * sizeof(float);
+    *bytes = 64 + (size_t)c->m.copy * sizeof(float);
     return LBPF_OK;
 }
 
@@ -317,16 +332,13 @@ lbpf_status lbpf_save_state(lbpf_ctx* c, void* dst) {
     if (lbpf_status s = check_ctx(c, true)) return s;
     if (!dst) return fail(c, LBPF_E_INVALID, "dst is NULL");
     // the header is copied synchronously so that hdr may be reused at once
-    c->hdr[0] = kMagic; c->hdr[1] = 1; c->hdr[2] = c->m.nx; c->hdr[3] = c->m.ny;
-    c->hdr[4] = c->m.pitch; c->hdr[5] = c->step; c->hdr[6] = c->m.plane; c->hdr[7] = 0;
+    c->hdr[0] = kMagic; c->hdr[1] = kVersion; c->hdr[2] = c->m.nx; c->hdr[3] = c->m.ny;
+    c->hdr[4] = c->m.pitch; c->hdr[5] = c->step; c->hdr[6] = c->m.plane; c->hdr[7] = c->m.copy;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = hipMemcpy(dst, c->hdr, 64, hipMemcpyHostToDevice);
-    const size_t pb = (size_t)c->m.plane * sizeof(float);
-    char* d = (char*)dst + 64;
-    if (e == hipSuccess) e = hipMemcpyAsync(d, fcur(c), kFPlanes * pb, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(d + kFPlanes * pb, hcur(c), kHPlanes * pb, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(d + (kFPlanes + kHPlanes) * pb, pcur(c), pb, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(d + (kFPlanes + kHPlanes + 1) * pb, plane(c, kPlanePhiU), 2 * pb, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((char*)dst + 64, cur_copy(c), (size_t)c->m.copy * sizeof(float),
+                           hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "save state");
     return LBPF_OK;
 }
@@ -338,16 +350,12 @@ lbpf_status lbpf_load_state(lbpf_ctx* c, const void* src) {
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = hipMemcpy(hdr, src, 64, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(c, e, "load state header");
-    if (hdr[0] != kMagic || hdr[1] != 1 || hdr[2] != c->m.nx || hdr[3] != c->m.ny || hdr[4] != c->m.pitch ||
-        hdr[6] != c->m.plane)
-        return fail(c, LBPF_E_INVALID, "checkpoint does not match this grid");
+    if (hdr[0] != kMagic || hdr[1] != kVersion || hdr[2] != c->m.nx || hdr[3] != c->m.ny ||
+        hdr[4] != c->m.pitch || hdr[6] != c->m.plane || hdr[7] != c->m.copy)
+        return fail(c, LBPF_E_INVALID, "checkpoint does not match this grid and layout");
     c->cur = 0;
-    const size_t pb = (size_t)c->m.plane * sizeof(float);
-    const char* s = (const char*)src + 64;
-    e = hipMemcpyAsync(fcur(c), s, kFPlanes * pb, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(hcur(c), s + kFPlanes * pb, kHPlanes * pb, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(pcur(c), s + (kFPlanes + kHPlanes) * pb, pb, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(plane(c, kPlanePhiU), s + (kFPlanes + kHPlanes + 1) * pb, 2 * pb, hipMemcpyDeviceToDevice, c->stream);
+    e = hipMemcpyAsync(cur_copy(c), (const char*)src + 64, (size_t)c->m.copy * sizeof(float),
+                       hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "load state");
     c->step = hdr[5];
     c->initialized = 1;
@@ -407,7 +415,7 @@ lbpf_status lbpf_fields_to_nhwc(lbpf_ctx* c, float* dst, const float* shift, con
             return fail(c, LBPF_E_INVALID, "scale must be finite and nonzero, shift finite");
     if (((uintptr_t)dst) % 16) return fail(c, LBPF_E_INVALID, "dst must be 16-byte aligned");
     if (lbpf_status s = run_fields(c)) return s;
-    hipError_t e = launch_fields_to_nhwc(c->m, plane(c, kPlaneFields), dst, shift, scale, c->stream);
+    hipError_t e = launch_fields_to_nhwc(c->m, fields(c), dst, shift, scale, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "fields to NHWC");
     return LBPF_OK;
 }
@@ -417,9 +425,9 @@ lbpf_status lbpf_init_from_nhwc(lbpf_ctx* c, const float* src, const float* shif
     if (lbpf_status s = check_ctx(c, false)) return s;
     if (!src || !shift || !scale) return fail(c, LBPF_E_INVALID, "NULL argument");
     if (((uintptr_t)src) % 16) return fail(c, LBPF_E_INVALID, "src must be 16-byte aligned");
-    // dense fields in the field scratch planes (each plane holds at least nx*ny floats)
+    // dense nx*ny fields in the copy that init does not write (it holds 21 ny*pitch floats)
     float* d[4];
-    for (int k = 0; k < 4; ++k) d[k] = plane(c, kPlaneFields + k);
+    for (int k = 0; k < 4; ++k) d[k] = fields(c) + (size_t)k * c->m.nx * c->m.ny;
     hipError_t e = launch_nhwc_to_dense(c->m, src, d[0], d[1], d[2], d[3], shift, scale, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "NHWC to fields");
     if (step < 0) return fail(c, LBPF_E_INVALID, "step must be >= 0");
@@ -741,15 +749,8 @@ lbpf_status lbpf_batch_step_each(lbpf_batch* b, int64_t nsteps) {
             lbpf_ctx* c = b->inst[k];
             if (b->frozen[k]) {  // held fixed: copy the state into the other population copy
                 const int a = c->cur, o = 1 - a;
-                const size_t pb = (size_t)c->m.plane * sizeof(float);
-                hipError_t e = hipMemcpyAsync(plane(c, o ? kPlaneFB : kPlaneFA), plane(c, a ? kPlaneFB : kPlaneFA),
-                                              kFPlanes * pb, hipMemcpyDeviceToDevice, b->stream);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(plane(c, o ? kPlaneHB : kPlaneHA), plane(c, a ? kPlaneHB : kPlaneHA),
-                                       kHPlanes * pb, hipMemcpyDeviceToDevice, b->stream);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(plane(c, o ? kPlanePB : kPlanePA), plane(c, a ? kPlanePB : kPlanePA),
-                                       pb, hipMemcpyDeviceToDevice, b->stream);
+                hipError_t e = hipMemcpyAsync(copy_of(c, o), copy_of(c, a), (size_t)c->m.copy * sizeof(float),
+                                              hipMemcpyDeviceToDevice, b->stream);
                 if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "frozen copy: %s", hipGetErrorString(e));
                 c->cur = o;
                 continue;

@@ -18,7 +18,7 @@
 // strip is read from HBM once; only the two ghost columns on each side and the four ghost
 // rows at the ends of a chunk are read twice (from L2 when the neighbouring workgroup has just
 // read them). Each node moves 168 bytes of HBM traffic per step: f_1..8, h_0 hi, h_1..8,
-// h_0 lo, p, (phi u)_x,y, read once and written once.
+// h_0 lo, p, (phi u)_x,y, read once from one population copy and written once to the other.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -81,8 +81,8 @@ template <int TX, int TY, int BC>
 __device__ __forceinline__ void march_load(const Model& m, const float* __restrict__ fin,
                                            const float* __restrict__ hin,
                                            const float* __restrict__ pin,
-                                           const float* __restrict__ phiu, int x0, int Y, int ye,
-                                           int tid, MarchLoads<TX, TY>& L) {
+                                           const float* __restrict__ phiu_in, int x0, int Y,
+                                           int ye, int tid, MarchLoads<TX, TY>& L) {
     const int nx = m.nx, ny = m.ny, pitch = m.pitch;
     const long long P = m.plane;
     const int tx = tid % TX, r = tid / TX;
@@ -104,8 +104,8 @@ __device__ __forceinline__ void march_load(const Model& m, const float* __restri
         const unsigned cell = node_off(rowO, pitch, x0 + tx);
 #pragma unroll
         for (int q = 0; q < kFPlanes; ++q) L.f[q] = *pl(fin, P, q, cell);
-        L.pu[0] = *pl(phiu, P, 0, cell);
-        L.pu[1] = *pl(phiu, P, 1, cell);
+        L.pu[0] = *pl(phiu_in, P, 0, cell);
+        L.pu[1] = *pl(phiu_in, P, 1, cell);
     }
     L.p = *pl(pin, P, 0, node_off(src_row<BC>(Y + 1 + r, ny), pitch, wrap(x0 + tx, nx)));
     if (tid < 4 * TY) {
@@ -144,7 +144,9 @@ __device__ __forceinline__ void march_chunk(const Model& m, const float* __restr
                                             const float* __restrict__ hin,
                                             float* __restrict__ hout,
                                             const float* __restrict__ pin,
-                                            float* __restrict__ pout, float* __restrict__ phiu,
+                                            float* __restrict__ pout,
+                                            const float* __restrict__ phiu_in,
+                                            float* __restrict__ phiu_out,
                                             float* __restrict__ fields, int x0, int ys,
                                             MarchLds<TX, NT>& S) {
     using L_ = MarchLds<TX, NT>;
@@ -163,7 +165,7 @@ __device__ __forceinline__ void march_chunk(const Model& m, const float* __restr
 
     // loads of the first step are issued before the prologue so that both are in flight together
     MarchLoads<TX, TY> L;
-    march_load<TX, TY, BC>(m, fin, hin, pin, phiu, x0, ys, ye, tid, L);
+    march_load<TX, TY, BC>(m, fin, hin, pin, phiu_in, x0, ys, ye, tid, L);
 
     // ---- prologue: phi rows ys-2 .. ys+1, pressure and mu rows ys-1, ys --------------------
     for (int j = tid; j < 4 * PX; j += NT) {
@@ -225,13 +227,13 @@ __device__ __forceinline__ void march_chunk(const Model& m, const float* __restr
         }
         __syncthreads();
         // (3) with PF, issue the loads of the next step first; then update the owned node
-        if (PF && Y + TY < ye) march_load<TX, TY, BC>(m, fin, hin, pin, phiu, x0, Y + TY, ye, tid, L);
+        if (PF && Y + TY < ye) march_load<TX, TY, BC>(m, fin, hin, pin, phiu_in, x0, Y + TY, ye, tid, L);
         if (active) {
             const Stencil st = gather(s_phh, s_phl, prow(rowO - 1), prow(rowO), prow(rowO + 1), tx + 2,
                                       s_mu, s_p, mrow(rowO - 1), mrow(rowO), mrow(rowO + 1), tx + 1);
-            cell_update<COLLIDE, BC>(m, xo, rowO, cell, f, hc, pu, st, fout, hout, pout, phiu, fields);
+            cell_update<COLLIDE, BC>(m, xo, rowO, cell, f, hc, pu, st, fout, hout, pout, phiu_out, fields);
         }
-        if (!PF && Y + TY < ye) march_load<TX, TY, BC>(m, fin, hin, pin, phiu, x0, Y + TY, ye, tid, L);
+        if (!PF && Y + TY < ye) march_load<TX, TY, BC>(m, fin, hin, pin, phiu_in, x0, Y + TY, ye, tid, L);
     }
 }
 
@@ -242,12 +244,13 @@ __global__ __launch_bounds__(NT) void strip_kernel(Model m, const float* __restr
                                                    float* __restrict__ hout,
                                                    const float* __restrict__ pin,
                                                    float* __restrict__ pout,
-                                                   float* __restrict__ phiu,
+                                                   const float* __restrict__ phiu_in,
+                                                   float* __restrict__ phiu_out,
                                                    float* __restrict__ fields, int nsx, int nsy) {
     __shared__ MarchLds<TX, NT> S;
     const int blk = xcd_tile(blockIdx.x, nsx * nsy);
-    march_chunk<TX, NT, CH, PF, COLLIDE, BC>(m, fin, fout, hin, hout, pin, pout, phiu, fields,
-                                             (blk % nsx) * TX, (blk / nsx) * CH, S);
+    march_chunk<TX, NT, CH, PF, COLLIDE, BC>(m, fin, fout, hin, hout, pin, pout, phiu_in, phiu_out,
+                                             fields, (blk % nsx) * TX, (blk / nsx) * CH, S);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -378,7 +381,7 @@ __global__ void phi64_kernel(Model m, const float* __restrict__ h, double* __res
     const long long cell = (long long)y * m.pitch + x, P = m.plane;
     double phi = (double)h[cell] + (double)h[kH0Lo * P + cell];
     for (int q = 1; q <= 8; ++q) phi += (double)h[q * P + cell];
-    phi64[cell] = phi;
+    phi64[(long long)y * m.xpitch + x] = phi;
 }
 
 // Laplace pressure of Sec. 4.2 in FP64, P = p0 - kappa phi lap(phi) + kappa |grad phi|^2 / 2 + p
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(256) void laplace_partial_kernel(Model m, const dou
         const int x = (int)(k % m.nx), y = (int)(k / m.nx);
         auto at = [&](int dx, int dy) {
             const int sy = m.bc ? src_row<1>(y + dy, m.ny) : src_row<0>(y + dy, m.ny);
-            return phi64[(long long)sy * m.pitch + wrap(x + dx, m.nx)];
+            return phi64[(long long)sy * m.xpitch + wrap(x + dx, m.nx)];
         };
         const double c = at(0, 0);
         const double gx = (at(1, 0) - at(-1, 0)) / 3.0 + ((at(1, 1) - at(-1, 1)) + (at(1, -1) - at(-1, -1))) / 12.0;
@@ -444,19 +447,19 @@ void tile_shape(int i, int* tx, int* ch, int* nt) {
 
 template <int TX, int NT, int CH, bool PF, bool C>
 static hipError_t launch_strip_t(const Model& m, const float* fin, float* fout, const float* hin,
-                                 float* hout, const float* pin, float* pout, float* phiu,
-                                 float* fields, hipStream_t st) {
+                                 float* hout, const float* pin, float* pout, const float* phiu_in,
+                                 float* phiu_out, float* fields, hipStream_t st) {
     const int nsx = (m.nx + TX - 1) / TX, nsy = (m.ny + CH - 1) / CH;
     if (m.bc == 1)
         hipLaunchKernelGGL((strip_kernel<TX, NT, CH, PF, C, 1>), dim3(nsx * nsy), dim3(NT), 0, st,
-                           m, fin, fout, hin, hout, pin, pout, phiu, fields, nsx, nsy);
+                           m, fin, fout, hin, hout, pin, pout, phiu_in, phiu_out, fields, nsx, nsy);
     else
         hipLaunchKernelGGL((strip_kernel<TX, NT, CH, PF, C, 0>), dim3(nsx * nsy), dim3(NT), 0, st,
-                           m, fin, fout, hin, hout, pin, pout, phiu, fields, nsx, nsy);
+                           m, fin, fout, hin, hout, pin, pout, phiu_in, phiu_out, fields, nsx, nsy);
     return hipGetLastError();
 }
 
-#define LBPF_ARGS m, fin, fout, hin, hout, pin, pout, phiu, fields, st
+#define LBPF_ARGS m, fin, fout, hin, hout, pin, pout, phiu_in, phiu_out, fields, st
 #define LBPF_STRIP_CASES(C)                                                  \
     case 0: return launch_strip_t<64, 256, 4, false, C>(LBPF_ARGS);         \
     case 1: return launch_strip_t<64, 256, 16, false, C>(LBPF_ARGS);        \
@@ -480,7 +483,8 @@ static hipError_t launch_strip_t(const Model& m, const float* fin, float* fout, 
 template <bool C>
 static hipError_t launch_fused(int tile, const Model& m, const float* fin, float* fout,
                                const float* hin, float* hout, const float* pin, float* pout,
-                               float* phiu, float* fields, hipStream_t st) {
+                               const float* phiu_in, float* phiu_out, float* fields,
+                               hipStream_t st) {
     switch (tile) {
         LBPF_STRIP_CASES(C)
         default: return hipErrorInvalidValue;
@@ -495,15 +499,12 @@ static hipError_t launch_fused(int tile, const Model& m, const float* fin, float
 // A frozen instance's chunk is copied through unchanged so that all instances share parity.
 // ---------------------------------------------------------------------------------------------
 template <int TX, int NT>
-__device__ __forceinline__ void copy_chunk(const Model& m, const float* fin, float* fout,
-                                           const float* hin, float* hout, const float* pin,
-                                           float* pout, int x0, int ys, int ch) {
+__device__ __forceinline__ void copy_chunk(const Model& m, const float* src, float* dst, int x0,
+                                           int ys, int ch) {
     const int w = min(TX, m.nx - x0), h = min(ch, m.ny - ys);
     for (int i = threadIdx.x; i < w * h; i += NT) {
         const long long c = (long long)(ys + i / w) * m.pitch + x0 + i % w;
-        for (int q = 0; q < kFPlanes; ++q) fout[q * m.plane + c] = fin[q * m.plane + c];
-        for (int q = 0; q < kHPlanes; ++q) hout[q * m.plane + c] = hin[q * m.plane + c];
-        pout[c] = pin[c];
+        for (int q = 0; q < kCopyPlanes; ++q) dst[q * m.plane + c] = src[q * m.plane + c];
     }
 }
 
@@ -516,25 +517,20 @@ __global__ __launch_bounds__(NT) void batch_kernel(const BatchInst* __restrict__
         const BatchItem w = items[it];
         const BatchInst& I = insts[w.inst];
         const Model m = I.m;
-        float* ws = I.ws;
         const long long P = m.plane;
-        const int a = parity, b = 1 - parity;
-        const float* fin = ws + (a ? kPlaneFB : kPlaneFA) * P;
-        float* fout = ws + (b ? kPlaneFB : kPlaneFA) * P;
-        const float* hin = ws + (a ? kPlaneHB : kPlaneHA) * P;
-        float* hout = ws + (b ? kPlaneHB : kPlaneHA) * P;
-        const float* pin = ws + (a ? kPlanePB : kPlanePA) * P;
-        float* pout = ws + (b ? kPlanePB : kPlanePA) * P;
-        float* phiu = ws + kPlanePhiU * P;
+        const float* in = I.ws + parity * m.copy;
+        float* out = I.ws + (1 - parity) * m.copy;
         const int x0 = (w.chunk % I.nsx) * TX, ys = (w.chunk / I.nsx) * CH;
         if (I.frozen)
-            copy_chunk<TX, NT>(m, fin, fout, hin, hout, pin, pout, x0, ys, CH);
+            copy_chunk<TX, NT>(m, in, out, x0, ys, CH);
         else if (m.bc == 1)
-            march_chunk<TX, NT, CH, PF, true, 1>(m, fin, fout, hin, hout, pin, pout, phiu, nullptr,
-                                                 x0, ys, S);
+            march_chunk<TX, NT, CH, PF, true, 1>(m, in + kCopyF * P, out + kCopyF * P, in + kCopyH * P,
+                                                 out + kCopyH * P, in + kCopyP * P, out + kCopyP * P,
+                                                 in + kCopyPhiU * P, out + kCopyPhiU * P, nullptr, x0, ys, S);
         else
-            march_chunk<TX, NT, CH, PF, true, 0>(m, fin, fout, hin, hout, pin, pout, phiu, nullptr,
-                                                 x0, ys, S);
+            march_chunk<TX, NT, CH, PF, true, 0>(m, in + kCopyF * P, out + kCopyF * P, in + kCopyH * P,
+                                                 out + kCopyH * P, in + kCopyP * P, out + kCopyP * P,
+                                                 in + kCopyPhiU * P, out + kCopyPhiU * P, nullptr, x0, ys, S);
         __syncthreads();  // LDS is reused by the next item
     }
 }
@@ -585,20 +581,25 @@ hipError_t launch_batch(int tile, const BatchInst* insts, const BatchItem* items
     return hipLaunchKernel(fn, dim3(grid), dim3(nt), args, 0, st);
 }
 
-hipError_t launch_step(int tile, const Model& m, const float* fin, float* fout, const float* hin,
-                       float* hout, const float* pin, float* pout, float* phiu, hipStream_t st) {
-    return launch_fused<true>(tile, m, fin, fout, hin, hout, pin, pout, phiu, nullptr, st);
+hipError_t launch_step(int tile, const Model& m, const float* in, float* out, hipStream_t st) {
+    const long long P = m.plane;
+    return launch_fused<true>(tile, m, in + kCopyF * P, out + kCopyF * P, in + kCopyH * P,
+                              out + kCopyH * P, in + kCopyP * P, out + kCopyP * P,
+                              in + kCopyPhiU * P, out + kCopyPhiU * P, nullptr, st);
 }
 
-hipError_t launch_fields(const Model& m, const float* fin, const float* hin, const float* pin,
-                         float* phiu, float* fields, hipStream_t st) {
-    return launch_fused<false>(1, m, fin, nullptr, hin, nullptr, pin, nullptr, phiu, fields, st);
+hipError_t launch_fields(const Model& m, const float* in, float* fields, hipStream_t st) {
+    const long long P = m.plane;
+    return launch_fused<false>(1, m, in + kCopyF * P, nullptr, in + kCopyH * P, nullptr,
+                               in + kCopyP * P, nullptr, in + kCopyPhiU * P, nullptr, fields, st);
 }
 
 hipError_t launch_init(const Model& m, const float* phi0, const float* ux0, const float* uy0,
-                       const float* p0, float* f, float* h, float* pp, float* phiu, hipStream_t st) {
+                       const float* p0, float* copy, hipStream_t st) {
+    const long long P = m.plane;
     dim3 grid((m.nx + 255) / 256, m.ny);
-    hipLaunchKernelGGL(init_kernel, grid, dim3(256), 0, st, m, phi0, ux0, uy0, p0, f, h, pp, phiu);
+    hipLaunchKernelGGL(init_kernel, grid, dim3(256), 0, st, m, phi0, ux0, uy0, p0, copy + kCopyF * P,
+                       copy + kCopyH * P, copy + kCopyP * P, copy + kCopyPhiU * P);
     return hipGetLastError();
 }
 
@@ -610,10 +611,12 @@ static int red_blocks(const Model& m) {
     return (int)b;
 }
 
-hipError_t launch_diag(const Model& m, const float* f, const float* h, const float* pp,
-                       const float* phiu, const float* fields, double* red, hipStream_t st) {
+hipError_t launch_diag(const Model& m, const float* copy, const float* fields, double* red,
+                       hipStream_t st) {
     const int nb = red_blocks(m);
-    hipLaunchKernelGGL(diag_partial_kernel, dim3(nb), dim3(256), 0, st, m, f, h, pp, phiu, fields, red);
+    const long long P = m.plane;
+    hipLaunchKernelGGL(diag_partial_kernel, dim3(nb), dim3(256), 0, st, m, copy + kCopyF * P,
+                       copy + kCopyH * P, copy + kCopyP * P, copy + kCopyPhiU * P, fields, red);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     double* out = red + (size_t)kRedBlocks * kRedSlots;
@@ -621,11 +624,11 @@ hipError_t launch_diag(const Model& m, const float* f, const float* h, const flo
     return hipGetLastError();
 }
 
-hipError_t launch_laplace(const Model& m, const float* h, const float* fields, double* phi64,
+hipError_t launch_laplace(const Model& m, const float* copy, const float* fields, double* phi64,
                           double xc, double yc, double r_in, double r_out, double* red,
                           hipStream_t st) {
     dim3 grid((m.nx + 255) / 256, m.ny);
-    hipLaunchKernelGGL(phi64_kernel, grid, dim3(256), 0, st, m, h, phi64);
+    hipLaunchKernelGGL(phi64_kernel, grid, dim3(256), 0, st, m, copy + kCopyH * m.plane, phi64);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nb = red_blocks(m);

@@ -21,17 +21,23 @@ constexpr int kFPlanes = 8;   // f_1..f_8   -> plane i-1
 constexpr int kHPlanes = 10;  // h_0 hi, h_1..h_8, h_0 lo -> planes 0, 1..8, 9
 constexpr int kH0Lo = 9;
 
-// Workspace layout, in planes of ny*pitch floats (each plane 256-byte aligned):
-//   [0, 8)    f copy A         [8, 16)   f copy B
-//   [16, 26)  h copy A         [26, 36)  h copy B
-//   36, 37    p copy A, B      38, 39    (phi u)_x, (phi u)_y history (updated in place)
-//   [40, 46)  field scratch: phi, rho, ux, uy, p, mu of the current state
-//   [46, 48)  FP64 scratch plane (order parameter in double, Laplace diagnostic)
-// followed by the reduction area (kRedDoubles doubles).
-constexpr int kPlaneFA = 0, kPlaneFB = 8, kPlaneHA = 16, kPlaneHB = 26;
-constexpr int kPlanePA = 36, kPlanePB = 37, kPlanePhiU = 38, kPlaneFields = 40;
-constexpr int kPlaneF64 = 46;
-constexpr int kNumPlanes = 48;
+// One population copy (the state at one time level) holds 21 planes:
+//   0..7    f_1..f_8
+//   8..17   h_0 hi, h_1..h_8, h_0 lo
+//   18      p
+//   19, 20  (phi u)_x, (phi u)_y
+// The workspace holds two copies (a step reads one and writes the other), then an FP64 scratch
+// of ny * xpitch doubles (order parameter in double for the Laplace diagnostic), then the
+// reduction area (kRedDoubles doubles). Between steps the copy that does not hold the state is
+// free: field evaluation (phi, rho, ux, uy, p, mu for reads, diagnostics and the hand-over to the
+// surrogate) writes its six planes there.
+//
+// Element (q, y, x) of a copy sits at q * plane + y * pitch + x. The planes are either
+// interleaved by grid row (pitch = 21 xpitch, plane = xpitch: the 21 values of a row of nodes are
+// neighbours in memory, so a workgroup keeps few DRAM pages open) or separate (pitch = xpitch,
+// plane = ny * xpitch + pad) for grids too large for 32-bit per-lane offsets when interleaved.
+constexpr int kCopyF = 0, kCopyH = 8, kCopyP = 18, kCopyPhiU = 19, kCopyPlanes = 21;
+constexpr int kFieldPlanes = 6;
 constexpr int kRedBlocks = 4096;                 // max partial-sum blocks of a reduction
 constexpr int kRedSlots = 8;                     // doubles per partial
 constexpr size_t kRedDoubles = (size_t)kRedBlocks * kRedSlots + 64;
@@ -41,8 +47,11 @@ constexpr long kDefaultPlanePad = 4160;  // floats; measured +5..10 % at 4096^2,
 
 // Physical and derived model constants in the precision the kernels compute in (FP32).
 struct Model {
-    int nx, ny, pitch;
-    long long plane;       // floats per plane: ny * pitch plus the layout pad
+    int nx, ny;
+    int pitch;             // floats between rows of a copy (row stride)
+    int xpitch;            // floats per row of one plane: nx rounded up to 64
+    long long plane;       // floats between planes of a copy
+    long long copy;        // floats per population copy (21 planes and a pad)
     int variant;           // 0 quasi-incompressible, 1 incompressible
     int pscheme;           // 0 eq.(28) with G0 of eq.(34), 1 simplified G0, 2 eq.(29)
     int fsurf;             // 0 mu grad phi, 1 -phi grad mu

@@ -45,9 +45,10 @@ def test_workspace_size_scales_with_grid(lib):
     cfg, _ = workloads.static_droplet(n=64)
     a = lbpf.workspace_size(cfg)
     b = lbpf.workspace_size(dict(cfg, nx=128, ny=128))
-    # 48 FP32 planes per node (two population copies, histories, field scratch); the layout pad
-    # and the reduction area do not depend on the grid size
-    assert b - a == 48 * 4 * (128 * 128 - 64 * 64)
+    # 44 FP32 planes per node: two population copies of 21 planes (f_1..8, h hi/lo pair and
+    # h_1..8, p, phi u) and the FP64 scratch; the layout pad and the reduction area do not depend
+    # on the grid size
+    assert b - a == 44 * 4 * (128 * 128 - 64 * 64)
 
 
 @pytest.mark.parametrize("bad,why", [
@@ -73,9 +74,19 @@ def test_invalid_parameters_rejected(lib, bad, why):
 
 
 def test_largest_plane_accepted(lib):
-    # 32768 x 32704 nodes (plus the layout pad) stays below 2^30 floats per plane
+    # 32768 x 32704 nodes (plus the layout pad) stays below 2^30 floats per plane; planes of a
+    # grid this large are stored separately (interleaved, a copy would exceed 2^30 floats)
     cfg, _ = workloads.static_droplet(n=16, R=4)
-    assert lbpf.workspace_size(dict(cfg, nx=32768, ny=32704)) > 48 * 4 * 32768 * 32704
+    assert lbpf.workspace_size(dict(cfg, nx=32768, ny=32704)) > 44 * 4 * 32768 * 32704
+
+
+def test_planar_layout_size(lib, monkeypatch):
+    # separate planes carry one layout pad per plane; interleaved copies one per copy
+    cfg, _ = workloads.static_droplet(n=64)
+    inter = lbpf.workspace_size(cfg)
+    monkeypatch.setenv("LBPF_STATE_LAYOUT", "planar")
+    planar = lbpf.workspace_size(cfg)
+    assert planar - inter == 2 * 20 * 4160 * 4
 
 
 def test_status_strings(lib):
