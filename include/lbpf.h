@@ -101,8 +101,11 @@ typedef struct lbpf_diag {
 
 typedef struct lbpf_ctx lbpf_ctx;
 
-/* Bytes of device workspace a simulation with these parameters needs (the populations in two
- * ping-pong copies, pressure history, (phi u) history, field and reduction scratch). */
+/* Bytes of device workspace a simulation with these parameters needs: two ping-pong copies of
+ * the state (f_1..8, h_0 hi/lo and h_1..8, pressure and (phi u) histories; 21 planes each,
+ * interleaved by grid row, or as separate planes for grids above about 7100^2 or when the
+ * environment sets LBPF_STATE_LAYOUT=planar), an FP64 scratch and the reduction area. The layout
+ * must not change between this call and lbpf_create. */
 lbpf_status lbpf_workspace_size(const lbpf_params* params, size_t* bytes);
 
 /* Validate params and bind a handle to a caller-owned device workspace and stream.
@@ -136,9 +139,10 @@ lbpf_status lbpf_laplace_dp(lbpf_ctx* ctx, double xc, double yc, double R, doubl
 
 /* Checkpoint: bytes of the current state (populations, histories, step count). */
 lbpf_status lbpf_state_size(const lbpf_ctx* ctx, size_t* bytes);
-/* Copy the current state into / out of a caller device buffer of lbpf_state_size() bytes.
- * Asynchronous; a save followed by a load on another handle with equal params resumes
- * bit-identically. */
+/* Copy the current state into / out of a caller device buffer of lbpf_state_size() bytes
+ * (a 64-byte header, then the state copy as stored). Asynchronous; a save followed by a load on
+ * another handle with equal params and layout resumes bit-identically; a checkpoint of another
+ * grid or layout is refused with LBPF_E_INVALID. */
 lbpf_status lbpf_save_state(lbpf_ctx* ctx, void* dst_device);
 lbpf_status lbpf_load_state(lbpf_ctx* ctx, const void* src_device);
 
