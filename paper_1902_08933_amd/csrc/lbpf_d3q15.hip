@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -58,17 +59,25 @@ static_assert(2.0 * (double)k3WA + 8.0 * (double)k3WC == 1.0, "odd-part weights 
 constexpr int kFP = 14;    // g_1..g_14 -> planes 0..13
 constexpr int kHP = 16;    // h_0 hi, h_1..h_14, h_0 lo
 constexpr int kH0Lo = 15;
-// workspace planes
-constexpr int kPlFA = 0, kPlFB = 14, kPlHA = 28, kPlHB = 44, kPlPA = 60, kPlPB = 61;
-constexpr int kPlPhiU = 62, kPlFields = 65, kNumFields = 7, kNumPlanes = 72;
+// One population copy (the state at one time level): g_1..14 (planes 0..13), h_0 hi, h_1..14,
+// h_0 lo (14..29), p (30), (phi u)_x,y,z (31..33). The workspace holds two copies (a step reads
+// one and writes the other) and the reduction area; between steps the copy not holding the state
+// is free and field evaluation writes its seven planes there. Element (q, x, y, z) of a copy sits
+// at q * plane + z * slab + y * pitch + x, with the planes interleaved by grid row (plane =
+// pitch3(nx) + 64, pitch = 34 plane) unless the copy would then need per-lane offsets of 2^30
+// floats or more, or the environment sets LBPF_STATE_LAYOUT=planar (separate planes).
+constexpr int kCopyG = 0, kCopyH = 14, kCopyP = 30, kCopyPhiU = 31, kCopyPlanes = 34;
+constexpr int kNumFields = 7;
 constexpr long kPlanePad = 4160;
 constexpr int kRedBlocks = 2048, kRedSlots = 4;
 constexpr size_t kRedDoubles = (size_t)kRedBlocks * kRedSlots + 64;
 
 struct Model3 {
-    int nx, ny, nz, pitch;
-    int slab;              // ny * pitch floats per z plane of the grid
-    long long plane;       // floats per population plane
+    int nx, ny, nz;
+    int pitch;             // floats between rows (y) of a copy
+    int slab;              // ny * pitch: floats between z planes of the grid
+    long long plane;       // floats between planes (q) of a copy
+    long long copy;        // floats per population copy (34 planes and a pad)
     int variant, pscheme, fsurf, visc, bc, clamp;
     float beta4, kappa, eta, gammaM, rhoA, rhoB, drho, inv_nuA, inv_nuB, muA, muB;
     float inv_tau_h, src_coef, fx, fy, fz, grav;
@@ -368,7 +377,8 @@ __global__ __launch_bounds__(TX * TY) void march3d_kernel(Model3 m, const float*
                                                           float* __restrict__ hout,
                                                           const float* __restrict__ pin,
                                                           float* __restrict__ pout,
-                                                          float* __restrict__ phiu,
+                                                          const float* __restrict__ phiu_in,
+                                                          float* __restrict__ phiu_out,
                                                           float* __restrict__ fields, int ntx,
                                                           int nty, int cz) {
     using L = Lds3<TX, TY, PF>;
@@ -497,7 +507,6 @@ __global__ __launch_bounds__(TX * TY) void march3d_kernel(Model3 m, const float*
     const int x = x0 + tx, y = y0 + ty;
     const bool col_active = x < m.nx && y < m.ny;
     // PF: the owned node's g and (phi u) of the next plane are loaded with the halo prefetch
-    // ((phi u) is updated in place, but only by this thread and only at the plane it updates)
     float gn[PF ? kFP : 1], pun[PF ? 3 : 1];
     auto load_own = [&](int zz) {
         if constexpr (PF != 0) {
@@ -505,7 +514,7 @@ __global__ __launch_bounds__(TX * TY) void march3d_kernel(Model3 m, const float*
 #pragma unroll
             for (int q = 0; q < kFP; ++q) gn[q] = *pl(gin, P, q, c);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) pun[a] = *pl(phiu, P, a, c);
+            for (int a = 0; a < 3; ++a) pun[a] = *pl(phiu_in, P, a, c);
         }
     };
     if (PF && col_active) load_own(zs);
@@ -523,7 +532,7 @@ __global__ __launch_bounds__(TX * TY) void march3d_kernel(Model3 m, const float*
 #pragma unroll
                 for (int q = 0; q < kFP; ++q) g[q] = *pl(gin, P, q, cell);
 #pragma unroll
-                for (int a = 0; a < 3; ++a) pu[a] = *pl(phiu, P, a, cell);
+                for (int a = 0; a < 3; ++a) pu[a] = *pl(phiu_in, P, a, cell);
             }
         }
         if (PF) {
@@ -551,7 +560,7 @@ __global__ __launch_bounds__(TX * TY) void march3d_kernel(Model3 m, const float*
         if (col_active) {
             const Stencil3 st = gather3(S, pslot(z - 1), pslot(z), pslot(z + 1), mslot(z - 1), mslot(z),
                                         mslot(z + 1), qslot(z - 1), qslot(z), qslot(z + 1), tx, ty);
-            cell3<COLLIDE, BC>(m, x, y, z, cell, g, h, pu, st, gout, hout, pout, phiu, fields);
+            cell3<COLLIDE, BC>(m, x, y, z, cell, g, h, pu, st, gout, hout, pout, phiu_out, fields);
         }
     }
 }
@@ -757,8 +766,8 @@ constexpr int kDefaultShape3 = 0;
 
 template <int TX, int TY, bool C, int BC, int PF>
 static hipError_t launch_t(const Model3& m, int cz, const float* gin, float* gout, const float* hin,
-                           float* hout, const float* pin, float* pout, float* phiu, float* fields,
-                           hipStream_t st) {
+                           float* hout, const float* pin, float* pout, const float* phiu_in,
+                           float* phiu_out, float* fields, hipStream_t st) {
     const int ntx = (m.nx + TX - 1) / TX, nty = (m.ny + TY - 1) / TY, nch = (m.nz + cz - 1) / cz;
     const long long nblk = (long long)ntx * nty * nch;
     if (nblk > 0x7fffffff) return hipErrorInvalidConfiguration;
@@ -771,19 +780,19 @@ static hipError_t launch_t(const Model3& m, int cz, const float* gin, float* gou
         attr_set = true;
     }
     hipLaunchKernelGGL((march3d_kernel<TX, TY, C, BC, PF>), dim3((unsigned)nblk), dim3(TX * TY), lds, st, m,
-                       gin, gout, hin, hout, pin, pout, phiu, fields, ntx, nty, cz);
+                       gin, gout, hin, hout, pin, pout, phiu_in, phiu_out, fields, ntx, nty, cz);
     return hipGetLastError();
 }
 
 template <bool C, int BC>
 static hipError_t launch_shape(int s, const Model3& m, const float* gin, float* gout, const float* hin,
-                               float* hout, const float* pin, float* pout, float* phiu, float* fields,
-                               hipStream_t st) {
+                               float* hout, const float* pin, float* pout, const float* phiu_in,
+                               float* phiu_out, float* fields, hipStream_t st) {
     const Shape3 sh = kShapes3[s];
 #define LBPF3D_CASE(TX, TY)                                                                         \
     if (sh.tx == TX && sh.ty == TY)                                                                 \
-        return sh.pf ? launch_t<TX, TY, C, BC, 1>(m, sh.cz, gin, gout, hin, hout, pin, pout, phiu, fields, st) \
-                     : launch_t<TX, TY, C, BC, 0>(m, sh.cz, gin, gout, hin, hout, pin, pout, phiu, fields, st);
+        return sh.pf ? launch_t<TX, TY, C, BC, 1>(m, sh.cz, gin, gout, hin, hout, pin, pout, phiu_in, phiu_out, fields, st) \
+                     : launch_t<TX, TY, C, BC, 0>(m, sh.cz, gin, gout, hin, hout, pin, pout, phiu_in, phiu_out, fields, st);
     LBPF3D_CASE(32, 8)
     LBPF3D_CASE(64, 4)
     LBPF3D_CASE(64, 8)
@@ -847,27 +856,41 @@ static std::string validate3(const lbpf3d_params* p) {
     return "";
 }
 
-static size_t plane_floats3(const lbpf3d_params* p) {
-    return (size_t)p->nz * p->ny * pitch3(p->nx) + kPlanePad;
+// Interleaved by row, consecutive planes of a row are pitch3(nx) + 64 floats apart: a row of a
+// 256-wide grid is 1 KiB, and planes a power of two apart measured 14.6 against 17.1 GLUPS at
+// 256^3.
+static long long row_plane3(int nx) { return pitch3(nx) + 64; }
+static bool interleaved3(const lbpf3d_params* p) {
+    const char* e = getenv("LBPF_STATE_LAYOUT");
+    if (e && strcmp(e, "planar") == 0) return false;
+    return (long long)p->nz * p->ny * kCopyPlanes * row_plane3(p->nx) < (1LL << 30);
+}
+static size_t copy_floats3(const lbpf3d_params* p) {
+    const size_t rows = (size_t)p->nz * p->ny;
+    return interleaved3(p) ? kCopyPlanes * rows * row_plane3(p->nx) + kPlanePad
+                           : kCopyPlanes * (rows * pitch3(p->nx) + kPlanePad);
 }
 
-static float* plane3(lbpf3d* c, int k) { return c->ws + (size_t)k * c->m.plane; }
+static float* copy3(lbpf3d* c, int k) { return c->ws + (size_t)k * c->m.copy; }
 
+// one launch of the march from copy src: a step into the other copy (C), or the field evaluation
+// of copy src into the other copy's first seven planes (!C)
 template <bool C>
 static lbpf_status run3(lbpf3d* c, int src) {
     const Model3& m = c->m;
-    const int dst = 1 - src;
-    const float* gin = plane3(c, src ? kPlFB : kPlFA);
-    float* gout = plane3(c, dst ? kPlFB : kPlFA);
-    const float* hin = plane3(c, src ? kPlHB : kPlHA);
-    float* hout = plane3(c, dst ? kPlHB : kPlHA);
-    const float* pin = plane3(c, src ? kPlPB : kPlPA);
-    float* pout = plane3(c, dst ? kPlPB : kPlPA);
-    float* phiu = plane3(c, kPlPhiU);
-    float* fields = plane3(c, kPlFields);
+    const long long P = m.plane;
+    const float* in = copy3(c, src);
+    float* out = copy3(c, 1 - src);
+    float* gout = C ? out + kCopyG * P : nullptr;
+    float* hout = C ? out + kCopyH * P : nullptr;
+    float* pout = C ? out + kCopyP * P : nullptr;
+    float* puout = C ? out + kCopyPhiU * P : nullptr;
+    float* fields = C ? nullptr : out;
     hipError_t e = (m.bc == 0)
-        ? launch_shape<C, 0>(c->shape, m, gin, gout, hin, hout, pin, pout, phiu, fields, c->stream)
-        : launch_shape<C, 1>(c->shape, m, gin, gout, hin, hout, pin, pout, phiu, fields, c->stream);
+        ? launch_shape<C, 0>(c->shape, m, in + kCopyG * P, gout, in + kCopyH * P, hout, in + kCopyP * P,
+                             pout, in + kCopyPhiU * P, puout, fields, c->stream)
+        : launch_shape<C, 1>(c->shape, m, in + kCopyG * P, gout, in + kCopyH * P, hout, in + kCopyP * P,
+                             pout, in + kCopyPhiU * P, puout, fields, c->stream);
     return hip3(c, e, "march3d_kernel");
 }
 
@@ -877,7 +900,7 @@ lbpf_status lbpf3d_workspace_size(const lbpf3d_params* params, size_t* bytes) {
     if (!bytes) return fail3(nullptr, LBPF_E_INVALID, "bytes is NULL");
     const std::string v = validate3(params);
     if (!v.empty()) return fail3(nullptr, LBPF_E_INVALID, v);
-    const size_t fl = plane_floats3(params) * kNumPlanes;
+    const size_t fl = 2 * copy_floats3(params);
     *bytes = (fl * sizeof(float) + 255) / 256 * 256 + kRedDoubles * sizeof(double);
     return LBPF_OK;
 }
@@ -897,15 +920,23 @@ lbpf_status lbpf3d_create(const lbpf3d_params* params, void* workspace, size_t w
     if (!c) return fail3(nullptr, LBPF_E_NOMEM, "host allocation failed");
     c->prm = *params;
     c->ws = static_cast<float*>(workspace);
-    const size_t fl = plane_floats3(params) * kNumPlanes;
+    const size_t fl = 2 * copy_floats3(params);
     c->red = reinterpret_cast<double*>(reinterpret_cast<char*>(workspace) + (fl * sizeof(float) + 255) / 256 * 256);
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->shape = kDefaultShape3;
     Model3& m = c->m;
     const lbpf3d_params& p = *params;
-    m.nx = p.nx; m.ny = p.ny; m.nz = p.nz; m.pitch = pitch3(p.nx);
+    m.nx = p.nx; m.ny = p.ny; m.nz = p.nz;
+    const int xp = pitch3(p.nx);
+    if (interleaved3(params)) {
+        m.plane = row_plane3(p.nx);
+        m.pitch = (int)(kCopyPlanes * m.plane);
+    } else {
+        m.pitch = xp;
+        m.plane = (long long)p.nz * p.ny * xp + kPlanePad;
+    }
     m.slab = p.ny * m.pitch;
-    m.plane = (long long)plane_floats3(params);
+    m.copy = (long long)copy_floats3(params);
     m.variant = p.variant; m.pscheme = p.pscheme; m.fsurf = p.fsurf; m.visc = p.visc;
     m.bc = p.bc; m.clamp = p.clamp_props ? 1 : 0;
     // eqs. (6)-(7): kappa / beta = W^2 / 8, kappa beta = 18 sigma^2
@@ -934,10 +965,12 @@ lbpf_status lbpf3d_init(lbpf3d* c, const float* phi, const float* ux, const floa
     dim3 grid((m.nx + 255) / 256, m.ny, m.nz);
     if (m.bc == 0)
         hipLaunchKernelGGL(init3d_kernel<0>, grid, dim3(256), 0, c->stream, m, phi, ux, uy, uz, p,
-                           plane3(c, kPlFA), plane3(c, kPlHA), plane3(c, kPlPA), plane3(c, kPlPhiU));
+                           copy3(c, 0) + kCopyG * m.plane, copy3(c, 0) + kCopyH * m.plane,
+                           copy3(c, 0) + kCopyP * m.plane, copy3(c, 0) + kCopyPhiU * m.plane);
     else
         hipLaunchKernelGGL(init3d_kernel<1>, grid, dim3(256), 0, c->stream, m, phi, ux, uy, uz, p,
-                           plane3(c, kPlFA), plane3(c, kPlHA), plane3(c, kPlPA), plane3(c, kPlPhiU));
+                           copy3(c, 0) + kCopyG * m.plane, copy3(c, 0) + kCopyH * m.plane,
+                           copy3(c, 0) + kCopyP * m.plane, copy3(c, 0) + kCopyPhiU * m.plane);
     lbpf_status s = hip3(c, hipGetLastError(), "init3d_kernel");
     if (s != LBPF_OK) return s;
     c->cur = 0;
@@ -968,7 +1001,7 @@ lbpf_status lbpf3d_read(lbpf3d* c, int32_t field, float* dst) {
     if (s != LBPF_OK) return s;
     const Model3& m = c->m;
     hipLaunchKernelGGL(compact3d_kernel, dim3((m.nx + 255) / 256, m.ny, m.nz), dim3(256), 0, c->stream, m,
-                       plane3(c, kPlFields + field), dst);
+                       copy3(c, 1 - c->cur) + field * m.plane, dst);
     return hip3(c, hipGetLastError(), "compact3d_kernel");
 }
 
@@ -983,8 +1016,9 @@ lbpf_status lbpf3d_diagnostics(lbpf3d* c, lbpf_diag* out) {
     const int nblk = (int)std::min<long long>(kRedBlocks, (n + 255) / 256);
     const int cur = c->cur;
     hipLaunchKernelGGL(diag3d_partial_kernel, dim3(nblk), dim3(256), 0, c->stream, m,
-                       plane3(c, cur ? kPlFB : kPlFA), plane3(c, cur ? kPlHB : kPlHA),
-                       plane3(c, cur ? kPlPB : kPlPA), plane3(c, kPlPhiU), plane3(c, kPlFields), c->red);
+                       copy3(c, cur) + kCopyG * m.plane, copy3(c, cur) + kCopyH * m.plane,
+                       copy3(c, cur) + kCopyP * m.plane, copy3(c, cur) + kCopyPhiU * m.plane,
+                       copy3(c, 1 - cur), c->red);
     if ((s = hip3(c, hipGetLastError(), "diag3d_partial_kernel")) != LBPF_OK) return s;
     double* fin = c->red + (size_t)kRedBlocks * kRedSlots;
     hipLaunchKernelGGL(reduce3d_final_kernel, dim3(1), dim3(256), 0, c->stream, c->red, nblk, 1u << 2, fin);
@@ -1011,14 +1045,14 @@ lbpf_status lbpf3d_laplace_dp(lbpf3d* c, double xc, double yc, double zc, double
     const Model3& m = c->m;
     const long long n = (long long)m.nx * m.ny * m.nz;
     const int nblk = (int)std::min<long long>(kRedBlocks, (n + 255) / 256);
-    const float* h = plane3(c, c->cur ? kPlHB : kPlHA);
+    const float* h = copy3(c, c->cur) + kCopyH * c->m.plane;
     const double r_in = 0.5 * R, r_out = R + 3.0 * c->prm.W;
     if (m.bc == 0)
         hipLaunchKernelGGL(laplace3d_partial_kernel<0>, dim3(nblk), dim3(256), 0, c->stream, m, h,
-                           plane3(c, kPlFields), xc, yc, zc, r_in, r_out, c->red);
+                           copy3(c, 1 - c->cur), xc, yc, zc, r_in, r_out, c->red);
     else
         hipLaunchKernelGGL(laplace3d_partial_kernel<1>, dim3(nblk), dim3(256), 0, c->stream, m, h,
-                           plane3(c, kPlFields), xc, yc, zc, r_in, r_out, c->red);
+                           copy3(c, 1 - c->cur), xc, yc, zc, r_in, r_out, c->red);
     if ((s = hip3(c, hipGetLastError(), "laplace3d_partial_kernel")) != LBPF_OK) return s;
     double* fin = c->red + (size_t)kRedBlocks * kRedSlots;
     hipLaunchKernelGGL(reduce3d_final_kernel, dim3(1), dim3(256), 0, c->stream, c->red, nblk, 0u, fin);
