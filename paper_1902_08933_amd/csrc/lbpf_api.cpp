@@ -577,6 +577,20 @@ static lbpf_status batch_setup(lbpf_batch* b) {
     }
     if (items.size() > b->max_items) return bfail(b, LBPF_E_NOMEM, "work list overflow");
     b->nitems = (int)items.size();
+    {
+        // Workgroup g of the persistent grid runs on XCD g % 8 and takes list positions g,
+        // g + grid, ...; with a grid that is a multiple of 8 (or covers the list), position p is
+        // processed on XCD p % 8. Give each XCD a contiguous band of chunks so that neighbouring
+        // strips, which re-read each other's ghost columns, share an L2 (1024^2 in one instance:
+        // 23 -> 28 GLUPS).
+        std::vector<BatchItem> perm(items.size());
+        const int n = b->nitems, per = n / 8, rem = n % 8;
+        for (int p = 0; p < n; ++p) {
+            const int xcd = p % 8, loc = p / 8;
+            perm[p] = items[xcd * per + std::min(xcd, rem) + loc];
+        }
+        items.swap(perm);
+    }
     int dev = 0, cus = 0;
     e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
