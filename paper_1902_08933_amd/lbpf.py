@@ -102,6 +102,11 @@ def library(path=LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1902_08933_amd.build`"
                            " (or __graft_entry__.build())")
+    # PyTorch ships its own HIP runtime and asks for it by an unversioned name. Loaded first,
+    # that runtime also satisfies this library's libamdhip64.so.7; loaded after this library,
+    # it would be a second HIP (and HSA) runtime in the process, and this library's launches
+    # then find no device. So torch is imported before the library is opened.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -300,3 +300,60 @@ def test_state_layouts_bit_identical(walls, monkeypatch):
     buf[:ckpt.numel()] = ckpt
     with pytest.raises(lbpf.LbpfError):
         sims["planar"].load_state(buf)  # the header names the other layout
+
+
+def test_large_grid_separate_planes_against_oracle_crop():
+    # 8192 x 6400 nodes: a population copy interleaved by row would need per-lane offsets of
+    # 2^30 floats or more, so this grid keeps separate planes (the workspace size says which);
+    # two steps from a seeded spinodal field, then the inner 20^2 nodes of a 40^2 periodic crop
+    # around the grid corner against the oracle run on that crop (the fields read after two
+    # steps depend on the initial field within a radius of 9 nodes)
+    from paper_1902_08933_amd import lbpf
+    nx, ny = 8192, 6400
+    cfg, _ = W.spinodal(n=64, variant="qim", seed=3)
+    cfg = dict(cfg, nx=nx, ny=ny)
+    xp, pad, red = nx, 4160, (4096 * 8 + 64) * 8
+    assert lbpf.workspace_size(cfg) == (2 * 21 * (ny * xp + pad) + 2 * ny * xp) * 4 + red
+    phi = W.spinodal_phi(nx, ny, 0.5, 0.05, 3).astype(np.float32)
+    print(f"large grid {nx}x{ny}, separate planes", flush=True)
+    sim = gpu_sim(cfg, phi)
+    sim.step(2)
+    ix, iy = np.arange(-20, 20) % nx, np.arange(-20, 20) % ny
+    crop = phi[np.ix_(iy, ix)].astype(np.float64)
+    o = oracle.Oracle(dict(cfg, nx=40, ny=40)).init(crop).step(2)
+    inner = np.arange(10, 30)
+    sel = np.ix_(iy[inner], ix[inner])
+    for f, tol in (("phi", TOL_PHI), ("ux", TOL_U), ("uy", TOL_U), ("p", TOL_P)):
+        g = sim.read(f)[torch_index(sel)].double().cpu().numpy()
+        e = rel(g, o.read(f)[np.ix_(inner, inner)])
+        print(f"  {f} {e:.2e}", flush=True)
+        assert e <= tol, f
+    d = sim.diagnostics()
+    assert d["nonfinite"] == 0
+
+
+def torch_index(sel):
+    import torch
+    return tuple(torch.from_numpy(np.asarray(s)).cuda() for s in sel)
+
+
+def test_library_opened_before_torch_shares_its_hip_runtime():
+    # a fresh interpreter that opens the library (workspace_size) before importing torch itself:
+    # the binding imports torch first, so one HIP runtime serves both and the step runs
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import numpy as np\n"
+        "from paper_1902_08933_amd import lbpf, workloads as W\n"
+        "cfg, phi = W.static_droplet(n=32, R=8.0)\n"
+        "lbpf.workspace_size(cfg)\n"
+        "import torch\n"
+        "sim = lbpf.Simulation(cfg).init(torch.from_numpy(phi.astype(np.float32)).cuda())\n"
+        "sim.step(3)\n"
+        "print('steps', sim.diagnostics()['step'])\n"
+    )
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "steps 3" in r.stdout
