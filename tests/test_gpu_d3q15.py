@@ -195,3 +195,33 @@ def test_state_layouts_bit_identical(walls, monkeypatch):
     for k in out["interleaved"]:
         assert np.array_equal(out["interleaved"][k], out["planar"][k]), k
     assert diag["interleaved"] == diag["planar"]
+
+
+def test_large_grid_separate_planes_against_oracle_crop():
+    # 320^3 nodes: a population copy interleaved by row would need per-lane offsets of 2^30
+    # floats or more, so this grid keeps separate planes (the workspace size says which); two
+    # steps, then the inner 20^3 nodes of a 40^3 periodic crop around the grid corner against
+    # the oracle run on that crop, as in the benchmark-size test
+    from paper_1902_08933_amd import lbpf
+    import ctypes
+    n = 320
+    cfg, phi = W.spinodal3d(n=n, seed=4, amplitude=0.05)
+    nodes, pad = n * n * n, 4160
+    need = ctypes.c_size_t()
+    p = lbpf.make_params3d(cfg)
+    assert lbpf.library().lbpf3d_workspace_size(ctypes.byref(p), ctypes.byref(need)) == 0
+    fl = 2 * 34 * (nodes + pad)
+    assert need.value == (fl * 4 + 255) // 256 * 256 + (2048 * 4 + 64) * 8
+    print(f"d3q15 large grid {n}^3, separate planes", flush=True)
+    sim = gpu_sim(cfg, phi)
+    sim.step(2)
+    idx = np.arange(-20, 20) % n
+    crop = phi[np.ix_(idx, idx, idx)].astype(np.float32).astype(np.float64)
+    o = O.Oracle3D(dict(cfg, nx=40, ny=40, nz=40)).init(crop)
+    o.step(2)
+    inner = np.arange(10, 30)
+    for f, tol in (("phi", TOL_PHI), ("ux", TOL_U), ("uz", TOL_U), ("p", TOL_P)):
+        g = sim.read(f)[np.ix_(idx[inner], idx[inner], idx[inner])].double().cpu().numpy()
+        e = rel(g, o.read(f)[np.ix_(inner, inner, inner)])
+        print(f"  {f} {e:.2e}", flush=True)
+        assert e <= tol, f
