@@ -119,7 +119,8 @@ def batch_bench(steps, count=256, seed=0):
     flags, _ = b.status()     # freezes the instances that went unstable
     b.autotune(trial_steps=8)  # strip shape for the active instances
     active = sum(c["nx"] * c["ny"] for c, f in zip(b.cfgs, flags) if not f)
-    out = {"instances": count, "frozen": int(sum(flags)), "active_nodes": active,
+    total = sum(c["nx"] * c["ny"] for c in b.cfgs)
+    out = {"instances": count, "frozen": int(sum(flags)), "active_nodes": active, "total_nodes": total,
            "strip": list(lbpf.tile_shapes()[b.tile])}
     for name, fn in (("graph_persistent", b.step), ("launch_per_instance", b.step_each)):
         fn(8)
@@ -130,7 +131,11 @@ def batch_bench(steps, count=256, seed=0):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
-        out[name] = {"ms_per_step": round(ms, 4), "MLUPS": round(active / (ms * 1e-3) / 1e6, 1)}
+        # MLUPS counts the active instances' nodes; the bandwidth counts every node, since a frozen
+        # instance's chunk is copied through (168 B per node, as an update moves)
+        gbs = BYTES_PER_CELL * total / (ms * 1e-3) / 1e9
+        out[name] = {"ms_per_step": round(ms, 4), "MLUPS": round(active / (ms * 1e-3) / 1e6, 1),
+                     "algorithmic_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
     out["speedup"] = round(out["launch_per_instance"]["ms_per_step"] / out["graph_persistent"]["ms_per_step"], 2)
     return out
 

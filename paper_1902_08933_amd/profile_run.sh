@@ -72,6 +72,40 @@ if [ "$W" = "d3q15_256" ]; then
         --out "$PROF/fused_step3d_d3q15_256_pmc.txt"
     exit $?
 fi
+if [ "$W" = "batch256" ]; then
+    # batched persistent step over the 256 seeded instances (frozen ones included: their chunks
+    # are copied through, 168 B per node like an update): autotuned strip shape, kernel trace,
+    # then HBM traffic (FETCH_SIZE, WRITE_SIZE, scaled by the same counters on the copy probe)
+    OUT=$RAW/prof_batch256
+    PROF=${PROFILE_OUT:-profiles}
+    mkdir -p "$OUT" "$PROF"
+    export TMPDIR=/tmp
+    CELLS=$(python3 -c "from paper_1902_08933_amd import workloads as W; print(sum(c['nx'] * c['ny'] for c, _ in W.batch_instances(256, seed=0)))") || exit 1
+    TILE=$(timeout -k 10 180 python3 -m paper_1902_08933_amd.profile_step --workload batch256 --autotune | tail -1) || exit 1
+    echo "profile: autotuned strip shape $TILE, $CELLS nodes"
+    STEP="python3 -m paper_1902_08933_amd.profile_step --workload batch256 --tile $TILE"
+    PROBE="python3 -m paper_1902_08933_amd.profile_step --copy-mib 1024 --steps 2 --probe-blocks 4096"
+    echo "profile: kernel trace batch256" && \
+    timeout -k 10 180 rocprofv3 --kernel-trace --stats -d "$OUT/trace" -o run -- $STEP --steps 40 --warmup 8 > "$OUT/trace.log" 2>&1 && \
+    echo "profile: FETCH_SIZE batch256" && \
+    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d "$OUT/fetch" -o run -- $STEP --steps 5 --warmup 1 > "$OUT/fetch.log" 2>&1 && \
+    echo "profile: WRITE_SIZE batch256" && \
+    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d "$OUT/write" -o run -- $STEP --steps 5 --warmup 1 > "$OUT/write.log" 2>&1 && \
+    echo "profile: probe FETCH_SIZE" && \
+    timeout -s KILL 90 rocprofv3 --pmc FETCH_SIZE -d "$OUT/cfetch" -o run -- $PROBE > "$OUT/cfetch.log" 2>&1 && \
+    echo "profile: probe WRITE_SIZE" && \
+    timeout -s KILL 90 rocprofv3 --pmc WRITE_SIZE -d "$OUT/cwrite" -o run -- $PROBE > "$OUT/cwrite.log" 2>&1 && \
+    python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --cells $CELLS \
+        --kernel batch_kernel --alg-bytes-per-cell 168 --sources step \
+        --command "bash paper_1902_08933_amd/profile_run.sh batch256  (trace: rocprofv3 --kernel-trace --stats -- $STEP --steps 40 --warmup 8)" \
+        --out "$PROF/batch_step_batch256_trace.txt" && \
+    python3 -m paper_1902_08933_amd.rocprof_summary --fetch "$OUT/fetch/run_results.db" --write "$OUT/write/run_results.db" \
+        --calib-fetch "$OUT/cfetch/run_results.db" --calib-write "$OUT/cwrite/run_results.db" --calib-bytes 1073741824 \
+        --cells $CELLS --kernel batch_kernel --alg-bytes-per-cell 168 --sources step \
+        --command "bash paper_1902_08933_amd/profile_run.sh batch256  (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE -- $STEP --steps 5 --warmup 1; calibration: same counters on $PROBE)" \
+        --out "$PROF/batch_step_batch256_pmc.txt"
+    exit $?
+fi
 if [ "$W" = "unet1024" ]; then
     # surrogate forward pass at 1024^2: kernel trace of 1 + 10 forwards (214 GFLOP each)
     OUT=$RAW/prof_unet1024

@@ -4,6 +4,7 @@ python -m paper_1902_08933_amd.profile_step --workload spinodal4096 --steps 20
 python -m paper_1902_08933_amd.profile_step --workload spinodal1024 --sweep
 python -m paper_1902_08933_amd.profile_step --workload r4_1024   (Remark 4 scheme, single phase)
 python -m paper_1902_08933_amd.profile_step --workload d3q15_256 --sweep   (D3Q15 two-phase step)
+python -m paper_1902_08933_amd.profile_step --workload batch256 --steps 40   (batched persistent step)
 python -m paper_1902_08933_amd.profile_step --copy-mib 2048 --steps 10   (bandwidth probe:
     copy / read / write of a known byte count, the reference for the HBM roofline and for
     scaling the FETCH_SIZE / WRITE_SIZE counters)
@@ -69,6 +70,40 @@ def run_d3q15(torch, n, steps, warmup, shape=None, sweep=False):
     return out
 
 
+def make_batch(torch, count=256, seed=0, tile=None):
+    """the batched workload of the benchmark: seeded instances, 16 steps (at strip shape `tile`
+    when given, so that a profiled run launches one kernel only), unstable ones frozen; returns
+    the batch, its active node count and its total node count"""
+    import numpy as np
+    insts = workloads.batch_instances(count, seed=seed)
+    b = lbpf.Batch([c for c, _ in insts])
+    if tile is not None:
+        b.set_tile(tile)
+    for k, (_, phi) in enumerate(insts):
+        b.init(k, torch.from_numpy(np.ascontiguousarray(phi, dtype=np.float32)).cuda())
+    b.step(16)
+    flags, _ = b.status()
+    active = sum(c["nx"] * c["ny"] for c, f in zip(b.cfgs, flags) if not f)
+    total = sum(c["nx"] * c["ny"] for c in b.cfgs)
+    return b, active, total
+
+
+def run_batch(torch, steps, warmup, tile=None):
+    """graph-replayed persistent batched step: ms per step at the given (or autotuned) shape"""
+    b, active, total = make_batch(torch, tile=tile)
+    if tile is None:
+        tile, _ = b.autotune(trial_steps=8)
+    b.set_tile(tile)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    return tile, e0.elapsed_time(e1) / steps, active, total
+
+
 def run_steps(torch, cfg, phi, steps, warmup, tile):
     sim = lbpf.Simulation(cfg)
     if tile is not None:
@@ -129,6 +164,16 @@ def main():
             print(f"{a.workload} shape {s} {shapes[s]}: {ms:.4f} ms/step, "
                   f"{n ** 3 / (ms * 1e-3) / 1e6:.0f} MLUPS, {272 * n ** 3 / (ms * 1e-3) / 1e9:.0f} GB/s",
                   flush=True)
+        return 0
+    if a.workload == "batch256":
+        if a.autotune:
+            b, _, _ = make_batch(torch)
+            print(b.autotune(trial_steps=8)[0], flush=True)
+            return 0
+        tile, ms, active, total = run_batch(torch, a.steps, a.warmup, a.tile)
+        print(f"batch256 tile {tile} {lbpf.tile_shapes()[tile]}: {ms:.4f} ms/step, active {active} of "
+              f"{total} nodes, {active / (ms * 1e-3) / 1e6:.0f} MLUPS, "
+              f"{BYTES_PER_CELL * total / (ms * 1e-3) / 1e9:.0f} GB/s", flush=True)
         return 0
     single = re.fullmatch(r"(sp|r4_)(\d+)", a.workload)  # "spinodal<N>" is the two-phase step
     if single:
