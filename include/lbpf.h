@@ -210,11 +210,12 @@ lbpf_status lbpf_batch_init(lbpf_batch* b, int32_t idx, const float* phi, const 
  * instance must be initialized. Asynchronous. */
 lbpf_status lbpf_batch_step(lbpf_batch* b, int64_t nsteps);
 /* Reference path: the same steps with one single-simulation launch per instance per step (a
- * frozen instance's state is copied instead), for comparison with lbpf_batch_step. */
+ * frozen instance is skipped), for comparison with lbpf_batch_step. */
 lbpf_status lbpf_batch_step_each(lbpf_batch* b, int64_t nsteps);
 /* Per-instance FP64 diagnostics (flags[k] = 1 for a frozen instance). An instance whose state
- * holds a non-finite value is frozen: later steps hold its state fixed while the others go on.
- * flags (n int32) and diags (n lbpf_diag) may be NULL. Synchronizes the stream. */
+ * holds a non-finite value is frozen: it leaves the work list (rebuilt here), later steps leave
+ * its state and step count as they are while the others go on, and lbpf_batch_init brings it
+ * back. flags (n int32) and diags (n lbpf_diag) may be NULL. Synchronizes the stream. */
 lbpf_status lbpf_batch_status(lbpf_batch* b, int32_t* flags, lbpf_diag* diags);
 lbpf_ctx* lbpf_batch_instance(lbpf_batch* b, int32_t idx);
 int32_t lbpf_batch_count(const lbpf_batch* b);

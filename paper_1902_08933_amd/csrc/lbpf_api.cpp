@@ -571,8 +571,7 @@ static lbpf_status batch_setup(lbpf_batch* b) {
         hi[k].ws = b->inst[k]->ws;
         hi[k].nsx = (m.nx + tx - 1) / tx;
         hi[k].nsy = (m.ny + ch - 1) / ch;
-        hi[k].frozen = b->frozen[k];
-        hi[k].pad = 0;
+        if (b->frozen[k]) continue;  // held fixed: no work, its state stays in its copy
         for (int c = 0; c < hi[k].nsx * hi[k].nsy; ++c) items.push_back(BatchItem{k, c});
     }
     if (items.size() > b->max_items) return bfail(b, LBPF_E_NOMEM, "work list overflow");
@@ -598,7 +597,8 @@ static lbpf_status batch_setup(lbpf_batch* b) {
     b->grid = std::max(1, std::min(b->nitems, cus * per));
     e = hipStreamSynchronize(b->stream);
     if (e == hipSuccess) e = hipMemcpy(b->d_insts, hi.data(), sizeof(BatchInst) * b->n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !items.empty())  // every instance frozen: an empty list
+        e = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "work list upload: %s", hipGetErrorString(e));
     destroy_graphs(b);
     for (int start = 0; start < 2; ++start) {
@@ -709,13 +709,9 @@ lbpf_status lbpf_batch_init(lbpf_batch* b, int32_t idx, const float* phi, const 
     if (idx < 0 || idx >= b->n) return bfail(b, LBPF_E_INVALID, "instance %d out of range", idx);
     lbpf_status s = init_copy(b->inst[idx], b->parity, phi, ux, uy, p);
     if (s != LBPF_OK) return bfail(b, s, "instance %d: %s", idx, b->inst[idx]->err.c_str());
-    if (b->frozen[idx]) {
+    if (b->frozen[idx]) {  // back in the work list, in step with the batch's parity
         b->frozen[idx] = 0;
-        const int zero = 0;
-        hipError_t e = hipMemcpyAsync((char*)b->d_insts + sizeof(BatchInst) * idx + offsetof(BatchInst, frozen),
-                                      &zero, sizeof(int), hipMemcpyHostToDevice, b->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-        if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "unfreeze: %s", hipGetErrorString(e));
+        return batch_setup(b);
     }
     return LBPF_OK;
 }
@@ -728,12 +724,14 @@ static lbpf_status batch_check(lbpf_batch* b) {
     return LBPF_OK;
 }
 
+// frozen instances keep their copy and step count
 static void batch_advance(lbpf_batch* b, int64_t nsteps) {
     b->parity = (int)((b->parity + nsteps) & 1);
     b->step += nsteps;
     for (int k = 0; k < b->n; ++k) {
+        if (b->frozen[k]) continue;
         b->inst[k]->cur = b->parity;
-        if (!b->frozen[k]) b->inst[k]->step += nsteps;
+        b->inst[k]->step += nsteps;
     }
 }
 
@@ -761,14 +759,7 @@ lbpf_status lbpf_batch_step_each(lbpf_batch* b, int64_t nsteps) {
     for (int64_t t = 0; t < nsteps; ++t) {
         for (int k = 0; k < b->n; ++k) {
             lbpf_ctx* c = b->inst[k];
-            if (b->frozen[k]) {  // held fixed: copy the state into the other population copy
-                const int a = c->cur, o = 1 - a;
-                hipError_t e = hipMemcpyAsync(copy_of(c, o), copy_of(c, a), (size_t)c->m.copy * sizeof(float),
-                                              hipMemcpyDeviceToDevice, b->stream);
-                if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "frozen copy: %s", hipGetErrorString(e));
-                c->cur = o;
-                continue;
-            }
+            if (b->frozen[k]) continue;  // held fixed in its copy
             const int tile = c->tile;
             c->tile = b->tile;
             lbpf_status s = lbpf_step(c, 1);
@@ -796,13 +787,7 @@ lbpf_status lbpf_batch_status(lbpf_batch* b, int32_t* flags, lbpf_diag* diags) {
         if (diags) diags[k] = d;
         if (flags) flags[k] = b->frozen[k];
     }
-    if (changed) {
-        for (int k = 0; k < b->n; ++k) {
-            hipError_t e = hipMemcpy((char*)b->d_insts + sizeof(BatchInst) * k + offsetof(BatchInst, frozen),
-                                     &b->frozen[k], sizeof(int), hipMemcpyHostToDevice);
-            if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "freeze flags: %s", hipGetErrorString(e));
-        }
-    }
+    if (changed) return batch_setup(b);  // work list without the newly frozen instances
     return LBPF_OK;
 }
 

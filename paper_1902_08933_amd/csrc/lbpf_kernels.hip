@@ -496,17 +496,8 @@ static hipError_t launch_fused(int tile, const Model& m, const float* fin, float
 // items of all simulations of a batch, with a stride of the grid size; each item is one
 // march_chunk of that instance with its own model constants, so each instance evolves
 // bit-identically to a single-simulation launch. `parity` selects the population copy read.
-// A frozen instance's chunk is copied through unchanged so that all instances share parity.
+// Frozen instances have no items: their state stays in the copy it was in.
 // ---------------------------------------------------------------------------------------------
-template <int TX, int NT>
-__device__ __forceinline__ void copy_chunk(const Model& m, const float* src, float* dst, int x0,
-                                           int ys, int ch) {
-    const int w = min(TX, m.nx - x0), h = min(ch, m.ny - ys);
-    for (int i = threadIdx.x; i < w * h; i += NT) {
-        const long long c = (long long)(ys + i / w) * m.pitch + x0 + i % w;
-        for (int q = 0; q < kCopyPlanes; ++q) dst[q * m.plane + c] = src[q * m.plane + c];
-    }
-}
 
 template <int TX, int NT, int CH, bool PF>
 __global__ __launch_bounds__(NT) void batch_kernel(const BatchInst* __restrict__ insts,
@@ -521,9 +512,7 @@ __global__ __launch_bounds__(NT) void batch_kernel(const BatchInst* __restrict__
         const float* in = I.ws + parity * m.copy;
         float* out = I.ws + (1 - parity) * m.copy;
         const int x0 = (w.chunk % I.nsx) * TX, ys = (w.chunk / I.nsx) * CH;
-        if (I.frozen)
-            copy_chunk<TX, NT>(m, in, out, x0, ys, CH);
-        else if (m.bc == 1)
+        if (m.bc == 1)
             march_chunk<TX, NT, CH, PF, true, 1>(m, in + kCopyF * P, out + kCopyF * P, in + kCopyH * P,
                                                  out + kCopyH * P, in + kCopyP * P, out + kCopyP * P,
                                                  in + kCopyPhiU * P, out + kCopyPhiU * P, nullptr, x0, ys, S);

@@ -75,10 +75,8 @@ struct Model {
 // One simulation of a batch, as the batched kernel sees it (device memory).
 struct BatchInst {
     Model m;
-    float* ws;        // base of the instance's workspace (planes as above)
+    float* ws;        // base of the instance's workspace (population copies as above)
     int nsx, nsy;     // strips and chunks of the batch's strip shape
-    int frozen;       // nonzero: a non-finite state was detected; the instance is held fixed
-    int pad;
 };
 // One unit of work of the batched kernel: chunk `chunk` (row-major over nsx x nsy) of `inst`.
 struct BatchItem {

@@ -73,15 +73,16 @@ if [ "$W" = "d3q15_256" ]; then
     exit $?
 fi
 if [ "$W" = "batch256" ]; then
-    # batched persistent step over the 256 seeded instances (frozen ones included: their chunks
-    # are copied through, 168 B per node like an update): autotuned strip shape, kernel trace,
-    # then HBM traffic (FETCH_SIZE, WRITE_SIZE, scaled by the same counters on the copy probe)
+    # batched persistent step over the 256 seeded instances (the ones frozen after the warm-up
+    # leave the work list; the node count is that of the active ones): autotuned strip shape,
+    # kernel trace, then HBM traffic (FETCH_SIZE, WRITE_SIZE, scaled by the same counters on the
+    # copy probe)
     OUT=$RAW/prof_batch256
     PROF=${PROFILE_OUT:-profiles}
     mkdir -p "$OUT" "$PROF"
     export TMPDIR=/tmp
-    CELLS=$(python3 -c "from paper_1902_08933_amd import workloads as W; print(sum(c['nx'] * c['ny'] for c, _ in W.batch_instances(256, seed=0)))") || exit 1
-    TILE=$(timeout -k 10 180 python3 -m paper_1902_08933_amd.profile_step --workload batch256 --autotune | tail -1) || exit 1
+    LAST=$(timeout -k 10 180 python3 -m paper_1902_08933_amd.profile_step --workload batch256 --autotune | tail -1) || exit 1
+    read -r TILE CELLS <<< "$LAST"
     echo "profile: autotuned strip shape $TILE, $CELLS nodes"
     STEP="python3 -m paper_1902_08933_amd.profile_step --workload batch256 --tile $TILE"
     PROBE="python3 -m paper_1902_08933_amd.profile_step --copy-mib 1024 --steps 2 --probe-blocks 4096"

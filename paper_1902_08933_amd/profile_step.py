@@ -166,9 +166,9 @@ def main():
                   flush=True)
         return 0
     if a.workload == "batch256":
-        if a.autotune:
-            b, _, _ = make_batch(torch)
-            print(b.autotune(trial_steps=8)[0], flush=True)
+        if a.autotune:  # last line: the strip shape and the number of active nodes
+            b, active, _ = make_batch(torch)
+            print(b.autotune(trial_steps=8)[0], active, flush=True)
             return 0
         tile, ms, active, total = run_batch(torch, a.steps, a.warmup, a.tile)
         print(f"batch256 tile {tile} {lbpf.tile_shapes()[tile]}: {ms:.4f} ms/step, active {active} of "
