@@ -793,11 +793,20 @@ static hipError_t launch_conv_t(const ConvArgs& a, hipStream_t st) {
     return pfw ? launch_conv_pf<KS, R, C, true>(a, grid, st) : launch_conv_pf<KS, R, C, false>(a, grid, st);
 }
 
+// LDS of the first layer: its patch and staged weights, or the epilogue's bf16 output tile (it has
+// no fused head, so nothing beyond the tile), whichever is larger; 20 KB at C = 32, which leaves
+// room for six workgroups per CU, as many as its registers allow
+template <int C>
+constexpr int conv_first_lds_elems() {
+    constexpr int in = (kConvTR + 2) * (kConvTC + 2) * 4 + C * 9 * 4;
+    constexpr int out = kConvTR * kConvTC * (C + 8);
+    return in > out ? in : out;
+}
+
 template <bool R, int C>
 static hipError_t launch_first_t(const ConvArgs& a, hipStream_t st) {
-    constexpr size_t lds = (size_t)conv_lds_elems<1, C>() * sizeof(bf16);
-    static_assert((kConvTR + 2) * (kConvTC + 2) * 4 + C * 9 * 4 <= conv_lds_elems<1, C>(),
-                  "patch and staged weights fit the first layer's LDS");
+    if (a.hw) return hipErrorInvalidValue;  // the LDS below holds no head outputs
+    constexpr size_t lds = (size_t)conv_first_lds_elems<C>() * sizeof(bf16);
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)&conv_first_kernel<R, C>,
