@@ -162,3 +162,29 @@ def test_batch_of_256_instances_runs():
     assert len(ok) >= 100
     assert all(d["nonfinite"] == 0 for d in ok)
     print(f"256 instances: {sum(flags)} frozen after 40 steps", flush=True)
+
+
+def test_every_instance_frozen_leaves_an_empty_work_list():
+    # both instances go non-finite: the work list is empty, steps (graph replays and single
+    # launches) do nothing, and re-initializing one brings it back alone
+    insts = mixed_instances()[:2]
+    bad = [(c, np.where(np.arange(p.size).reshape(p.shape) == 7, np.nan, p).astype(np.float32))
+           for c, p in insts]
+    b = make_batch(bad)
+    b.step(3)
+    flags, _ = b.status()
+    assert flags == [1, 1]
+    before = [fields(b.instance(k)) for k in range(2)]
+    b.step(11)
+    for k in range(2):
+        after = fields(b.instance(k))
+        for f in after:
+            np.testing.assert_array_equal(before[k][f], after[f])
+    b.init(0, insts[0][1])
+    b.step(5)
+    flags, diags = b.status()
+    assert flags == [0, 1] and diags[0]["nonfinite"] == 0
+    got = fields(b.instance(0))
+    ref = fields(single(insts[0][0], insts[0][1], 5))
+    for f in got:
+        np.testing.assert_array_equal(got[f], ref[f])
