@@ -27,7 +27,8 @@ def traffic_summary_path(workload, prefix="fused_step"):
 
 def measured_traffic(workload, cells, tile, prefix="fused_step", sources="step"):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken on the
-    current kernel source with the same strip (launch) shape; otherwise None."""
+    current kernel source with the same strip (launch) shape (tile None: a kernel without
+    shapes); otherwise None."""
     from paper_1902_08933_amd.rocprof_summary import kernel_source_hash
     path = traffic_summary_path(workload, prefix)
     if not os.path.exists(path):
@@ -37,9 +38,9 @@ def measured_traffic(workload, cells, tile, prefix="fused_step", sources="step")
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     c = re.search(r"cells:\s*([0-9]+)", text)
     k = re.search(r"--tile (\d+)", text)
-    if not (m and t and c and k) or m.group(1) != kernel_source_hash(sources) or int(c.group(1)) != cells:
+    if not (m and t and c) or m.group(1) != kernel_source_hash(sources) or int(c.group(1)) != cells:
         return None
-    if int(k.group(1)) != tile:
+    if tile is not None and (not k or int(k.group(1)) != tile):
         return None
     return float(t.group(1))
 
@@ -298,6 +299,8 @@ def single_phase_bench(n=1024, steps=2000, warmup=100):
                       "MLUPS": round(n * n / (ms * 1e-3) / 1e6, 1), "bytes_per_node": b,
                       "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                       "finite": bool(np.isfinite(sums["rho_tilde"]))}
+        if name == "incompressible" and n == 1024:  # HBM bytes per launch of sp_step_kernel
+            out[name]["traffic"] = measured_traffic("sp1024", n * n, None, prefix="sp_step", sources="sp")
     out["workload"] = f"single-phase source flow {n}x{n} periodic, S0 1e-4, F 1e-6, nu 1/6"
     return out
 

@@ -10,18 +10,33 @@ set -o pipefail
 W=${1:-spinodal1024}
 RAW=${RAW_OUT:-prof_raw}
 if [ "$W" = "sp1024" ]; then
-    # single-phase step with a mass source at 1024^2 (incompressible, full force term)
+    # single-phase step with a mass source at 1024^2 (incompressible, full force term): kernel
+    # trace, then HBM traffic (FETCH_SIZE, WRITE_SIZE, scaled by the same counters on the probe)
     OUT=$RAW/prof_sp1024
     PROF=${PROFILE_OUT:-profiles}
     mkdir -p "$OUT" "$PROF"
     export TMPDIR=/tmp
-    CMD="python3 -m paper_1902_08933_amd.profile_step --workload sp1024 --steps 100 --warmup 10"
+    CMD="python3 -m paper_1902_08933_amd.profile_step --workload sp1024"
+    PROBE="python3 -m paper_1902_08933_amd.profile_step --copy-mib 1024 --steps 2 --probe-blocks 4096"
     echo "profile: kernel trace sp1024" && \
-    timeout -k 10 180 rocprofv3 --kernel-trace --stats -d "$OUT/trace" -o run -- $CMD > "$OUT/trace.log" 2>&1 && \
+    timeout -k 10 180 rocprofv3 --kernel-trace --stats -d "$OUT/trace" -o run -- $CMD --steps 100 --warmup 10 > "$OUT/trace.log" 2>&1 && \
+    echo "profile: FETCH_SIZE sp1024" && \
+    timeout -s KILL 90 rocprofv3 --pmc FETCH_SIZE -d "$OUT/fetch" -o run -- $CMD --steps 5 --warmup 1 > "$OUT/fetch.log" 2>&1 && \
+    echo "profile: WRITE_SIZE sp1024" && \
+    timeout -s KILL 90 rocprofv3 --pmc WRITE_SIZE -d "$OUT/write" -o run -- $CMD --steps 5 --warmup 1 > "$OUT/write.log" 2>&1 && \
+    echo "profile: probe FETCH_SIZE" && \
+    timeout -s KILL 90 rocprofv3 --pmc FETCH_SIZE -d "$OUT/cfetch" -o run -- $PROBE > "$OUT/cfetch.log" 2>&1 && \
+    echo "profile: probe WRITE_SIZE" && \
+    timeout -s KILL 90 rocprofv3 --pmc WRITE_SIZE -d "$OUT/cwrite" -o run -- $PROBE > "$OUT/cwrite.log" 2>&1 && \
     python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --cells 1048576 \
         --kernel sp_step_kernel --alg-bytes-per-cell 92 --sources sp \
-        --command "bash paper_1902_08933_amd/profile_run.sh sp1024  (rocprofv3 --kernel-trace --stats -- $CMD)" \
-        --out "$PROF/sp_step_sp1024_trace.txt"
+        --command "bash paper_1902_08933_amd/profile_run.sh sp1024  (rocprofv3 --kernel-trace --stats -- $CMD --steps 100 --warmup 10)" \
+        --out "$PROF/sp_step_sp1024_trace.txt" && \
+    python3 -m paper_1902_08933_amd.rocprof_summary --fetch "$OUT/fetch/run_results.db" --write "$OUT/write/run_results.db" \
+        --calib-fetch "$OUT/cfetch/run_results.db" --calib-write "$OUT/cwrite/run_results.db" --calib-bytes 1073741824 \
+        --cells 1048576 --kernel sp_step_kernel --alg-bytes-per-cell 92 --sources sp \
+        --command "bash paper_1902_08933_amd/profile_run.sh sp1024  (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE -- $CMD --steps 5 --warmup 1; calibration: same counters on $PROBE)" \
+        --out "$PROF/sp_step_sp1024_pmc.txt"
     exit $?
 fi
 if [ "$W" = "r4_1024" ]; then
