@@ -423,9 +423,19 @@ int32_t lbpf3d_shape_count(void);
 lbpf_status lbpf3d_shape_info(int32_t shape, int32_t* tx, int32_t* ty, int32_t* cz);
 lbpf_status lbpf3d_set_shape(lbpf3d* c, int32_t shape);
 int32_t lbpf3d_get_shape(const lbpf3d* c);
-/* Time each shape for `steps` steps on the current state (which advances) and keep the
- * fastest; *best_shape receives it. Synchronizes the stream. */
-lbpf_status lbpf3d_autotune(lbpf3d* c, int32_t steps, int32_t* best_shape);
+/* Time each shape for `steps` steps and keep the fastest; *best_shape receives it. With a
+ * scratch_state buffer of lbpf3d_state_size() device bytes the state and step count are saved
+ * there first and restored afterwards; with NULL the state advances by the steps taken.
+ * Synchronizes the stream. */
+lbpf_status lbpf3d_autotune(lbpf3d* c, int32_t steps, void* scratch_state, int32_t* best_shape);
+/* Checkpoint: bytes of the current state (populations, histories, step count). */
+lbpf_status lbpf3d_state_size(const lbpf3d* c, size_t* bytes);
+/* Copy the current state into / out of a caller device buffer of lbpf3d_state_size() bytes (a
+ * 64-byte header, then the state copy as stored). A save followed by a load on another handle
+ * with equal params and layout resumes bit-identically; a checkpoint of another grid or layout
+ * is refused with LBPF_E_INVALID. The state copy is asynchronous on the handle's stream. */
+lbpf_status lbpf3d_save_state(lbpf3d* c, void* dst_device);
+lbpf_status lbpf3d_load_state(lbpf3d* c, const void* src_device);
 int64_t lbpf3d_step_count(const lbpf3d* c);
 lbpf_status lbpf3d_destroy(lbpf3d* c);
 const char* lbpf3d_last_error(const lbpf3d* c);

@@ -1087,12 +1087,57 @@ int32_t lbpf3d_get_shape(const lbpf3d* c) { return c ? c->shape : -1; }
 
 // Time every launch shape for `steps` steps on the current state and keep the fastest. The
 // state advances by all the steps taken; every shape gives bit-identical results.
-lbpf_status lbpf3d_autotune(lbpf3d* c, int32_t steps, int32_t* best_shape) {
+// checkpoint: 64-byte header {magic, version, nx, ny, nz, step, plane stride, copy floats}, then
+// the population copy holding the state, as stored
+static const int64_t kMagic3 = 0x4433424C;  // "LB3D"
+static const int64_t kVersion3 = 1;
+
+lbpf_status lbpf3d_state_size(const lbpf3d* c, size_t* bytes) {
+    if (!c || !bytes) return LBPF_E_INVALID;
+    *bytes = 64 + (size_t)c->m.copy * sizeof(float);
+    return LBPF_OK;
+}
+
+lbpf_status lbpf3d_save_state(lbpf3d* c, void* dst) {
+    if (!c) return LBPF_E_INVALID;
+    if (!c->initialized) return fail3(c, LBPF_E_STATE, "save before init");
+    if (!dst) return fail3(c, LBPF_E_INVALID, "dst is NULL");
+    const int64_t hdr[8] = {kMagic3, kVersion3, c->m.nx, c->m.ny, c->m.nz, c->step, c->m.plane, c->m.copy};
+    lbpf_status s;
+    // the header is copied synchronously (it lives on this stack frame)
+    if ((s = hip3(c, hipStreamSynchronize(c->stream), "sync")) != LBPF_OK) return s;
+    if ((s = hip3(c, hipMemcpy(dst, hdr, sizeof hdr, hipMemcpyHostToDevice), "save header")) != LBPF_OK) return s;
+    return hip3(c, hipMemcpyAsync((char*)dst + 64, copy3(c, c->cur), (size_t)c->m.copy * sizeof(float),
+                                  hipMemcpyDeviceToDevice, c->stream), "save state");
+}
+
+lbpf_status lbpf3d_load_state(lbpf3d* c, const void* src) {
+    if (!c) return LBPF_E_INVALID;
+    if (!src) return fail3(c, LBPF_E_INVALID, "src is NULL");
+    int64_t hdr[8];
+    lbpf_status s;
+    if ((s = hip3(c, hipStreamSynchronize(c->stream), "sync")) != LBPF_OK) return s;
+    if ((s = hip3(c, hipMemcpy(hdr, src, sizeof hdr, hipMemcpyDeviceToHost), "load header")) != LBPF_OK) return s;
+    if (hdr[0] != kMagic3 || hdr[1] != kVersion3 || hdr[2] != c->m.nx || hdr[3] != c->m.ny ||
+        hdr[4] != c->m.nz || hdr[6] != c->m.plane || hdr[7] != c->m.copy)
+        return fail3(c, LBPF_E_INVALID, "checkpoint does not match this grid and layout");
+    c->cur = 0;
+    if ((s = hip3(c, hipMemcpyAsync(copy3(c, 0), (const char*)src + 64, (size_t)c->m.copy * sizeof(float),
+                                    hipMemcpyDeviceToDevice, c->stream), "load state")) != LBPF_OK)
+        return s;
+    c->step = hdr[5];
+    c->initialized = 1;
+    return LBPF_OK;
+}
+
+lbpf_status lbpf3d_autotune(lbpf3d* c, int32_t steps, void* scratch_state, int32_t* best_shape) {
     if (!c) return LBPF_E_INVALID;
     if (!c->initialized) return fail3(c, LBPF_E_STATE, "autotune before init");
     if (steps < 1) return fail3(c, LBPF_E_INVALID, "steps < 1");
     hipEvent_t e0, e1;
     lbpf_status s;
+    const int64_t step0 = c->step;
+    if (scratch_state && (s = lbpf3d_save_state(c, scratch_state)) != LBPF_OK) return s;
     if ((s = hip3(c, hipEventCreate(&e0), "event")) != LBPF_OK) return s;
     if ((s = hip3(c, hipEventCreate(&e1), "event")) != LBPF_OK) { (void)hipEventDestroy(e0); return s; }
     float best = 1e30f;
@@ -1113,7 +1158,12 @@ lbpf_status lbpf3d_autotune(lbpf3d* c, int32_t steps, int32_t* best_shape) {
     (void)hipEventDestroy(e1);
     c->shape = bi;
     if (best_shape) *best_shape = bi;
-    return s;
+    if (s != LBPF_OK) return s;
+    if (scratch_state) {  // the trial steps are undone: state and step count as on entry
+        if ((s = lbpf3d_load_state(c, scratch_state)) != LBPF_OK) return s;
+        c->step = step0;
+    }
+    return LBPF_OK;
 }
 
 int64_t lbpf3d_step_count(const lbpf3d* c) { return c ? c->step : -1; }

@@ -705,7 +705,10 @@ SIGNATURES.update({
     "lbpf3d_shape_info": (_S, [ctypes.c_int32, _I32P, _I32P, _I32P]),
     "lbpf3d_set_shape": (_S, [_V, ctypes.c_int32]),
     "lbpf3d_get_shape": (ctypes.c_int32, [_V]),
-    "lbpf3d_autotune": (_S, [_V, ctypes.c_int32, _I32P]),
+    "lbpf3d_autotune": (_S, [_V, ctypes.c_int32, _V, _I32P]),
+    "lbpf3d_state_size": (_S, [_V, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbpf3d_save_state": (_S, [_V, _V]),
+    "lbpf3d_load_state": (_S, [_V, _V]),
     "lbpf3d_step_count": (ctypes.c_int64, [_V]),
     "lbpf3d_destroy": (_S, [_V]),
     "lbpf3d_last_error": (ctypes.c_char_p, [_V]),
@@ -823,11 +826,31 @@ class Simulation3D:
     def launch_shape(self):
         return int(self.lib.lbpf3d_get_shape(self._h))
 
-    def autotune(self, trial_steps=5):
-        """Time every launch shape (the state advances by the steps taken); keep the fastest."""
+    def autotune(self, trial_steps=5, restore=True):
+        """Time every launch shape and keep the fastest; with restore the state and step count
+        are put back afterwards (through a checkpoint buffer), else they advance."""
         best = ctypes.c_int32()
-        self._c(self.lib.lbpf3d_autotune(self._h, int(trial_steps), ctypes.byref(best)))
+        scratch = self.torch.empty(self.state_size(), dtype=self.torch.uint8, device=self.device) if restore else None
+        ptr = ctypes.c_void_p(scratch.data_ptr()) if restore else None
+        self._c(self.lib.lbpf3d_autotune(self._h, int(trial_steps), ptr, ctypes.byref(best)))
         return best.value
+
+    def state_size(self):
+        n = ctypes.c_size_t()
+        self._c(self.lib.lbpf3d_state_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def save_state(self, out=None):
+        buf = out if out is not None else self.torch.empty(self.state_size(), dtype=self.torch.uint8,
+                                                           device=self.device)
+        self._c(self.lib.lbpf3d_save_state(self._h, ctypes.c_void_p(buf.data_ptr())))
+        return buf
+
+    def load_state(self, buf):
+        if buf.numel() < self.state_size() or not buf.is_cuda:
+            raise ValueError("checkpoint buffer too small or not on the GPU")
+        self._c(self.lib.lbpf3d_load_state(self._h, ctypes.c_void_p(buf.data_ptr())))
+        return self
 
     @property
     def step_count(self):

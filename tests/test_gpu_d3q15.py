@@ -225,3 +225,54 @@ def test_large_grid_separate_planes_against_oracle_crop():
         e = rel(g, o.read(f)[np.ix_(inner, inner, inner)])
         print(f"  {f} {e:.2e}", flush=True)
         assert e <= tol, f
+
+
+def test_checkpoint_resume_bitwise():
+    # save after 7 steps, go on 9; a new handle loads the checkpoint and takes the same 9 steps
+    cfg, phi = case("droplet_24_walls_gravity_paper_g0")
+    a = gpu_sim(cfg, phi)
+    a.step(7)
+    ckpt = a.save_state()
+    a.step(9)
+    b = gpu_sim(cfg, np.zeros_like(phi))
+    b.load_state(ckpt)
+    assert b.step_count == 7
+    b.step(9)
+    assert b.step_count == a.step_count == 16
+    fa, fb = gpu_fields(a), gpu_fields(b)
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+
+
+def test_checkpoint_of_other_layout_refused(monkeypatch):
+    import torch
+    from paper_1902_08933_amd import lbpf
+    cfg, phi = case("tiny_5x4x3_walls")
+    a = gpu_sim(cfg, phi)
+    ckpt = a.save_state()
+    monkeypatch.setenv("LBPF_STATE_LAYOUT", "planar")
+    b = gpu_sim(cfg, phi)
+    buf = torch.zeros(max(ckpt.numel(), b.state_size()), dtype=torch.uint8, device="cuda")
+    buf[:ckpt.numel()] = ckpt
+    with pytest.raises(lbpf.LbpfError):
+        b.load_state(buf)
+
+
+def test_autotune_restores_state():
+    # the trial steps of every shape are undone: state and step count as before, and stepping on
+    # with the tuned shape equals a run that never tuned
+    cfg, phi = case("spinodal_40x20x24_qim")
+    a = gpu_sim(cfg, phi)
+    a.step(5)
+    before = gpu_fields(a)
+    a.autotune(2)
+    assert a.step_count == 5
+    after = gpu_fields(a)
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+    a.step(6)
+    b = gpu_sim(cfg, phi)
+    b.step(11)
+    fa, fb = gpu_fields(a), gpu_fields(b)
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
