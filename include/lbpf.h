@@ -391,7 +391,7 @@ typedef struct lbpf3d lbpf3d;
 
 /* Bytes of device workspace: two ping-pong copies of the state (g_1..14, h_0 hi, h_1..14,
  * h_0 lo, pressure and (phi u) histories; 34 planes each, interleaved by grid row with planes
- * pitch(nx) + 64 floats apart, or as separate planes of nz * ny * pitch(nx) + 4160 floats for
+ * pitch(nx) + 32 floats apart, or as separate planes of nz * ny * pitch(nx) + 4160 floats for
  * grids too large to interleave or when the environment sets LBPF_STATE_LAYOUT=planar), then the
  * FP64 reduction area. LBPF_E_INVALID for invalid params. */
 lbpf_status lbpf3d_workspace_size(const lbpf3d_params* params, size_t* bytes);

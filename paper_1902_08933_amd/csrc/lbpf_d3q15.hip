@@ -64,7 +64,7 @@ constexpr int kH0Lo = 15;
 // one and writes the other) and the reduction area; between steps the copy not holding the state
 // is free and field evaluation writes its seven planes there. Element (q, x, y, z) of a copy sits
 // at q * plane + z * slab + y * pitch + x, with the planes interleaved by grid row (plane =
-// pitch3(nx) + 64, pitch = 34 plane) unless the copy would then need per-lane offsets of 2^30
+// pitch3(nx) + 32, pitch = 34 plane) unless the copy would then need per-lane offsets of 2^30
 // floats or more, or the environment sets LBPF_STATE_LAYOUT=planar (separate planes).
 constexpr int kCopyG = 0, kCopyH = 14, kCopyP = 30, kCopyPhiU = 31, kCopyPlanes = 34;
 constexpr int kNumFields = 7;
@@ -856,10 +856,10 @@ static std::string validate3(const lbpf3d_params* p) {
     return "";
 }
 
-// Interleaved by row, consecutive planes of a row are pitch3(nx) + 64 floats apart: a row of a
-// 256-wide grid is 1 KiB, and planes a power of two apart measured 14.6 against 17.1 GLUPS at
-// 256^3.
-static long long row_plane3(int nx) { return pitch3(nx) + 64; }
+// Interleaved by row, consecutive planes of a row are pitch3(nx) + 32 floats apart: a row of a
+// 256-wide grid is 1 KiB, and planes a power of two apart measured 14.6 GLUPS at 256^3 against
+// 17.3 with 32 more floats (17.0 with 64, 128 or 192).
+static long long row_plane3(int nx) { return pitch3(nx) + 32; }
 static bool interleaved3(const lbpf3d_params* p) {
     const char* e = getenv("LBPF_STATE_LAYOUT");
     if (e && strcmp(e, "planar") == 0) return false;

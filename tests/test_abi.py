@@ -128,8 +128,8 @@ def test_workspace3d_size(lib):
     p = lbpf.make_params3d(_cfg3d())
     assert lib.lbpf3d_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
     # two population copies of 34 planes (g_1..14, h hi/lo pair and h_1..14, p, phi u), planes
-    # interleaved by row 64 + 64 floats apart, one layout pad per copy, then the reduction area
-    copy = 34 * 40 * 48 * (64 + 64) + 4160
+    # interleaved by row 64 + 32 floats apart, one layout pad per copy, then the reduction area
+    copy = 34 * 40 * 48 * (64 + 32) + 4160
     assert 2 * copy * 4 <= n.value < 2 * copy * 4 + 256 + 8 * (2048 * 4 + 64)
 
 
