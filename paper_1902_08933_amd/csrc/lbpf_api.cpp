@@ -117,14 +117,18 @@ static size_t plane_pad() {
 // LBPF_STATE_LAYOUT=planar, or unless a copy of 21 interleaved planes would need per-lane offsets
 // of 2^30 floats or more. The choice must not change between lbpf_workspace_size() and
 // lbpf_create() of one simulation.
+// Interleaved by row, consecutive planes of a row are row_plane(nx) floats apart: rows of 4 KiB
+// or less get 32 floats more, so that the planes of a row do not sit a power of two apart
+// (1024^2: 33.9 -> 34.4 GLUPS); longer rows do not (4096^2: 30.4 without, 30.1 with).
+static long long row_plane(int nx) { const int xp = pitch_of(nx); return xp + (xp <= 1024 ? 32 : 0); }
 static bool interleaved(const lbpf_params* p) {
     const char* e = getenv("LBPF_STATE_LAYOUT");
     if (e && strcmp(e, "planar") == 0) return false;
-    return (long long)p->ny * kCopyPlanes * pitch_of(p->nx) < (1LL << 30);
+    return (long long)p->ny * kCopyPlanes * row_plane(p->nx) < (1LL << 30);
 }
 static size_t copy_floats(const lbpf_params* p) {
-    const size_t rows = (size_t)p->ny * pitch_of(p->nx);
-    return interleaved(p) ? kCopyPlanes * rows + plane_pad() : kCopyPlanes * (rows + plane_pad());
+    return interleaved(p) ? kCopyPlanes * (size_t)p->ny * row_plane(p->nx) + plane_pad()
+                          : kCopyPlanes * ((size_t)p->ny * pitch_of(p->nx) + plane_pad());
 }
 static size_t f64_floats(const lbpf_params* p) { return 2 * (size_t)p->ny * pitch_of(p->nx); }
 
@@ -141,8 +145,8 @@ static Model make_model(const lbpf_params* p) {
     m.ny = p->ny;
     m.xpitch = pitch_of(p->nx);
     if (interleaved(p)) {
-        m.pitch = kCopyPlanes * m.xpitch;
-        m.plane = m.xpitch;
+        m.plane = row_plane(p->nx);
+        m.pitch = (int)(kCopyPlanes * m.plane);
     } else {
         m.pitch = m.xpitch;
         m.plane = (long long)p->ny * m.xpitch + (long long)plane_pad();

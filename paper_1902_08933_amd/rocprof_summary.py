@@ -17,7 +17,9 @@ import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_FILES = {
-    "step": [os.path.join(HERE, "csrc", n) for n in ("lbpf_kernels.hip", "lbpf_cell.hpp", "lbpf_model.hpp")],
+    # the state layout (strides) of the step is chosen in lbpf_api.cpp
+    "step": [os.path.join(HERE, "csrc", n) for n in ("lbpf_kernels.hip", "lbpf_cell.hpp", "lbpf_model.hpp",
+                                                     "lbpf_api.cpp")],
     "unet": [os.path.join(HERE, "csrc", n) for n in ("lbpf_unet_kernels.hip", "lbpf_unet_ops.hpp",
                                                      "lbpf_unet.cpp")],
     "sp": [os.path.join(HERE, "csrc", "lbpf_sp.hip")],

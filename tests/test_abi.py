@@ -45,10 +45,12 @@ def test_workspace_size_scales_with_grid(lib):
     cfg, _ = workloads.static_droplet(n=64)
     a = lbpf.workspace_size(cfg)
     b = lbpf.workspace_size(dict(cfg, nx=128, ny=128))
-    # 44 FP32 planes per node: two population copies of 21 planes (f_1..8, h hi/lo pair and
-    # h_1..8, p, phi u) and the FP64 scratch; the layout pad and the reduction area do not depend
-    # on the grid size
-    assert b - a == 44 * 4 * (128 * 128 - 64 * 64)
+    # two population copies of 21 planes (f_1..8, h hi/lo pair and h_1..8, p, phi u), rows of
+    # planes 64 + 32 floats apart (short rows), and the FP64 scratch of ny * pitch doubles; the
+    # layout pad and the reduction area do not depend on the grid size
+    def grid_floats(n):
+        return 2 * 21 * n * (n + 32) + 2 * n * n
+    assert b - a == 4 * (grid_floats(128) - grid_floats(64))
 
 
 @pytest.mark.parametrize("bad,why", [
@@ -81,12 +83,13 @@ def test_largest_plane_accepted(lib):
 
 
 def test_planar_layout_size(lib, monkeypatch):
-    # separate planes carry one layout pad per plane; interleaved copies one per copy
+    # separate planes carry one layout pad per plane; interleaved copies one per copy, and their
+    # short rows 32 floats more per plane
     cfg, _ = workloads.static_droplet(n=64)
     inter = lbpf.workspace_size(cfg)
     monkeypatch.setenv("LBPF_STATE_LAYOUT", "planar")
     planar = lbpf.workspace_size(cfg)
-    assert planar - inter == 2 * 20 * 4160 * 4
+    assert planar - inter == (2 * 20 * 4160 - 2 * 21 * 64 * 32) * 4
 
 
 def test_status_strings(lib):
