@@ -359,7 +359,7 @@ def main():
     ap.add_argument("--workload", default="spinodal1024")
     ap.add_argument("--variant", default="qim")
     ap.add_argument("--tile", type=int, default=None, help="strip shape index (default: library default)")
-    ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--cpu-steps", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
