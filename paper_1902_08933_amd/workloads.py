@@ -78,17 +78,6 @@ def plane_phi(nx, ny, W, y0=None):
     return np.broadcast_to(0.5 + 0.5 * np.tanh(2.0 * y / W), (ny, nx)).copy()
 
 
-def layered_analytic_ux(ny, G, mu_A, mu_B):
-    """Steady layered-Poiseuille velocity, eq. (37), at the node rows of layered_phi."""
-    h = ny / 2.0
-    y = np.arange(ny, dtype=np.float64) + 0.5 - h
-    s = y / h
-    k = (mu_A - mu_B) / (mu_A + mu_B)
-    top = G * h * h / (2 * mu_A) * (-s * s - s * k + 2 * mu_A / (mu_A + mu_B))
-    bot = G * h * h / (2 * mu_B) * (-s * s - s * k + 2 * mu_B / (mu_A + mu_B))
-    return np.where(y > 0, top, bot)
-
-
 # ---- workloads -----------------------------------------------------------------------------
 
 def static_droplet(n=64, R=16.0, variant="qim", rho_ratio=10.0, sigma=0.01, tau=0.8,

@@ -16,6 +16,8 @@ import oracle
 import oracle.d3q15 as O
 from paper_1902_08933_amd import workloads as W
 
+from analytic import layered_analytic_ux
+
 C = np.array([[0, 1, 0, 0, -1, 0, 0, 1, 1, 1, -1, -1, -1, -1, 1],
               [0, 0, 1, 0, 0, -1, 0, 1, 1, -1, 1, -1, -1, 1, -1],
               [0, 0, 0, 1, 0, 0, -1, 1, -1, 1, 1, -1, 1, -1, -1]], dtype=float).T
@@ -276,7 +278,7 @@ def test_layered_poiseuille_table2():
     o = O.Oracle3D(cfg).init(phi)
     o.step(40000)
     u = o.read("ux")
-    ua = W.layered_analytic_ux(nz, G, mu_A, mu_B)
+    ua = layered_analytic_ux(nz, G, mu_A, mu_B)
     err = np.abs(u[:, 0, 0] - ua).sum() / np.abs(ua).sum()
     assert err <= bound
     assert np.abs(u - u[:, :1, :1]).max() < 1e-12 * np.abs(ua).max()

@@ -20,6 +20,8 @@ import pytest
 
 from paper_1902_08933_amd import workloads as W
 
+from analytic import layered_analytic_ux
+
 pytestmark = pytest.mark.gpu
 
 NY = 100
@@ -31,7 +33,7 @@ def setup(ratio):
     nu_A, nu_B = W.table2_viscosities(ratio)
     G = 5e-5 * (nu_A + nu_B) / h ** 2  # u_c (mu_A + mu_B) / h^2 at unit density
     steps = max(150000, int(1.2 * h * h / nu_B))
-    return nu_B, G, steps, W.layered_analytic_ux(NY, G, nu_A, nu_B)
+    return nu_B, G, steps, layered_analytic_ux(NY, G, nu_A, nu_B)
 
 
 def error(u, ua):

@@ -10,6 +10,8 @@ import pytest
 import oracle
 from paper_1902_08933_amd import workloads as W
 
+from analytic import layered_analytic_ux
+
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -120,7 +122,7 @@ def test_layered_poiseuille_table2(ratio):
     o = oracle.Oracle(cfg).init(phi)
     o.step(40000)
     u = o.read("ux")[:, 0]
-    ua = W.layered_analytic_ux(ny, G, mu_A, mu_B)
+    ua = layered_analytic_ux(ny, G, mu_A, mu_B)
     err = np.abs(u - ua).sum() / np.abs(ua).sum()
     assert err <= bound
 
