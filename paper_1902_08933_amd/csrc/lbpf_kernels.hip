@@ -138,7 +138,7 @@ struct MarchLds {
 
 // One workgroup marches the chunk of a strip starting at column x0, rows ys .. ys+CH-1
 // (clipped to the grid), of one simulation.
-template <int TX, int NT, int CH, bool PF, bool COLLIDE, int BC>
+template <int TX, int NT, int CH, bool PF, bool COLLIDE, int BC, bool PADFILL = false>
 __device__ __forceinline__ void march_chunk(const Model& m, const float* __restrict__ fin,
                                             float* __restrict__ fout,
                                             const float* __restrict__ hin,
@@ -232,6 +232,16 @@ __device__ __forceinline__ void march_chunk(const Model& m, const float* __restr
             const Stencil st = gather(s_phh, s_phl, prow(rowO - 1), prow(rowO), prow(rowO + 1), tx + 2,
                                       s_mu, s_p, mrow(rowO - 1), mrow(rowO), mrow(rowO + 1), tx + 1);
             cell_update<COLLIDE, BC>(m, xo, rowO, cell, f, hc, pu, st, fout, hout, pout, phiu_out, fields);
+        } else if (PADFILL && COLLIDE && xo >= nx && xo < ((nx + 31) & ~31) && rowO < ye) {
+            // columns from nx to the end of the row's last 128-byte line are never read: filling
+            // them makes every line of the output rows a whole-line write
+#pragma unroll
+            for (int q = 0; q < kFPlanes; ++q) *pl(fout, P, q, cell) = 0.0f;
+#pragma unroll
+            for (int q = 0; q < kHPlanes; ++q) *pl(hout, P, q, cell) = 0.0f;
+            *pl(pout, P, 0, cell) = 0.0f;
+            *pl(phiu_out, P, 0, cell) = 0.0f;
+            *pl(phiu_out, P, 1, cell) = 0.0f;
         }
         if (!PF && Y + TY < ye) march_load<TX, TY, BC>(m, fin, hin, pin, phiu_in, x0, Y + TY, ye, tid, L);
     }
@@ -513,11 +523,11 @@ __global__ __launch_bounds__(NT) void batch_kernel(const BatchInst* __restrict__
         float* out = I.ws + (1 - parity) * m.copy;
         const int x0 = (w.chunk % I.nsx) * TX, ys = (w.chunk / I.nsx) * CH;
         if (m.bc == 1)
-            march_chunk<TX, NT, CH, PF, true, 1>(m, in + kCopyF * P, out + kCopyF * P, in + kCopyH * P,
+            march_chunk<TX, NT, CH, PF, true, 1, true>(m, in + kCopyF * P, out + kCopyF * P, in + kCopyH * P,
                                                  out + kCopyH * P, in + kCopyP * P, out + kCopyP * P,
                                                  in + kCopyPhiU * P, out + kCopyPhiU * P, nullptr, x0, ys, S);
         else
-            march_chunk<TX, NT, CH, PF, true, 0>(m, in + kCopyF * P, out + kCopyF * P, in + kCopyH * P,
+            march_chunk<TX, NT, CH, PF, true, 0, true>(m, in + kCopyF * P, out + kCopyF * P, in + kCopyH * P,
                                                  out + kCopyH * P, in + kCopyP * P, out + kCopyP * P,
                                                  in + kCopyPhiU * P, out + kCopyPhiU * P, nullptr, x0, ys, S);
         __syncthreads();  // LDS is reused by the next item
