@@ -149,6 +149,8 @@ def batch_bench(steps, count=256, seed=0):
         out[name] = {"ms_per_step": round(ms, 4), "MLUPS": round(active / (ms * 1e-3) / 1e6, 1),
                      "algorithmic_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
     out["speedup"] = round(out["launch_per_instance"]["ms_per_step"] / out["graph_persistent"]["ms_per_step"], 2)
+    # HBM bytes of one persistent launch, from the committed counter summary of this workload
+    out["graph_persistent"]["traffic"] = measured_traffic("batch256", active, batch_tile, prefix="batch_step")
     return out
 
 
