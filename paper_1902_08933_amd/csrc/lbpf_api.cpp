@@ -35,7 +35,7 @@ hipError_t launch_fields_to_nhwc(const Model& m, const float* fields, float* dst
 hipError_t launch_nhwc_to_dense(const Model& m, const float* src, float* phi, float* ux, float* uy,
                                 float* p, const float* shift, const float* scale, hipStream_t st);
 hipError_t launch_batch(int tile, const BatchInst* insts, const BatchItem* items, int nitems,
-                        int grid, int parity, hipStream_t st);
+                        int grid, int parity, int* ctrs, int slot, hipStream_t st);
 }  // namespace lbpf
 
 using namespace lbpf;
@@ -506,6 +506,8 @@ struct lbpf_batch {
     size_t ws_bytes;
     BatchInst* d_insts;               // device arrays at the start of the workspace
     BatchItem* d_items;
+    int* d_ctr;                       // kBatchSlots x 8 band counters of the batch kernel
+    int slot;                         // counter slot of the next batch-kernel launch
     size_t max_items;
     int nitems;
     int tile;
@@ -520,6 +522,7 @@ struct lbpf_batch {
 };
 
 static const int kBatchGraphSteps = 8;
+static_assert(kBatchGraphSteps == kBatchSlots, "a graph replay uses every counter slot once, in order");
 
 static lbpf_status bfail(lbpf_batch* b, lbpf_status s, const char* fmt, ...) {
     char buf[512];
@@ -548,7 +551,8 @@ static size_t batch_max_items(int n, const lbpf_params* params) {
 }
 
 static size_t batch_header_bytes(int n, const lbpf_params* params) {
-    return align256(sizeof(BatchInst) * n) + align256(sizeof(BatchItem) * batch_max_items(n, params));
+    return align256(sizeof(BatchInst) * n) + align256(sizeof(BatchItem) * batch_max_items(n, params)) +
+           align256(sizeof(int) * 8 * kBatchSlots);
 }
 
 static void destroy_graphs(lbpf_batch* b) {
@@ -580,20 +584,6 @@ static lbpf_status batch_setup(lbpf_batch* b) {
     }
     if (items.size() > b->max_items) return bfail(b, LBPF_E_NOMEM, "work list overflow");
     b->nitems = (int)items.size();
-    {
-        // Workgroup g of the persistent grid runs on XCD g % 8 and takes list positions g,
-        // g + grid, ...; with a grid that is a multiple of 8 (or covers the list), position p is
-        // processed on XCD p % 8. Give each XCD a contiguous band of chunks so that neighbouring
-        // strips, which re-read each other's ghost columns, share an L2 (1024^2 in one instance:
-        // 23 -> 28 GLUPS).
-        std::vector<BatchItem> perm(items.size());
-        const int n = b->nitems, per = n / 8, rem = n % 8;
-        for (int p = 0; p < n; ++p) {
-            const int xcd = p % 8, loc = p / 8;
-            perm[p] = items[xcd * per + std::min(xcd, rem) + loc];
-        }
-        items.swap(perm);
-    }
     int dev = 0, cus = 0;
     e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -603,18 +593,24 @@ static lbpf_status batch_setup(lbpf_batch* b) {
     if (e == hipSuccess) e = hipMemcpy(b->d_insts, hi.data(), sizeof(BatchInst) * b->n, hipMemcpyHostToDevice);
     if (e == hipSuccess && !items.empty())  // every instance frozen: an empty list
         e = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
+    // counters start at zero, and the next launch uses slot 0 (the first of a graph replay)
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_ctr, 0, sizeof(int) * 8 * kBatchSlots, b->stream);
+    b->slot = 0;
     if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "work list upload: %s", hipGetErrorString(e));
     destroy_graphs(b);
     for (int start = 0; start < 2; ++start) {
         e = hipGraphCreate(&b->graph[start], 0);
         hipGraphNode_t prev = nullptr;
-        int parities[kBatchGraphSteps];
+        int parities[kBatchGraphSteps], slots[kBatchGraphSteps];
         for (int sidx = 0; sidx < kBatchGraphSteps && e == hipSuccess; ++sidx) {
             parities[sidx] = (start + sidx) & 1;
+            slots[sidx] = sidx;
             const BatchInst* di = b->d_insts;
             const BatchItem* dt = b->d_items;
             int ni = b->nitems;
-            void* args[] = {(void*)&di, (void*)&dt, (void*)&ni, (void*)&parities[sidx]};
+            int* dc = b->d_ctr;
+            void* args[] = {(void*)&di, (void*)&dt, (void*)&ni, (void*)&parities[sidx], (void*)&dc,
+                            (void*)&slots[sidx]};
             hipKernelNodeParams kp{};
             kp.func = fn;
             kp.gridDim = dim3(b->grid);
@@ -668,6 +664,8 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_params* params, void* worksp
     b->d_insts = (BatchInst*)b->ws;
     b->max_items = batch_max_items(n, params);
     b->d_items = (BatchItem*)(b->ws + align256(sizeof(BatchInst) * n));
+    b->d_ctr = (int*)(b->ws + align256(sizeof(BatchInst) * n) + align256(sizeof(BatchItem) * b->max_items));
+    b->slot = 0;
     b->tile = kDefaultBatchTile;
     b->parity = 0;
     b->step = 0;
@@ -742,18 +740,28 @@ static void batch_advance(lbpf_batch* b, int64_t nsteps) {
 lbpf_status lbpf_batch_step(lbpf_batch* b, int64_t nsteps) {
     if (lbpf_status s = batch_check(b)) return s;
     if (nsteps < 0) return bfail(b, LBPF_E_INVALID, "nsteps must be >= 0");
+    // launches use the counter slots in cyclic order: single launches up to slot 0, then whole
+    // graph replays (slots 0 .. 7), then single launches for the rest
     int64_t done = 0;
+    auto single = [&]() -> lbpf_status {
+        hipError_t e = launch_batch(b->tile, b->d_insts, b->d_items, b->nitems, b->grid, b->parity, b->d_ctr,
+                                    b->slot, b->stream);
+        if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "batch kernel: %s", hipGetErrorString(e));
+        b->slot = (b->slot + 1) % kBatchSlots;
+        batch_advance(b, 1);
+        ++done;
+        return LBPF_OK;
+    };
+    while (b->slot != 0 && done < nsteps)
+        if (lbpf_status s = single()) return s;
     while (nsteps - done >= b->graph_steps) {
         hipError_t e = hipGraphLaunch(b->exec[b->parity], b->stream);
         if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "graph launch: %s", hipGetErrorString(e));
         batch_advance(b, b->graph_steps);
         done += b->graph_steps;
     }
-    for (; done < nsteps; ++done) {
-        hipError_t e = launch_batch(b->tile, b->d_insts, b->d_items, b->nitems, b->grid, b->parity, b->stream);
-        if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "batch kernel: %s", hipGetErrorString(e));
-        batch_advance(b, 1);
-    }
+    while (done < nsteps)
+        if (lbpf_status s = single()) return s;
     return LBPF_OK;
 }
 

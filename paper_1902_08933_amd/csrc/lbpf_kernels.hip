@@ -502,20 +502,40 @@ static hipError_t launch_fused(int tile, const Model& m, const float* fin, float
 }
 
 // ---------------------------------------------------------------------------------------------
-// Batched persistent step: every workgroup loops over the work list of (instance, chunk)
-// items of all simulations of a batch, with a stride of the grid size; each item is one
-// march_chunk of that instance with its own model constants, so each instance evolves
-// bit-identically to a single-simulation launch. `parity` selects the population copy read.
-// Frozen instances have no items: their state stays in the copy it was in.
+// Batched persistent step. The work list of (instance, chunk) items is split into nb = min(8,
+// grid) contiguous bands; workgroup g serves band g % nb (with g on XCD g % 8, each XCD works on
+// one band, so neighbouring strips, which re-read each other's ghost columns and share the cache
+// lines at their boundary, run together in one L2). Within a band the workgroups take items in
+// list order from a counter, so neighbouring items start together even when item costs differ.
+// Each item is one march_chunk of its instance with its own model constants, so each instance
+// evolves bit-identically to a single-simulation launch. `parity` selects the population copy
+// read. Frozen instances have no items: their state stays in the copy it was in.
+//
+// Counters: kBatchSlots slots of 8 band counters; a launch uses slot `slot` and the launches are
+// issued with slots in cyclic order, so the slot used by the previous launch (finished, by stream
+// order) is cleared by this one for its next use kBatchSlots launches later.
 // ---------------------------------------------------------------------------------------------
 
 template <int TX, int NT, int CH, bool PF>
 __global__ __launch_bounds__(NT) void batch_kernel(const BatchInst* __restrict__ insts,
                                                    const BatchItem* __restrict__ items,
-                                                   int nitems, int parity) {
+                                                   int nitems, int parity, int* __restrict__ ctrs,
+                                                   int slot) {
     __shared__ MarchLds<TX, NT> S;
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const BatchItem w = items[it];
+    __shared__ int s_loc;
+    if (blockIdx.x == 0 && threadIdx.x < 8)
+        ctrs[((slot + kBatchSlots - 1) % kBatchSlots) * 8 + threadIdx.x] = 0;
+    const int nb = min(8, (int)gridDim.x), band = blockIdx.x % nb;
+    const int per = nitems / nb, rem = nitems % nb;
+    const int first = band * per + min(band, rem), len = per + (band < rem ? 1 : 0);
+    int* ctr = ctrs + slot * 8 + band;
+    for (;;) {
+        __syncthreads();  // LDS and s_loc of the previous item are no longer read
+        if (threadIdx.x == 0) s_loc = atomicAdd(ctr, 1);
+        __syncthreads();
+        const int loc = s_loc;
+        if (loc >= len) break;
+        const BatchItem w = items[first + loc];
         const BatchInst& I = insts[w.inst];
         const Model m = I.m;
         const long long P = m.plane;
@@ -530,7 +550,6 @@ __global__ __launch_bounds__(NT) void batch_kernel(const BatchInst* __restrict__
             march_chunk<TX, NT, CH, PF, true, 0, true>(m, in + kCopyF * P, out + kCopyF * P, in + kCopyH * P,
                                                  out + kCopyH * P, in + kCopyP * P, out + kCopyP * P,
                                                  in + kCopyPhiU * P, out + kCopyPhiU * P, nullptr, x0, ys, S);
-        __syncthreads();  // LDS is reused by the next item
     }
 }
 
@@ -571,12 +590,12 @@ hipError_t batch_kernel_info(int tile, void** fn, int* nt, int* tx, int* ch, int
 }
 
 hipError_t launch_batch(int tile, const BatchInst* insts, const BatchItem* items, int nitems,
-                        int grid, int parity, hipStream_t st) {
+                        int grid, int parity, int* ctrs, int slot, hipStream_t st) {
     void* fn;
     int nt, tx, ch, per;
     hipError_t e = batch_kernel_info(tile, &fn, &nt, &tx, &ch, &per);
     if (e != hipSuccess) return e;
-    void* args[] = {(void*)&insts, (void*)&items, (void*)&nitems, (void*)&parity};
+    void* args[] = {(void*)&insts, (void*)&items, (void*)&nitems, (void*)&parity, (void*)&ctrs, (void*)&slot};
     return hipLaunchKernel(fn, dim3(grid), dim3(nt), args, 0, st);
 }
 

@@ -78,6 +78,8 @@ struct BatchInst {
     float* ws;        // base of the instance's workspace (population copies as above)
     int nsx, nsy;     // strips and chunks of the batch's strip shape
 };
+// Counter slots of the batched kernel (launches use them in cyclic order; see batch_kernel).
+constexpr int kBatchSlots = 8;
 // One unit of work of the batched kernel: chunk `chunk` (row-major over nsx x nsy) of `inst`.
 struct BatchItem {
     int inst, chunk;
