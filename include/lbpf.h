@@ -197,7 +197,8 @@ const char* lbpf_create_error(void);
  * ------------------------------------------------------------------------------------------ */
 typedef struct lbpf_batch lbpf_batch;
 
-/* Device workspace bytes for n instances with parameters params[0..n-1]. */
+/* Device workspace bytes for n instances with parameters params[0..n-1]: the instance table,
+ * the work list, 8 x 8 work counters of the batched kernel, then each instance's workspace. */
 lbpf_status lbpf_batch_workspace_size(int32_t n, const lbpf_params* params, size_t* bytes);
 /* Bind a batch to a caller-owned workspace (256-byte aligned) and stream; builds the work
  * list of (instance, strip chunk) items and the step graphs. Errors as lbpf_create. */
@@ -206,8 +207,10 @@ lbpf_status lbpf_batch_create(int32_t n, const lbpf_params* params, void* worksp
 /* Initial state of instance idx, as lbpf_init; also clears a frozen flag. */
 lbpf_status lbpf_batch_init(lbpf_batch* b, int32_t idx, const float* phi, const float* ux,
                             const float* uy, const float* p);
-/* Advance every instance nsteps steps: graph replays of 8 steps, then single launches. Every
- * instance must be initialized. Asynchronous. */
+/* Advance every instance nsteps steps. Launches use the 8 work-counter slots of the workspace
+ * in cyclic order: single launches until slot 0 comes round, graph replays of 8 steps (slots
+ * 0..7), then single launches. Every instance must be initialized. Asynchronous; steps of one
+ * batch must not be issued on two streams at once (they share the counters). */
 lbpf_status lbpf_batch_step(lbpf_batch* b, int64_t nsteps);
 /* Reference path: the same steps with one single-simulation launch per instance per step (a
  * frozen instance is skipped), for comparison with lbpf_batch_step. */
