@@ -188,3 +188,19 @@ def test_every_instance_frozen_leaves_an_empty_work_list():
     ref = fields(single(insts[0][0], insts[0][1], 5))
     for f in got:
         np.testing.assert_array_equal(got[f], ref[f])
+
+
+def test_single_launches_then_graph_replays_keep_every_item():
+    # 3 single launches leave the next counter slot at 3: the following call launches 5 singles
+    # up to slot 0, then a graph replay of 8 and 6 more singles; every item must run each step
+    insts = mixed_instances()[:4]
+    b = make_batch(insts)
+    b.step(3)
+    b.step(19)
+    b.step(1)
+    assert b.step_count == 23
+    for k, (c, p) in enumerate(insts):
+        got = fields(b.instance(k))
+        ref = fields(single(c, p, 23))
+        for f in got:
+            np.testing.assert_array_equal(got[f], ref[f])
