@@ -83,6 +83,10 @@ static const char* validate(const lbpf_params* p) {
     if (!p) return "params is NULL";
     if (p->nx < 3 || p->ny < 3) return "nx and ny must be >= 3";
     if (p->nx >= (1 << 24) || p->ny >= (1 << 24)) return "nx and ny must be below 2^24";
+    // the kernels form a row offset y * pitch with the 24-bit multiplier, so the row stride of
+    // a copy must stay below 2^24 floats (interleaved() falls back to separate planes, whose
+    // stride is pitch_of(nx))
+    if (pitch_of(p->nx) >= (1 << 24)) return "nx rounded up to a multiple of 64 must be below 2^24";
     // kernels address a node inside a plane with a 32-bit byte offset (planes stored separately
     // when the grid is too large to interleave them)
     if ((long long)p->ny * pitch_of(p->nx) + plane_pad() >= (1LL << 30))
@@ -115,8 +119,9 @@ static size_t plane_pad() {
 }
 // Layout of a population copy (see lbpf_model.hpp): planes interleaved by row unless
 // LBPF_STATE_LAYOUT=planar, or unless a copy of 21 interleaved planes would need per-lane offsets
-// of 2^30 floats or more. The choice must not change between lbpf_workspace_size() and
-// lbpf_create() of one simulation.
+// of 2^30 floats or more, or a row stride (21 row planes) of 2^24 floats or more, which the
+// kernels' 24-bit row multiply cannot form. The choice must not change between
+// lbpf_workspace_size() and lbpf_create() of one simulation.
 // Interleaved by row, consecutive planes of a row are row_plane(nx) floats apart: rows of 4 KiB
 // or less get 32 floats more, so that the planes of a row do not sit a power of two apart
 // (1024^2: 33.9 -> 34.4 GLUPS); longer rows do not (4096^2: 30.4 without, 30.1 with).
@@ -124,7 +129,8 @@ static long long row_plane(int nx) { const int xp = pitch_of(nx); return xp + (x
 static bool interleaved(const lbpf_params* p) {
     const char* e = getenv("LBPF_STATE_LAYOUT");
     if (e && strcmp(e, "planar") == 0) return false;
-    return (long long)p->ny * kCopyPlanes * row_plane(p->nx) < (1LL << 30);
+    const long long stride = kCopyPlanes * row_plane(p->nx);
+    return stride < (1LL << 24) && (long long)p->ny * stride < (1LL << 30);
 }
 static size_t copy_floats(const lbpf_params* p) {
     return interleaved(p) ? kCopyPlanes * (size_t)p->ny * row_plane(p->nx) + plane_pad()

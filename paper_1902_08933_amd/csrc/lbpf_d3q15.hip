@@ -840,6 +840,9 @@ static std::string validate3(const lbpf3d_params* p) {
     if (!p) return "params is NULL";
     if (p->nx < 3 || p->ny < 3 || p->nz < 3) return "nx, ny, nz must be >= 3";
     if (p->nx >= (1 << 24) || p->ny >= (1 << 24) || p->nz >= (1 << 24)) return "grid side >= 2^24";
+    // row offsets y * pitch use the 24-bit multiplier: the row stride must stay below 2^24
+    // floats (interleaved3() falls back to separate planes, whose stride is pitch3(nx))
+    if (pitch3(p->nx) >= (1 << 24)) return "nx rounded up to a multiple of 64 must be below 2^24";
     const long long slab = (long long)p->ny * pitch3(p->nx);
     if (slab * p->nz + kPlanePad >= (1LL << 30)) return "nz * ny * pitch(nx) + pad must be < 2^30";
     if (p->variant != 0 && p->variant != 1) return "variant must be 0 (QIM) or 1 (IM)";
@@ -863,7 +866,8 @@ static long long row_plane3(int nx) { return pitch3(nx) + 32; }
 static bool interleaved3(const lbpf3d_params* p) {
     const char* e = getenv("LBPF_STATE_LAYOUT");
     if (e && strcmp(e, "planar") == 0) return false;
-    return (long long)p->nz * p->ny * kCopyPlanes * row_plane3(p->nx) < (1LL << 30);
+    const long long stride = kCopyPlanes * row_plane3(p->nx);
+    return stride < (1LL << 24) && (long long)p->nz * p->ny * stride < (1LL << 30);
 }
 static size_t copy_floats3(const lbpf3d_params* p) {
     const size_t rows = (size_t)p->nz * p->ny;

@@ -165,3 +165,47 @@ def test_shapes3d_listed(lib):
     shapes = lbpf.shapes3d()
     assert len(shapes) >= 4 and all(tx * ty in (256, 512) for tx, ty, _ in shapes)
     assert lib.lbpf3d_shape_info(len(shapes), None, None, None) == -1
+
+
+def test_long_rows_fall_back_to_separate_planes(lib):
+    # Row offsets y * pitch use the 24-bit multiplier. At nx = 800000 an interleaved copy would
+    # have a row stride of 21 * 800000 = 16.8 M floats >= 2^24 (but only 52.9 M floats per copy,
+    # well below 2^30), so the layout must be separate planes, whose row stride is 800000.
+    cfg, _ = workloads.static_droplet(n=16, R=4)
+    nx, ny = 800000, 63
+    got = lbpf.workspace_size(dict(cfg, nx=nx, ny=ny))
+    red = 8 * (4096 * 8 + 64)
+    planar = (2 * 21 * (ny * nx + 4160) + 2 * ny * nx) * 4 + red
+    interleaved = (2 * (21 * ny * nx + 4160) + 2 * ny * nx) * 4 + red
+    assert got == planar != interleaved
+    # the largest row stride an interleaved copy may have: 21 * 798912 < 2^24 <= 21 * 798976
+    for nx, inter in ((798912, True), (798976, False)):
+        got = lbpf.workspace_size(dict(cfg, nx=nx, ny=ny))
+        expect = ((2 * (21 * ny * nx + 4160) if inter else 2 * 21 * (ny * nx + 4160))
+                  + 2 * ny * nx) * 4 + red
+        assert got == expect, nx
+
+
+def test_row_pitch_of_2_pow_24_rejected(lib):
+    # nx = 2^24 - 10 rounds up to a pitch of 2^24, whose low 24 bits are 0
+    cfg, _ = workloads.static_droplet(n=16, R=4)
+    with pytest.raises(lbpf.LbpfError) as ei:
+        lbpf.workspace_size(dict(cfg, nx=(1 << 24) - 10, ny=3))
+    assert ei.value.status == -1 and "2^24" in str(ei.value)
+    p = lbpf.make_params3d(_cfg3d(nx=(1 << 24) - 10, ny=3, nz=3))
+    n = ctypes.c_size_t()
+    assert lib.lbpf3d_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
+
+
+def test_long_rows_3d_fall_back_to_separate_planes(lib):
+    # D3Q15 copies interleave 34 planes per row, (pitch + 32) floats apart: 34 * (493440 + 32)
+    # = 16.78 M floats >= 2^24, so a 493440-wide grid is stored as separate planes
+    def size(nx):
+        n = ctypes.c_size_t()
+        p = lbpf.make_params3d(_cfg3d(nx=nx, ny=3, nz=3))
+        assert lib.lbpf3d_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+        return n.value
+    for nx, inter in ((493376, True), (493440, False)):
+        rows = 9
+        copy = 34 * rows * (nx + 32) + 4160 if inter else 34 * (rows * nx + 4160)
+        assert 2 * copy * 4 <= size(nx) < 2 * copy * 4 + 256 + 8 * (2048 * 4 + 64), nx
