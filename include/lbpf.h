@@ -288,6 +288,52 @@ const char* lbpf_unet_last_error(const lbpf_unet* u);
  * bf16, D 16 x 16 FP32, device arrays): the operand-layout check of the surrogate kernels. */
 lbpf_status lbpf_mfma_probe(int32_t k, const void* A, const void* B, float* D, void* hip_stream);
 
+/* One convolution of the surrogate network run by the kernel the network's layers use, chosen by
+ * the same rules from the sizes: the check of the convolution kernels on caller tensors, layer by
+ * layer. out[p, co] = bias[co] + sum_{tap, ci} in[p + off(tap), ci] wt[co][tap][ci] with circular
+ * padding (off(tap) = (tap / 3 - 1, tap % 3 - 1) for ks = 3, (0, 0) for ks = 1), FP32
+ * accumulation, then ReLU if asked. The input channels are [up(xl), x]: channels [0, cl) the
+ * nearest 2x upsampling of xl, channels [cl, cin) from x; or, in first-layer mode (xin set,
+ * ks = 3, cl = 0), the bf16 rounding of the FP32 fields of xin, cin being then the weights'
+ * channel stride. Outputs (each optional, all NHWC device arrays): y the bf16 rounding (to
+ * nearest even) of out; yp the bf16 rounding of the mean of each 2 x 2 block of y (h, w even);
+ * yf out in FP32; pred = res + out[:, :rc], or with hw set (cout <= 32) res + hb + the 1 x 1
+ * head hw [rc][cout] applied to y. Channel counts, cl and cin - cl multiples of 8 except in
+ * first-layer mode. variant (3 int32, may be NULL) receives the kernel chosen: first-layer
+ * kernel (1) or tiled (0), output channels per workgroup (16, 32, 64), and 1 if the next input
+ * chunk's weights are prefetched into registers. Asynchronous; LBPF_E_INVALID for shapes the
+ * kernels do not take. Defined by the network description above; used by its tests. */
+typedef struct lbpf_unet_conv_desc {
+    int32_t ks, relu;  /* 1 or 3; nonzero: ReLU after the bias */
+    int32_t n, h, w;   /* images and their size */
+    int32_t cin, cl;   /* input channels; the first cl of them upsampled from xl */
+    int32_t cout;      /* output channels */
+    int32_t xin_c;     /* first-layer mode: fields of xin (1..4) */
+    int32_t rc;        /* channels of res and pred (1..16) */
+    const void* x;     /* bf16 [n][h][w][cin - cl] */
+    const void* xl;    /* bf16 [n][h/2][w/2][cl] */
+    const float* xin;  /* FP32 [n][h][w][xin_c] */
+    const void* wt;    /* bf16 [cout][ks*ks][cin] */
+    const float* bias; /* FP32 [cout] or NULL */
+    void* y;           /* bf16 [n][h][w][cout] */
+    void* yp;          /* bf16 [n][h/2][w/2][cout] */
+    float* yf;         /* FP32 [n][h][w][cout] */
+    const float* res;  /* FP32 [n][h][w][rc] */
+    float* pred;       /* FP32 [n][h][w][rc] */
+    const void* hw;    /* bf16 [rc][cout] */
+    const float* hb;   /* FP32 [rc] or NULL */
+} lbpf_unet_conv_desc;
+lbpf_status lbpf_unet_conv_probe(const lbpf_unet_conv_desc* desc, int32_t* variant, void* hip_stream);
+/* The weight and bias gradients of one such convolution (ks 1 or 3, no upsampled part) as the
+ * network's backward pass computes them: dw[co][tap][ci] = sum_p dy[p, co] x[p + off(tap), ci]
+ * and db[co] = sum_p dy[p, co] (FP32), with dy bf16 [n][h][w][cout] and x bf16 [n][h][w][cin],
+ * from per-chunk partials summed in a fixed order. part and bpart are caller device scratch of
+ * max_chunks * cout * ks*ks * cin and max_chunks * cout floats. cin, cout multiples of 8.
+ * Asynchronous. */
+lbpf_status lbpf_unet_wgrad_probe(int32_t ks, const void* dy, const void* x, int32_t n, int32_t h,
+                                  int32_t w, int32_t cin, int32_t cout, int32_t max_chunks,
+                                  float* part, float* bpart, float* dw, float* db, void* hip_stream);
+
 /* Hand-over between the solver and the surrogate: the current fields of a simulation as
  * normalized NHWC [ny][nx][4] FP32, (field - shift[c]) / scale[c] for c = phi, u_x, u_y, p
  * (host arrays of 4; dst 16-byte aligned); and a new state from such fields at time level

@@ -516,6 +516,66 @@ lbpf_status lbpf_unet_destroy(lbpf_unet* u) {
 
 const char* lbpf_unet_last_error(const lbpf_unet* u) { return u ? u->err.c_str() : g_unet_err.c_str(); }
 
+lbpf_status lbpf_unet_conv_probe(const lbpf_unet_conv_desc* d, int32_t* variant, void* hip_stream) {
+    if (!d || !d->wt || (!d->x && !d->xin) || (d->cl > 0 && !d->xl)) return LBPF_E_INVALID;
+    if (d->n < 1 || d->h < 1 || d->w < 1 || d->cin < 1 || d->cout < 1 || d->cl < 0 || d->cl > d->cin)
+        return LBPF_E_INVALID;
+    if ((d->pred && !d->res) || (d->hw && !d->pred) || ((d->pred || d->hw) && (d->rc < 1 || d->rc > 16)))
+        return LBPF_E_INVALID;
+    ConvArgs a{};
+    if (d->xin) {
+        if (d->x || d->cl || d->xin_c < 1 || d->xin_c > 4) return LBPF_E_INVALID;
+        a.xin = d->xin;
+        a.xin_c = d->xin_c;
+    } else {
+        a.x = (const bf16*)d->x;
+        a.xs = d->cin - d->cl;
+        a.xo = 0;
+    }
+    a.xl = (const bf16*)d->xl;
+    a.xls = d->cl;
+    a.xlo = 0;
+    a.Cl = d->cl;
+    a.Cin = d->cin;
+    a.w = (const bf16*)d->wt;
+    a.bias = d->bias;
+    a.y = (bf16*)d->y;
+    a.ys = d->cout;
+    a.yo = 0;
+    a.yp = (bf16*)d->yp;
+    a.yps = d->cout;
+    a.ypo = 0;
+    a.yf = d->yf;
+    a.res = d->res;
+    a.pred = d->pred;
+    a.rc = d->rc;
+    a.hw = (const bf16*)d->hw;
+    a.hb = d->hb;
+    a.Cout = d->cout;
+    a.N = d->n;
+    a.H = d->h;
+    a.W = d->w;
+    ConvPlan plan;
+    if (unet_conv_plan(d->ks, a, &plan) != hipSuccess) return LBPF_E_INVALID;
+    if (variant) {
+        variant[0] = plan.first;
+        variant[1] = plan.cot;
+        variant[2] = plan.pfw;
+    }
+    return unet_conv(d->ks, d->relu != 0, a, (hipStream_t)hip_stream) == hipSuccess ? LBPF_OK : LBPF_E_HIP;
+}
+
+lbpf_status lbpf_unet_wgrad_probe(int32_t ks, const void* dy, const void* x, int32_t n, int32_t h,
+                                  int32_t w, int32_t cin, int32_t cout, int32_t max_chunks,
+                                  float* part, float* bpart, float* dw, float* db, void* hip_stream) {
+    if (!dy || !x || !part || !bpart || !dw || !db || n < 1 || h < 1 || w < 1 || max_chunks < 1 ||
+        (ks != 1 && ks != 3) || cin < 8 || cout < 8 || cin % 8 || cout % 8)
+        return LBPF_E_INVALID;
+    hipError_t e = unet_conv_wgrad(ks, (const bf16*)dy, cout, 0, cout, (const bf16*)x, cin, 0, cin, n, h, w,
+                                   max_chunks, part, bpart, dw, db, (hipStream_t)hip_stream);
+    return e == hipSuccess ? LBPF_OK : LBPF_E_HIP;
+}
+
 lbpf_status lbpf_mfma_probe(int32_t k, const void* A, const void* B, float* D, void* hip_stream) {
     if (!A || !B || !D || (k != 16 && k != 32)) return LBPF_E_INVALID;
     hipError_t e = unet_mfma_probe(k == 32, (const bf16*)A, (const bf16*)B, D, (hipStream_t)hip_stream);

@@ -784,12 +784,9 @@ static hipError_t launch_conv_pf(const ConvArgs& a, dim3 grid, hipStream_t st) {
 }
 
 template <int KS, bool R, int C>
-static hipError_t launch_conv_t(const ConvArgs& a, hipStream_t st) {
+static hipError_t launch_conv_t(const ConvArgs& a, bool pfw, hipStream_t st) {
     const long long tiles = (long long)a.N * ((a.H + kConvTR - 1) / kConvTR) * ((a.W + kConvTC - 1) / kConvTC);
     dim3 grid((unsigned)tiles, (unsigned)((a.Cout + C - 1) / C));
-    // COT = 32: three workgroups per CU without the weight prefetch pay off only when the grid
-    // has enough workgroups to fill them (three per CU)
-    const bool pfw = C >= 64 || (long long)grid.x * grid.y < 768;
     return pfw ? launch_conv_pf<KS, R, C, true>(a, grid, st) : launch_conv_pf<KS, R, C, false>(a, grid, st);
 }
 
@@ -820,7 +817,8 @@ static hipError_t launch_first_t(const ConvArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t unet_conv(int ks, bool relu, const ConvArgs& a, hipStream_t st) {
+hipError_t unet_conv_plan(int ks, const ConvArgs& a, ConvPlan* plan) {
+    ConvPlan p{};
     if (a.xin) {
         const bool ok = ks == 3 && a.xin_c >= 1 && a.xin_c <= 4 && a.Cl == 0 && !a.hw &&
                         (!a.y || (a.Cout % 8 == 0 && a.ys % 8 == 0 && a.yo % 8 == 0)) &&
@@ -828,8 +826,11 @@ hipError_t unet_conv(int ks, bool relu, const ConvArgs& a, hipStream_t st) {
                                    a.H % 2 == 0 && a.W % 2 == 0)) &&
                         (!a.pred || a.res) && a.N >= 1 && a.H >= 1 && a.W >= 1;
         if (!ok) return hipErrorInvalidValue;
-        if (a.Cout <= 32) return relu ? launch_first_t<true, 32>(a, st) : launch_first_t<false, 32>(a, st);
-        return relu ? launch_first_t<true, 64>(a, st) : launch_first_t<false, 64>(a, st);
+        p.first = 1;
+        p.cot = a.Cout <= 32 ? 32 : 64;
+        p.pfw = 0;
+        *plan = p;
+        return hipSuccess;
     }
     const bool aligned = a.Cin % 8 == 0 && a.xs % 8 == 0 && a.xo % 8 == 0 &&
                          (a.Cl == 0 || (a.Cl % 8 == 0 && a.xls % 8 == 0 && a.xlo % 8 == 0 &&
@@ -849,14 +850,32 @@ hipError_t unet_conv(int ks, bool relu, const ConvArgs& a, hipStream_t st) {
     // workgroups per CU when the grid fills them
     if (cot == 64 && a.Cin <= kConvCK && tiles * ((a.Cout + 31) / 32) >= 768) cot = 32;
     if (cot == 64 && tiles * ((a.Cout + 63) / 64) < 512) cot = 32;
-#define LBPF_CONV(KS_, C_) return relu ? launch_conv_t<KS_, true, C_>(a, st) : launch_conv_t<KS_, false, C_>(a, st)
+    // COT = 32: three workgroups per CU without the weight prefetch pay off only when the grid
+    // has enough workgroups to fill them (three per CU)
+    p.first = 0;
+    p.cot = cot;
+    p.pfw = (cot >= 64 || tiles * ((a.Cout + cot - 1) / cot) < 768) ? 1 : 0;
+    *plan = p;
+    return hipSuccess;
+}
+
+hipError_t unet_conv(int ks, bool relu, const ConvArgs& a, hipStream_t st) {
+    ConvPlan p;
+    const hipError_t e = unet_conv_plan(ks, a, &p);
+    if (e != hipSuccess) return e;
+    if (p.first) {
+        if (p.cot == 32) return relu ? launch_first_t<true, 32>(a, st) : launch_first_t<false, 32>(a, st);
+        return relu ? launch_first_t<true, 64>(a, st) : launch_first_t<false, 64>(a, st);
+    }
+    const bool pfw = p.pfw != 0;
+#define LBPF_CONV(KS_, C_) return relu ? launch_conv_t<KS_, true, C_>(a, pfw, st) : launch_conv_t<KS_, false, C_>(a, pfw, st)
     if (ks == 3) {
-        if (cot == 16) LBPF_CONV(3, 16);
-        if (cot == 32) LBPF_CONV(3, 32);
+        if (p.cot == 16) LBPF_CONV(3, 16);
+        if (p.cot == 32) LBPF_CONV(3, 32);
         LBPF_CONV(3, 64);
     }
-    if (cot == 16) LBPF_CONV(1, 16);
-    if (cot == 32) LBPF_CONV(1, 32);
+    if (p.cot == 16) LBPF_CONV(1, 16);
+    if (p.cot == 32) LBPF_CONV(1, 32);
     LBPF_CONV(1, 64);
 #undef LBPF_CONV
 }

@@ -48,6 +48,12 @@ struct ConvArgs {
     int Cout, N, H, W;
 };
 
+// Kernel variant a convolution runs with: the first-layer kernel or the tiled one, its output
+// channels per workgroup (16, 32, 64) and whether it prefetches the next chunk's weights.
+struct ConvPlan {
+    int first, cot, pfw;
+};
+hipError_t unet_conv_plan(int ks, const ConvArgs& a, ConvPlan* plan);
 hipError_t unet_conv(int ks, bool relu, const ConvArgs& a, hipStream_t st);
 // plain convolution (no upsampled part, bf16 output only)
 hipError_t unet_conv_fwd(int ks, bool relu, const bf16* x, int xs, int xo, int Cin, const bf16* w,

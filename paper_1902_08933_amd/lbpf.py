@@ -436,6 +436,9 @@ SIGNATURES.update({
     "lbpf_unet_destroy": (_S, [_V]),
     "lbpf_unet_last_error": (ctypes.c_char_p, [_V]),
     "lbpf_mfma_probe": (_S, [ctypes.c_int32, _V, _V, _V, _V]),
+    "lbpf_unet_conv_probe": (_S, [_V, ctypes.POINTER(ctypes.c_int32), _V]),
+    "lbpf_unet_wgrad_probe": (_S, [ctypes.c_int32, _V, _V, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _V, _V, _V, _V, _V]),
     "lbpf_fields_to_nhwc": (_S, [_V, _V, _PF, _PF]),
     "lbpf_init_from_nhwc": (_S, [_V, _V, _PF, _PF, ctypes.c_int64]),
 })
@@ -470,6 +473,53 @@ def mfma_probe(A_bf16_bits, B_bf16_bits, D, k=16):
     if st != 0:
         raise LbpfError(st, "mfma probe")
     return D
+
+
+class ConvDesc(ctypes.Structure):
+    """lbpf_unet_conv_desc"""
+    _fields_ = [(k, ctypes.c_int32) for k in ("ks", "relu", "n", "h", "w", "cin", "cl", "cout", "xin_c", "rc")] + \
+               [(k, ctypes.c_void_p) for k in ("x", "xl", "xin", "wt", "bias", "y", "yp", "yf", "res", "pred",
+                                               "hw", "hb")]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def conv_probe(ks, relu, n, h, w, cin, cout, wt, x=None, xl=None, cl=0, xin=None, bias=None, y=None, yp=None,
+               yf=None, res=None, pred=None, hw=None, hb=None):
+    """One convolution by the network's kernels (lbpf_unet_conv_probe); tensors are contiguous
+    NHWC device arrays (bf16 ones as int16 bits). Returns the kernel variant (first, cot, pfw)."""
+    import torch
+    d = ConvDesc()
+    d.ks, d.relu, d.n, d.h, d.w, d.cin, d.cl, d.cout = ks, int(bool(relu)), n, h, w, cin, cl, cout
+    d.xin_c = xin.shape[-1] if xin is not None else 0
+    d.rc = res.shape[-1] if res is not None else 0
+    for k, t in (("x", x), ("xl", xl), ("xin", xin), ("wt", wt), ("bias", bias), ("y", y), ("yp", yp),
+                 ("yf", yf), ("res", res), ("pred", pred), ("hw", hw), ("hb", hb)):
+        setattr(d, k, t.data_ptr() if t is not None else None)
+    var = (ctypes.c_int32 * 3)()
+    st = library().lbpf_unet_conv_probe(ctypes.byref(d), var, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != 0:
+        raise LbpfError(st, "conv probe")
+    return tuple(var)
+
+
+def wgrad_probe(ks, dy, x, n, h, w, cin, cout, max_chunks=64):
+    """Weight and bias gradients of one convolution by the network's kernels; returns (dw, db)
+    as FP32 device tensors [cout, ks*ks, cin] and [cout]."""
+    import torch
+    dev = dy.device
+    part = torch.empty(max_chunks * cout * ks * ks * cin, dtype=torch.float32, device=dev)
+    bpart = torch.empty(max_chunks * cout, dtype=torch.float32, device=dev)
+    dw = torch.empty((cout, ks * ks, cin), dtype=torch.float32, device=dev)
+    db = torch.empty(cout, dtype=torch.float32, device=dev)
+    st = library().lbpf_unet_wgrad_probe(ks, _ptr(dy), _ptr(x), n, h, w, cin, cout, max_chunks, _ptr(part),
+                                         _ptr(bpart), _ptr(dw), _ptr(db),
+                                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != 0:
+        raise LbpfError(st, "wgrad probe")
+    return dw, db
 
 
 class UNet:

@@ -1,9 +1,11 @@
 """Parity of the HIP solver (FP32 arithmetic, h_0 as an FP32 hi/lo pair) with the FP64 CPU
-oracle, element by element on the same seeded inputs, through the C ABI.
+oracle on the same seeded inputs, through the C ABI: every field is compared over all its
+nodes, by relative L2 and by the largest element-wise difference.
 
 Tolerances: relative L2 <= 1e-5 on phi and on u = (u_x, u_y) after 100 steps, and relative
 drift of sum(phi) <= 1e-6. The pressure has no stated bound; it is held to 1e-4 (its FP32
-error is of the same order as that of u, amplified by the 1/(1 - w_0) of eq. 28).
+error is of the same order as that of u, amplified by the 1/(1 - w_0) of eq. 28). Element-wise
+bounds: tests/parity.py.
 """
 import numpy as np
 import pytest
@@ -11,14 +13,9 @@ import pytest
 import oracle
 from paper_1902_08933_amd import workloads as W
 
+from parity import MAX_P, MAX_PHI, MAX_U, TOL_DRIFT, TOL_P, TOL_PHI, TOL_U, check
+
 pytestmark = pytest.mark.gpu
-
-TOL_PHI, TOL_U, TOL_P, TOL_DRIFT = 1e-5, 1e-5, 1e-4, 1e-6
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
 
 
 def gpu_sim(cfg, phi, tile=None):
@@ -99,16 +96,12 @@ def test_parity_100_steps(name):
     d1 = sim.diagnostics()
     o = oracle.Oracle(cfg).init(phi32.astype(np.float64)).step(100)
     r = oracle_fields(o)
-    e_phi = rel(g["phi"], r["phi"])
-    e_u = rel(np.stack([g["ux"], g["uy"]]), np.stack([r["ux"], r["uy"]]))
-    e_p = rel(g["p"], r["p"])
-    e_rho = rel(g["rho"], r["rho"])
+    check("phi", g["phi"], r["phi"], TOL_PHI, MAX_PHI)
+    check("u", np.stack([g["ux"], g["uy"]]), np.stack([r["ux"], r["uy"]]), TOL_U, MAX_U)
+    check("p", g["p"], r["p"], TOL_P, MAX_P)
+    check("rho", g["rho"], r["rho"], TOL_PHI, MAX_PHI)
     drift = abs(d1["sum_phi"] - d0["sum_phi"]) / abs(d0["sum_phi"])
-    print(f"  rel L2 phi {e_phi:.2e} u {e_u:.2e} p {e_p:.2e} rho {e_rho:.2e} drift {drift:.2e}",
-          flush=True)
-    assert e_phi <= TOL_PHI
-    assert e_u <= TOL_U
-    assert e_p <= TOL_P
+    print(f"  drift {drift:.2e}", flush=True)
     assert drift <= TOL_DRIFT
     assert abs(d1["sum_phi"] - o.sum_phi()) / abs(o.sum_phi()) <= TOL_DRIFT
     assert d1["nonfinite"] == 0
@@ -119,9 +112,9 @@ def test_init_state_matches_oracle():
     phi32 = phi.astype(np.float32)
     g = gpu_fields(gpu_sim(cfg, phi32))
     r = oracle_fields(oracle.Oracle(cfg).init(phi32.astype(np.float64)))
-    assert rel(g["phi"], r["phi"]) < 1e-7
-    assert rel(g["mu"], r["mu"]) < 1e-5
-    assert rel(np.stack([g["ux"], g["uy"]]), np.stack([r["ux"], r["uy"]])) < 1e-5
+    check("phi", g["phi"], r["phi"], 1e-7, 1e-7)
+    check("mu", g["mu"], r["mu"], 1e-5, 1e-4)
+    check("u", np.stack([g["ux"], g["uy"]]), np.stack([r["ux"], r["uy"]]), 1e-5, MAX_U)
 
 
 @pytest.mark.parametrize("nx,ny,bc", [(3, 3, "periodic"), (3, 5, "walls_y"), (65, 17, "walls_y"),
@@ -135,8 +128,8 @@ def test_parity_edge_grids(nx, ny, bc):
     sim.step(50)
     g = gpu_fields(sim)
     r = oracle_fields(oracle.Oracle(cfg).init(phi.astype(np.float64)).step(50))
-    assert rel(g["phi"], r["phi"]) <= TOL_PHI
-    assert rel(np.stack([g["ux"], g["uy"]]), np.stack([r["ux"], r["uy"]])) <= TOL_U
+    check("phi", g["phi"], r["phi"], TOL_PHI, MAX_PHI)
+    check("u", np.stack([g["ux"], g["uy"]]), np.stack([r["ux"], r["uy"]]), TOL_U, MAX_U)
 
 
 def test_zero_steps_is_noop():
@@ -252,8 +245,8 @@ def test_full_size_spinodal_1024(variant):
     sim.step(5)
     g = gpu_fields(sim, ("phi", "ux", "uy"))
     o = oracle.Oracle(cfg).init(phi32.astype(np.float64)).step(5)
-    assert rel(g["phi"], o.read("phi")) <= TOL_PHI
-    assert rel(np.stack([g["ux"], g["uy"]]), np.stack([o.read("ux"), o.read("uy")])) <= TOL_U
+    check("phi", g["phi"], o.read("phi"), TOL_PHI, MAX_PHI)
+    check("u", np.stack([g["ux"], g["uy"]]), np.stack([o.read("ux"), o.read("uy")]), TOL_U, MAX_U)
     sim.step(1995)
     d1 = sim.diagnostics()
     assert abs(d1["sum_phi"] - d0["sum_phi"]) / d0["sum_phi"] <= TOL_DRIFT
@@ -326,11 +319,10 @@ def test_large_grid_separate_planes_against_oracle_crop():
     o = oracle.Oracle(dict(cfg, nx=40, ny=40)).init(crop).step(2)
     inner = np.arange(10, 30)
     sel = np.ix_(iy[inner], ix[inner])
-    for f, tol in (("phi", TOL_PHI), ("ux", TOL_U), ("uy", TOL_U), ("p", TOL_P)):
+    for f, tol, tmax in (("phi", TOL_PHI, MAX_PHI), ("ux", TOL_U, MAX_U), ("uy", TOL_U, MAX_U),
+                         ("p", TOL_P, MAX_P)):
         g = sim.read(f)[torch_index(sel)].double().cpu().numpy()
-        e = rel(g, o.read(f)[np.ix_(inner, inner)])
-        print(f"  {f} {e:.2e}", flush=True)
-        assert e <= tol, f
+        check(f, g, o.read(f)[np.ix_(inner, inner)], tol, tmax)
     d = sim.diagnostics()
     assert d["nonfinite"] == 0
 
@@ -360,3 +352,42 @@ def test_library_opened_before_torch_shares_its_hip_runtime():
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "steps 3" in r.stdout
+
+
+@pytest.mark.parametrize("tile", [15, None])
+def test_bench_4096_interleaved_against_oracle_crop(tile):
+    # the benchmark's 4096^2 spinodal: rows longer than 4 KiB, so the 21 planes of a copy are
+    # interleaved by row with no pad between them (the workspace size says which layout), at strip
+    # shape 15 (256 x 32, 512 threads: the one the autotuner picks there) and at the shape the
+    # autotuner picks on this machine; two steps, then the inner 20^2 nodes of a 40^2 periodic crop
+    # around the grid corner against the oracle run on that crop
+    from paper_1902_08933_amd import lbpf
+    n = 4096
+    cfg, phi = W.spinodal(n=n, variant="qim", seed=0)
+    red = (4096 * 8 + 64) * 8
+    assert lbpf.workspace_size(cfg) == (2 * (21 * n * n + 4160) + 2 * n * n) * 4 + red
+    phi32 = phi.astype(np.float32)
+    sim = gpu_sim(cfg, phi32, tile=tile)
+    if tile is None:
+        sim.autotune(trial_steps=3)
+        assert sim.step_count == 0
+    print(f"4096^2 interleaved, strip shape {sim.tile} {lbpf.tile_shapes()[sim.tile]}", flush=True)
+    sim.step(2)
+    ix = np.arange(-20, 20) % n
+    crop = phi32[np.ix_(ix, ix)].astype(np.float64)
+    o = oracle.Oracle(dict(cfg, nx=40, ny=40)).init(crop).step(2)
+    inner = np.arange(10, 30)
+    sel = np.ix_(ix[inner], ix[inner])
+    for f, tol, tmax in (("phi", TOL_PHI, MAX_PHI), ("ux", TOL_U, MAX_U), ("uy", TOL_U, MAX_U),
+                         ("p", TOL_P, MAX_P)):
+        g = sim.read(f)[torch_index(sel)].double().cpu().numpy()
+        check(f, g, o.read(f)[np.ix_(inner, inner)], tol, tmax)
+    # and a crop in the middle of the grid, away from every periodic seam
+    c0 = n // 2 - 20
+    jx = np.arange(c0, c0 + 40)
+    o = oracle.Oracle(dict(cfg, nx=40, ny=40)).init(phi32[np.ix_(jx, jx)].astype(np.float64)).step(2)
+    sel = np.ix_(jx[inner], jx[inner])
+    for f, tol, tmax in (("phi", TOL_PHI, MAX_PHI), ("ux", TOL_U, MAX_U), ("uy", TOL_U, MAX_U)):
+        g = sim.read(f)[torch_index(sel)].double().cpu().numpy()
+        check(f, g, o.read(f)[np.ix_(inner, inner)], tol, tmax)
+    assert sim.diagnostics()["nonfinite"] == 0
