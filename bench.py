@@ -17,8 +17,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-BYTES_PER_CELL = 168   # f_1..8, h_0 hi, h_1..8, h_0 lo, p, (phi u)_x, (phi u)_y: 21 FP32 read + 21 written
+# Algorithmic HBM bytes per node update of the method: the hydrodynamic populations 1..8 (the rest
+# population is never read), the nine phase-field populations, p^{n-1} and (phi u)^{n-1}, each
+# FP32 read once and written once: 20 + 20 values.
+BYTES_PER_CELL = 160
+# What the kernel stores per node and step on top: the low word of the rest phase-field
+# population (an FP32 hi/lo pair), read and written: 21 + 21 values.
+STORAGE_BYTES_PER_CELL = 168
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+ROOFLINE_GATE = 0.70   # target fraction of the peak, judged at a footprint far above the 256 MB cache
 
 
 def traffic_summary_path(workload, prefix="fused_step"):
@@ -103,10 +110,15 @@ def probe_copy_gbs(mib=2048, reps=10):
     return best
 
 
+BATCH_WARMUP = 200  # steps before freezing: the unstable instances diverge within ~40 (FP64 too)
+
+
 def batch_bench(steps, count=256, seed=0):
     """256 independent instances (sides 64..512): one graph-replayed persistent launch per step
     vs one single-simulation launch per instance per step. Instances the method cannot hold
-    stable are frozen after the warm-up; MLUPS counts the active instances' nodes."""
+    stable (the largest density ratios) are frozen after a warm-up past their divergence window;
+    MLUPS counts the nodes of the instances that are still finite at the end of the run (the
+    frozen count is taken again after the timed legs, and the legs are re-timed if it grew)."""
     import numpy as np
     import torch
     from paper_1902_08933_amd import lbpf
@@ -116,13 +128,18 @@ def batch_bench(steps, count=256, seed=0):
     for k, (_, phi) in enumerate(insts):
         b.init(k, torch.from_numpy(np.ascontiguousarray(phi, dtype=np.float32)).cuda())
     del insts
-    b.step(16)
+    b.step(BATCH_WARMUP)
     flags, _ = b.status()     # freezes the instances that went unstable
+    frozen_warm = int(sum(flags))
     b.autotune(trial_steps=8)  # strip shape for the active instances
-    active = sum(c["nx"] * c["ny"] for c, f in zip(b.cfgs, flags) if not f)
     total = sum(c["nx"] * c["ny"] for c in b.cfgs)
-    out = {"instances": count, "frozen": int(sum(flags)), "active_nodes": active, "total_nodes": total,
-           "strip": list(lbpf.tile_shapes()[b.tile])}
+    ratio = [c["rho_A"] / c["rho_B"] for c in b.cfgs]
+    out = {"instances": count, "warmup_steps": BATCH_WARMUP, "frozen_after_warmup": frozen_warm,
+           "total_nodes": total, "strip": list(lbpf.tile_shapes()[b.tile]),
+           "density_ratio_ge_150": {"instances": int(sum(r >= 150 for r in ratio)),
+                                    "node_fraction": round(sum(c["nx"] * c["ny"] for c, r in zip(b.cfgs, ratio)
+                                                               if r >= 150) / total, 3)}}
+
     def timed(fn):
         fn(8)
         torch.cuda.synchronize()
@@ -136,14 +153,23 @@ def batch_bench(steps, count=256, seed=0):
     # the per-instance reference runs at its own best strip shape (a shape good for one persistent
     # launch over every instance is not the best for a launch per small instance)
     batch_tile = b.tile
-    per_inst = {}
-    for t in sorted({batch_tile, 0, 1, 5, 12}):
-        b.set_tile(t)
-        per_inst[t] = timed(b.step_each)
-    best_each = min(per_inst, key=per_inst.get)
-    b.set_tile(batch_tile)
+    for attempt in range(2):
+        per_inst = {}
+        for t in sorted({batch_tile, 0, 1, 5, 12}):
+            b.set_tile(t)
+            per_inst[t] = timed(b.step_each)
+        best_each = min(per_inst, key=per_inst.get)
+        b.set_tile(batch_tile)
+        ms_graph = timed(b.step)
+        flags_end, _ = b.status()
+        if int(sum(flags_end)) == int(sum(flags)):
+            break
+        flags = flags_end  # an instance went non-finite during the timed legs: time again
+    active = sum(c["nx"] * c["ny"] for c, f in zip(b.cfgs, flags_end) if not f)
+    out.update({"frozen": int(sum(flags_end)), "frozen_at_end": int(sum(flags_end)), "active_nodes": active,
+                "steps_total": int(b.step_count)})
     out["launch_per_instance_strip"] = list(lbpf.tile_shapes()[best_each])
-    for name, ms in (("graph_persistent", timed(b.step)), ("launch_per_instance", per_inst[best_each])):
+    for name, ms in (("graph_persistent", ms_graph), ("launch_per_instance", per_inst[best_each])):
         # frozen instances leave the work list, so only the active nodes move bytes
         gbs = BYTES_PER_CELL * active / (ms * 1e-3) / 1e9
         out[name] = {"ms_per_step": round(ms, 4), "MLUPS": round(active / (ms * 1e-3) / 1e6, 1),
@@ -307,12 +333,15 @@ def single_phase_bench(n=1024, steps=2000, warmup=100):
     return out
 
 
-D3Q15_BYTES = 4 * 2 * (14 + 16 + 1 + 3)  # g_1..14, h_0 hi, h_1..14, h_0 lo, p, (phi u): read + written
+# algorithmic bytes per node of the D3Q15 step: g_1..14 (g_0 is never read), h_0..14, p and (phi u),
+# read and written; the kernel also stores the low word of h_0 (272 B)
+D3Q15_BYTES = 4 * 2 * (14 + 15 + 1 + 3)
+D3Q15_STORAGE_BYTES = 4 * 2 * (14 + 16 + 1 + 3)
 
 
 def d3q15_bench(n=256, steps=200, warmup=20):
     """The D3Q15 two-phase step on an n^3 periodic spinodal (QIM, rho ratio 3, M_phi 0.01):
-    MLUPS and the fraction of the HBM roofline at 272 algorithmic bytes per node, launch shape
+    MLUPS and the fraction of the HBM roofline at 264 algorithmic bytes per node, launch shape
     from the library's autotuner."""
     import numpy as np
     import torch
@@ -336,21 +365,55 @@ def d3q15_bench(n=256, steps=200, warmup=20):
     return {"workload": f"spinodal {n}^3 periodic, D3Q15, QIM, rho ratio 3, nu ratio 0.1, sigma 0.03, "
                         "W 4, M_phi 0.01, tau_h 1",
             "steps": steps, "ms_per_step": round(ms, 5), "MLUPS": round(cells / (ms * 1e-3) / 1e6, 1),
-            "bytes_per_node": D3Q15_BYTES, "achieved_GBs": round(gbs, 1),
+            "bytes_per_node": D3Q15_BYTES, "storage_bytes_per_node": D3Q15_STORAGE_BYTES,
+            "achieved_GBs": round(gbs, 1),
             "frac": round(gbs / HBM_PEAK_GBS, 4),
             "launch_shape": {"tx": tx, "ty": ty, "cz": cz, "index": shape, "chosen_by": "autotuner"},
             "traffic": measured_traffic(f"d3q15_{n}", cells, shape, prefix="fused_step3d", sources="d3q15"),
             "sum_phi_final": d["sum_phi"]}
 
 
-def cpu_baseline(cfg, phi, steps):
+def _oracle_steps(args):
+    """one CPU worker: the FP64 oracle on the workload's own grid and field, `steps` steps;
+    returns the seconds the steps took (set-up excluded)"""
+    cfg, phi, steps = args
     import numpy as np
     import oracle
-    o = oracle.Oracle(cfg).init(phi.astype(np.float32).astype(np.float64))
+    o = oracle.Oracle(cfg).init(np.asarray(phi, dtype=np.float32).astype(np.float64))
     t0 = time.perf_counter()
     o.step(steps)
-    dt = time.perf_counter() - t0
-    return cfg["nx"] * cfg["ny"] * steps / dt / 1e6, dt
+    return time.perf_counter() - t0
+
+
+def host_cpu():
+    """CPU model, logical CPUs of the host, and the CPUs this process may run on"""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return model, os.cpu_count(), usable
+
+
+CPU_WORKERS_MAX = 16  # the host share of one GPU
+
+
+def cpu_baseline(cfg, phi, steps, workers):
+    """The FP64 oracle as it stands (one thread per simulation) on the workload: one simulation
+    alone, then `workers` independent copies at once in separate processes (one per core). The
+    all-core rate is workers x cells x steps over the slowest worker's time."""
+    import multiprocessing as mp
+    cells = cfg["nx"] * cfg["ny"]
+    one = _oracle_steps((cfg, phi, steps))
+    ctx = mp.get_context("spawn")  # fresh interpreters: the parent holds a GPU context
+    with ctx.Pool(workers) as pool:
+        times = pool.map(_oracle_steps, [(cfg, phi, steps)] * workers)
+    return cells * steps / one / 1e6, one, workers * cells * steps / max(times) / 1e6, max(times)
 
 
 def main():
@@ -361,9 +424,10 @@ def main():
     ap.add_argument("--workload", default="spinodal1024")
     ap.add_argument("--variant", default="qim")
     ap.add_argument("--tile", type=int, default=None, help="strip shape index (default: library default)")
-    ap.add_argument("--cpu-steps", type=int, default=32)
+    ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-im", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-single-phase", action="store_true")
@@ -384,6 +448,7 @@ def main():
     mlups = cells * args.steps / (ms * 1e-3) / 1e6
     achieved = BYTES_PER_CELL * cells / (ms_per_step * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, cells, tile)
+    vname = {"qim": "QIM", "im": "IM"}[args.variant]
     out = {
         "metric": "D2Q9 two-phase MLUPS, % of HBM roofline; surrogate speedup at fixed error",
         "value": round(mlups, 1),
@@ -398,7 +463,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic: seeded spinodal noise phi = 0.5 + U[-0.005, 0.005]",
         "config": {"workload": f"spinodal decomposition {cfg['nx']}x{cfg['ny']} periodic, "
-                               f"{args.variant.upper()}, rho ratio 3, nu ratio 0.1, sigma 0.03, "
+                               f"{vname}, rho ratio 3, nu_A 0.1, nu_B 1, sigma 0.03, "
                                "W 4, M_phi 0.1, tau_h 1",
                    "nx": cfg["nx"], "ny": cfg["ny"], "variant": args.variant,
                    "strip": {"tx": shape[0], "rows": shape[1], "threads": shape[2], "index": tile,
@@ -407,7 +472,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "bytes_per_cell_update": BYTES_PER_CELL,
+                     "storage_bytes_per_cell_update": STORAGE_BYTES_PER_CELL,
+                     "storage_frac": round(STORAGE_BYTES_PER_CELL * cells / (ms_per_step * 1e-3) / 1e9
+                                           / HBM_PEAK_GBS, 4),
                      "kernel": f"strip_kernel<{shape[0]},{shape[2]},{shape[1]}>",
+                     "footprint_note": "the 1024^2 state (185 MB) fits the 256 MB Infinity Cache; "
+                                       "large_footprint is the HBM-bound figure",
                      "copy_probe_GBs": None},
         "wall_s_timed": round(wall, 4),
         "sum_phi_final": diag["sum_phi"],
@@ -419,13 +489,24 @@ def main():
         lms, _, _, lshape, ltile = time_gpu(lcfg, lphi, lsteps, 20, args.tile)
         lcells = lcfg["nx"] * lcfg["ny"]
         lper = lms / lsteps
+        lfrac = BYTES_PER_CELL * lcells / (lper * 1e-3) / 1e9 / HBM_PEAK_GBS
         out["large_footprint"] = {
-            "workload": "spinodal 4096x4096", "steps": lsteps, "ms_per_step": lper,
+            "workload": f"spinodal 4096x4096 {vname} (2.95 GB of state)", "steps": lsteps, "ms_per_step": lper,
             "strip": {"tx": lshape[0], "rows": lshape[1], "threads": lshape[2], "index": ltile},
             "MLUPS": round(lcells / (lper * 1e-3) / 1e6, 1),
             "achieved_GBs": round(BYTES_PER_CELL * lcells / (lper * 1e-3) / 1e9, 1),
-            "frac": round(BYTES_PER_CELL * lcells / (lper * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "frac": round(lfrac, 4), "bytes_per_cell_update": BYTES_PER_CELL,
+            "gate": {"frac_target": ROOFLINE_GATE, "met": bool(lfrac >= ROOFLINE_GATE)},
             "traffic": measured_traffic("spinodal4096", lcells, ltile)}
+    if not args.no_im and args.workload == "spinodal1024":
+        # the incompressible variant on the same grid and strip shape
+        icfg, iphi = workload(args.workload, "im")
+        ims, _, _, _, _ = time_gpu(icfg, iphi, args.steps, args.warmup, tile)
+        iper = ims / args.steps
+        out["im_variant"] = {"workload": "spinodal 1024x1024 IM", "steps": args.steps, "ms_per_step": iper,
+                             "MLUPS": round(cells / (iper * 1e-3) / 1e6, 1),
+                             "achieved_GBs": round(BYTES_PER_CELL * cells / (iper * 1e-3) / 1e9, 1),
+                             "frac": round(BYTES_PER_CELL * cells / (iper * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     out["roofline"]["copy_probe_GBs"] = round(probe_copy_gbs(), 1)
     if not args.no_batch:
         out["batched"] = batch_bench(args.batch_steps)
@@ -436,11 +517,15 @@ def main():
     if not args.no_d3q15:
         out["d3q15"] = d3q15_bench()
     if not args.no_cpu_baseline:
-        v, dt = cpu_baseline(cfg, phi, args.cpu_steps)
-        out["cpu_baseline"] = {"value": round(v, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-                               "sample": f"{cfg['nx']}x{cfg['ny']} spinodal {args.variant}, "
-                                         f"{args.cpu_steps} steps of the FP64 C oracle "
-                                         f"({dt:.1f} s, one thread)"}
+        model, nproc, usable = host_cpu()
+        workers = max(1, min(CPU_WORKERS_MAX, usable))
+        v1, dt1, vall, dtall = cpu_baseline(cfg, phi, args.cpu_steps, workers)
+        out["cpu_baseline"] = {"value": round(vall, 3), "unit": "MLUPS", "cores": workers, "kind": "oracle",
+                               "sample": f"{cfg['nx']}x{cfg['ny']} spinodal {args.variant}: {workers} "
+                                         f"independent copies of the FP64 C oracle (one thread each), "
+                                         f"{args.cpu_steps} steps each, slowest {dtall:.1f} s",
+                               "single_thread": {"value": round(v1, 3), "seconds": round(dt1, 1)},
+                               "cpu_model": model, "nproc": nproc, "usable_cpus": usable}
     print(json.dumps(out), flush=True)
 
 

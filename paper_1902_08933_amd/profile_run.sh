@@ -77,12 +77,12 @@ if [ "$W" = "d3q15_256" ]; then
     echo "profile: probe WRITE_SIZE" && \
     timeout -s KILL 90 rocprofv3 --pmc WRITE_SIZE -d "$OUT/cwrite" -o run -- $PROBE > "$OUT/cwrite.log" 2>&1 && \
     python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --cells $CELLS \
-        --kernel march3d_kernel --alg-bytes-per-cell 272 --sources d3q15 \
+        --kernel march3d_kernel --alg-bytes-per-cell 264 --storage-bytes-per-cell 272 --sources d3q15 \
         --command "bash paper_1902_08933_amd/profile_run.sh d3q15_256  (trace: rocprofv3 --kernel-trace --stats -- $STEP --steps 50 --warmup 5)" \
         --out "$PROF/fused_step3d_d3q15_256_trace.txt" && \
     python3 -m paper_1902_08933_amd.rocprof_summary --fetch "$OUT/fetch/run_results.db" --write "$OUT/write/run_results.db" \
         --calib-fetch "$OUT/cfetch/run_results.db" --calib-write "$OUT/cwrite/run_results.db" --calib-bytes 1073741824 \
-        --cells $CELLS --kernel march3d_kernel --alg-bytes-per-cell 272 --sources d3q15 \
+        --cells $CELLS --kernel march3d_kernel --alg-bytes-per-cell 264 --storage-bytes-per-cell 272 --sources d3q15 \
         --command "bash paper_1902_08933_amd/profile_run.sh d3q15_256  (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE -- $STEP --steps 5 --warmup 1; calibration: same counters on $PROBE)" \
         --out "$PROF/fused_step3d_d3q15_256_pmc.txt"
     exit $?
@@ -112,12 +112,12 @@ if [ "$W" = "batch256" ]; then
     echo "profile: probe WRITE_SIZE" && \
     timeout -s KILL 90 rocprofv3 --pmc WRITE_SIZE -d "$OUT/cwrite" -o run -- $PROBE > "$OUT/cwrite.log" 2>&1 && \
     python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --cells $CELLS \
-        --kernel batch_kernel --alg-bytes-per-cell 168 --sources step \
+        --kernel batch_kernel --alg-bytes-per-cell 160 --storage-bytes-per-cell 168 --sources step \
         --command "bash paper_1902_08933_amd/profile_run.sh batch256  (trace: rocprofv3 --kernel-trace --stats -- $STEP --steps 40 --warmup 8)" \
         --out "$PROF/batch_step_batch256_trace.txt" && \
     python3 -m paper_1902_08933_amd.rocprof_summary --fetch "$OUT/fetch/run_results.db" --write "$OUT/write/run_results.db" \
         --calib-fetch "$OUT/cfetch/run_results.db" --calib-write "$OUT/cwrite/run_results.db" --calib-bytes 1073741824 \
-        --cells $CELLS --kernel batch_kernel --alg-bytes-per-cell 168 --sources step \
+        --cells $CELLS --kernel batch_kernel --alg-bytes-per-cell 160 --storage-bytes-per-cell 168 --sources step \
         --command "bash paper_1902_08933_amd/profile_run.sh batch256  (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE -- $STEP --steps 5 --warmup 1; calibration: same counters on $PROBE)" \
         --out "$PROF/batch_step_batch256_pmc.txt"
     exit $?
@@ -159,10 +159,10 @@ timeout -s KILL 90 rocprofv3 --pmc FETCH_SIZE -d "$OUT/cfetch" -o run -- $PROBE 
 echo "profile: probe WRITE_SIZE" && \
 timeout -s KILL 90 rocprofv3 --pmc WRITE_SIZE -d "$OUT/cwrite" -o run -- $PROBE > "$OUT/cwrite.log" 2>&1 && \
 python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --cells $CELLS \
-    --command "bash paper_1902_08933_amd/profile_run.sh $W  (trace: rocprofv3 --kernel-trace --stats -- $STEP --steps 100 --warmup 10)" \
+    --alg-bytes-per-cell 160 --storage-bytes-per-cell 168 --command "bash paper_1902_08933_amd/profile_run.sh $W  (trace: rocprofv3 --kernel-trace --stats -- $STEP --steps 100 --warmup 10)" \
     --out "$PROF/fused_step_${W}_trace.txt" && \
 python3 -m paper_1902_08933_amd.rocprof_summary --fetch "$OUT/fetch/run_results.db" --write "$OUT/write/run_results.db" \
     --calib-fetch "$OUT/cfetch/run_results.db" --calib-write "$OUT/cwrite/run_results.db" --calib-bytes 1073741824 \
-    --cells $CELLS \
+    --cells $CELLS --alg-bytes-per-cell 160 --storage-bytes-per-cell 168 \
     --command "bash paper_1902_08933_amd/profile_run.sh $W  (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE -- $STEP --steps 5 --warmup 1; calibration: same counters on $PROBE)" \
     --out "$PROF/fused_step_${W}_pmc.txt"

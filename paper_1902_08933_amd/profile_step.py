@@ -1,9 +1,9 @@
-"""Profiling driver for the fused step (run it under rocprofv3, or alone for a tile sweep).
+"""Profiling driver for the fused step, run under rocprofv3 by profile_run.sh.
 
 python -m paper_1902_08933_amd.profile_step --workload spinodal4096 --steps 20
-python -m paper_1902_08933_amd.profile_step --workload spinodal1024 --sweep
+python -m paper_1902_08933_amd.profile_step --workload spinodal1024 --autotune   (strip shape)
 python -m paper_1902_08933_amd.profile_step --workload r4_1024   (Remark 4 scheme, single phase)
-python -m paper_1902_08933_amd.profile_step --workload d3q15_256 --sweep   (D3Q15 two-phase step)
+python -m paper_1902_08933_amd.profile_step --workload d3q15_256   (D3Q15 two-phase step)
 python -m paper_1902_08933_amd.profile_step --workload batch256 --steps 40   (batched persistent step)
 python -m paper_1902_08933_amd.profile_step --copy-mib 2048 --steps 10   (bandwidth probe:
     copy / read / write of a known byte count, the reference for the HBM roofline and for
@@ -15,7 +15,8 @@ import sys
 
 from . import lbpf, workloads
 
-BYTES_PER_CELL = 168
+BYTES_PER_CELL = 160  # algorithmic bytes per node update of the D2Q9 step
+BATCH_WARMUP = 200    # steps before the unstable batch instances are frozen
 
 
 def make(name, variant):
@@ -50,30 +51,26 @@ def run_sp(torch, n, steps, warmup, remark4=False):
     return e0.elapsed_time(e1) / steps
 
 
-def run_d3q15(torch, n, steps, warmup, shape=None, sweep=False):
-    """D3Q15 spinodal at n^3: the autotuned (or given) launch shape, ms per step; with sweep,
-    every shape"""
+def run_d3q15(torch, n, steps, warmup, shape=None):
+    """D3Q15 spinodal at n^3: the autotuned (or given) launch shape, ms per step"""
     cfg, phi = workloads.spinodal3d(n=n, seed=0)
     sim = lbpf.Simulation3D(cfg).init(torch.from_numpy(phi.astype("float32")).cuda())
-    shapes = range(len(lbpf.shapes3d())) if sweep else [sim.autotune(3) if shape is None else shape]
-    out = []
-    for s in shapes:
-        sim.set_shape(s)
-        sim.step(warmup)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        sim.step(steps)
-        e1.record()
-        torch.cuda.synchronize()
-        out.append((s, e0.elapsed_time(e1) / steps))
-    return out
+    s = sim.autotune(3) if shape is None else shape
+    sim.set_shape(s)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    return s, e0.elapsed_time(e1) / steps
 
 
 def make_batch(torch, count=256, seed=0, tile=None):
-    """the batched workload of the benchmark: seeded instances, 16 steps (at strip shape `tile`
-    when given, so that a profiled run launches one kernel only), unstable ones frozen; returns
-    the batch, its active node count and its total node count"""
+    """the batched workload of the benchmark: seeded instances, the benchmark's warm-up (at strip
+    shape `tile` when given, so that a profiled run launches one kernel only), unstable ones
+    frozen; returns the batch, its active node count and its total node count"""
     import numpy as np
     insts = workloads.batch_instances(count, seed=seed)
     b = lbpf.Batch([c for c, _ in insts])
@@ -81,7 +78,7 @@ def make_batch(torch, count=256, seed=0, tile=None):
         b.set_tile(tile)
     for k, (_, phi) in enumerate(insts):
         b.init(k, torch.from_numpy(np.ascontiguousarray(phi, dtype=np.float32)).cuda())
-    b.step(16)
+    b.step(BATCH_WARMUP)
     flags, _ = b.status()
     active = sum(c["nx"] * c["ny"] for c, f in zip(b.cfgs, flags) if not f)
     total = sum(c["nx"] * c["ny"] for c in b.cfgs)
@@ -127,7 +124,6 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tile", type=int, default=None, help="strip shape (default: library default)")
-    ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="print the strip shape the library's autotuner picks for the workload and exit")
     ap.add_argument("--copy-mib", type=int, default=0)
@@ -159,11 +155,10 @@ def main():
             sim = lbpf.Simulation3D(cfg).init(torch.from_numpy(phi.astype("float32")).cuda())
             print(sim.autotune(3), flush=True)
             return 0
-        shapes = lbpf.shapes3d()
-        for s, ms in run_d3q15(torch, n, a.steps, a.warmup, shape=a.tile, sweep=a.sweep):
-            print(f"{a.workload} shape {s} {shapes[s]}: {ms:.4f} ms/step, "
-                  f"{n ** 3 / (ms * 1e-3) / 1e6:.0f} MLUPS, {272 * n ** 3 / (ms * 1e-3) / 1e9:.0f} GB/s",
-                  flush=True)
+        s, ms = run_d3q15(torch, n, a.steps, a.warmup, shape=a.tile)
+        print(f"{a.workload} shape {s} {lbpf.shapes3d()[s]}: {ms:.4f} ms/step, "
+              f"{n ** 3 / (ms * 1e-3) / 1e6:.0f} MLUPS, {264 * n ** 3 / (ms * 1e-3) / 1e9:.0f} GB/s",
+              flush=True)
         return 0
     if a.workload == "batch256":
         if a.autotune:  # last line: the strip shape and the number of active nodes
@@ -191,14 +186,13 @@ def main():
         best, _ = sim.autotune(trial_steps=20)
         print(best, flush=True)
         return 0
-    tiles = range(len(lbpf.tile_shapes())) if a.sweep else [a.tile]
-    for t in tiles:
-        ms = run_steps(torch, cfg, phi, a.steps, a.warmup, t)
-        gbs = BYTES_PER_CELL * cells / (ms * 1e-3) / 1e9
-        shape = lbpf.tile_shapes()[t] if t is not None else "default"
-        print(f"{a.workload} {a.variant} tile {t} {shape}: {ms:.4f} ms/step, "
-              f"{cells / (ms * 1e-3) / 1e6:.0f} MLUPS, {gbs:.0f} GB/s ({gbs / 80:.1f}% of 8 TB/s)",
-              flush=True)
+    t = a.tile
+    ms = run_steps(torch, cfg, phi, a.steps, a.warmup, t)
+    gbs = BYTES_PER_CELL * cells / (ms * 1e-3) / 1e9
+    shape = lbpf.tile_shapes()[t] if t is not None else "default"
+    print(f"{a.workload} {a.variant} tile {t} {shape}: {ms:.4f} ms/step, "
+          f"{cells / (ms * 1e-3) / 1e6:.0f} MLUPS, {gbs:.0f} GB/s ({gbs / 80:.1f}% of 8 TB/s)",
+          flush=True)
 
 
 if __name__ == "__main__":

@@ -35,6 +35,22 @@ def kernel_source_hash(which="step"):
     return h.hexdigest()[:16]
 
 
+def trace_span(db, key):
+    """(dispatches, first start to last end in ns) of the kernel whose name contains key with the
+    most dispatches: for back-to-back launches the span per launch is the time per launch as
+    events around the whole sequence see it (consecutive dispatches overlap at their ends)"""
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, start, end from kernels").fetchall()
+    by = {}
+    for name, st, en in rows:
+        if key in name:
+            by.setdefault(name, []).append((st, en))
+    if not by:
+        raise SystemExit(f"no kernel matching {key!r}")
+    v = max(by.values(), key=len)
+    return len(v), max(e for _, e in v) - min(s for s, _ in v)
+
+
 def trace_stats(db):
     c = sqlite3.connect(db)
     rows = c.execute("select name, end - start from kernels").fetchall()
@@ -73,7 +89,9 @@ def main():
     ap.add_argument("--calib-bytes", type=int, default=0)
     ap.add_argument("--kernel", default="strip_kernel")
     ap.add_argument("--cells", type=int, default=0)
-    ap.add_argument("--alg-bytes-per-cell", type=float, default=168.0)
+    ap.add_argument("--alg-bytes-per-cell", type=float, default=160.0)
+    ap.add_argument("--storage-bytes-per-cell", type=float, default=0.0,
+                    help="bytes per node the kernel stores and reloads, when above the algorithmic ones")
     ap.add_argument("--iterations", type=int, default=0,
                     help="with --trace: report the summed kernel time per iteration of the program")
     ap.add_argument("--flop", type=float, default=0.0, help="with --iterations: FLOP per iteration")
@@ -101,8 +119,13 @@ def main():
         if a.cells:
             name, (n, tot, avg, med) = pick(trace_stats(a.trace), a.kernel)
             gbs = a.alg_bytes_per_cell * a.cells / (avg * 1e-9) / 1e9
+            n_span, span = trace_span(a.trace, a.kernel)
             lines.append(f"avg_duration_us_{a.kernel}: {avg / 1e3:.3f}")
+            lines.append(f"span_us_per_launch_{a.kernel}: {span / n_span / 1e3:.3f} "
+                         f"(first start to last end over {n_span} back-to-back launches)")
+            lines.append(f"algorithmic_bytes_per_cell: {a.alg_bytes_per_cell:.0f}")
             lines.append(f"algorithmic_GBs_at_avg_duration: {gbs:.1f}")
+            lines.append(f"algorithmic_GBs_at_span: {a.alg_bytes_per_cell * a.cells / (span / n_span * 1e-9) / 1e9:.1f}")
     if a.fetch and a.write:
         fk, fv = pick(pmc_values(a.fetch, "FETCH_SIZE"), a.kernel)
         wk, wv = pick(pmc_values(a.write, "WRITE_SIZE"), a.kernel)
@@ -122,9 +145,10 @@ def main():
                   f"fetch_scale: {fs:.4f}", f"write_scale: {ws:.4f}",
                   f"hbm_bytes_per_launch: {hbm:.6e}"]
         if a.cells:
+            st = f", stored {a.storage_bytes_per_cell:.0f}" if a.storage_bytes_per_cell else ""
             lines.append(f"hbm_bytes_per_cell: {hbm / a.cells:.2f} "
                          f"(read {f_kib * 1024 * fs / a.cells:.2f}, write {w_kib * 1024 * ws / a.cells:.2f}; "
-                         f"algorithmic {a.alg_bytes_per_cell:.0f})")
+                         f"algorithmic {a.alg_bytes_per_cell:.0f}{st})")
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     with open(a.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")

@@ -44,7 +44,7 @@ def main():
         res = pool.map(run, jobs)
     with open(OUT, "w") as fh:
         fh.write("# Spinodal decomposition, 256 x 256 periodic, parameters of the 1024^2 workload\n"
-                 "# (rho ratio 3, nu_A/nu_B = 0.1 with nu_B = 1/6, sigma 0.03, W 4, M_phi 0.1, tau_h 1,\n"
+                 "# (rho ratio 3, nu_A = 0.1, nu_B = 1, sigma 0.03, W 4, M_phi 0.1, tau_h 1,\n"
                  "# F_s = mu grad phi, eq. (28)), phi0 = 0.5 + U[-0.005, 0.005] (numpy PCG64 seed),\n"
                  "# rounded to FP32. FP64 oracle; written by tests/golden/make_spinodal_stats.py.\n"
                  "# columns: variant seed step sum_phi characteristic_length\n")

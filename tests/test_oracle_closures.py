@@ -192,3 +192,20 @@ def test_batch_workload_high_ratio_instance_diverges_in_fp64():
     o = oracle.Oracle(cfg).init(phi)
     assert _steps_to_blow_up(o, 40, chunk=10) is None
     assert math.isfinite(o.sum_phi())
+
+
+def test_spinodal_viscosity_reading_keeps_the_qim_finite():
+    # Sec. 4.1 fixes nu_A / nu_B = 0.1 but not the viscosities. With nu_B = 1/6 (tau_B = 1,
+    # tau_A = 0.55) the quasi-incompressible spinodal (gamma M = 0.2) goes non-finite once the
+    # domains coarsen, after about 6000 steps, in FP64; with nu_B = 1 (tau_B = 3.5, tau_A = 0.8),
+    # the workload's reading, the same run stays finite and slow.
+    def run(nu_B, steps=6500):
+        cfg, phi = W.spinodal(n=64, variant="qim", seed=0, nu_B=nu_B)
+        o = oracle.Oracle(cfg).init(phi.astype(np.float32).astype(np.float64))
+        return _steps_to_blow_up(o, steps, chunk=500, umax=0.5), o
+
+    blown, _ = run(1.0 / 6.0)
+    assert blown is not None and blown > 3000
+    blown, o = run(1.0)
+    assert blown is None
+    assert np.hypot(o.read("ux"), o.read("uy")).max() < 0.05
