@@ -131,6 +131,12 @@ lbpf_status lbpf_read(lbpf_ctx* ctx, int32_t field, float* dst);
  * (with *out filled) when a stored value is not finite. */
 lbpf_status lbpf_diagnostics(lbpf_ctx* ctx, lbpf_diag* out);
 
+/* FP64 statistics of one lbpf_field of the current state over all nodes: out3[0] the mean,
+ * out3[1] the standard deviation about it, out3[2] the largest magnitude. Reduced on the GPU in
+ * a fixed order; synchronizes the stream. (Used to normalize the fields handed to the learned
+ * surrogate; equally a diagnostic of the state.) */
+lbpf_status lbpf_field_stats(lbpf_ctx* ctx, int32_t field, double* out3);
+
 /* Laplace-law pressure jump of Sec. 4.2 in FP64: P = p0 - kappa phi lap(phi)
  * + kappa |grad phi|^2 / 2 + p with p0 = phi psi'(phi) - psi(phi), averaged over nodes with
  * periodic distance r <= R/2 from (xc, yc) minus the average over r >= R + 3W.

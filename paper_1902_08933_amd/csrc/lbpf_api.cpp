@@ -23,6 +23,7 @@ hipError_t launch_step(int tile, const Model& m, const float* in, float* out, hi
 hipError_t launch_fields(const Model& m, const float* in, float* fields, hipStream_t st);
 hipError_t launch_init(const Model& m, const float* phi0, const float* ux0, const float* uy0,
                        const float* p0, float* copy, hipStream_t st);
+hipError_t launch_stats(const Model& m, const float* plane, double* red, hipStream_t st);
 hipError_t launch_diag(const Model& m, const float* copy, const float* fields, double* red,
                        hipStream_t st);
 hipError_t launch_laplace(const Model& m, const float* copy, const float* fields, double* phi64,
@@ -305,6 +306,26 @@ lbpf_status lbpf_diagnostics(lbpf_ctx* c, lbpf_diag* out) {
     if (out->nonfinite != 0 || !std::isfinite(r[0]))
         return fail(c, LBPF_E_UNSTABLE, "%lld non-finite values in the state at step %lld",
                     (long long)out->nonfinite, (long long)c->step);
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_field_stats(lbpf_ctx* c, int32_t field, double* out3) {
+    if (lbpf_status s = check_ctx(c, true)) return s;
+    if (field < LBPF_FIELD_PHI || field > LBPF_FIELD_MU) return fail(c, LBPF_E_INVALID, "unknown field %d", field);
+    if (!out3) return fail(c, LBPF_E_INVALID, "out is NULL");
+    if (lbpf_status s = run_fields(c)) return s;
+    hipError_t e = launch_stats(c->m, fields(c) + (size_t)field * c->m.plane, red(c), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "field statistics kernels");
+    double r[3];
+    e = hipMemcpyAsync(r, red(c) + (size_t)kRedBlocks * kRedSlots, sizeof r, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "field statistics readback");
+    const double n = (double)c->m.nx * (double)c->m.ny;
+    const double mean = r[0] / n;
+    const double var = r[1] / n - mean * mean;
+    out3[0] = mean;
+    out3[1] = var > 0.0 ? std::sqrt(var) : 0.0;
+    out3[2] = r[2];
     return LBPF_OK;
 }
 

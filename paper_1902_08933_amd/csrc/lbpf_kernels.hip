@@ -366,6 +366,29 @@ __global__ __launch_bounds__(256) void diag_partial_kernel(Model m, const float*
     }
 }
 
+// Partials of one evaluated field plane: sum, sum of squares and max |value| over the nodes.
+__global__ __launch_bounds__(256) void stats_partial_kernel(Model m, const float* __restrict__ v,
+                                                            double* __restrict__ part) {
+    __shared__ double sh[4];
+    const long long n = (long long)m.nx * m.ny;
+    double s1 = 0.0, s2 = 0.0, amax = 0.0;
+    for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
+        const int x = (int)(k % m.nx), y = (int)(k / m.nx);
+        const double a = v[(long long)y * m.pitch + x];
+        s1 += a;
+        s2 += a * a;
+        const double b = fabs(a);
+        amax = (b > amax || b != b) ? b : amax;
+    }
+    const double a = block_reduce<256>(s1, sh, false);
+    const double b = block_reduce<256>(s2, sh, false);
+    const double c = block_reduce<256>(amax, sh, true);
+    if (threadIdx.x == 0) {
+        double* o = part + (size_t)blockIdx.x * kRedSlots;
+        o[0] = a; o[1] = b; o[2] = c;
+    }
+}
+
 // Second pass: slot s of every partial reduced by one workgroup in a fixed order.
 // maxmask bit s selects max instead of sum for slot s.
 __global__ __launch_bounds__(256) void reduce_final_kernel(const double* __restrict__ part, int nblk,
@@ -639,6 +662,16 @@ hipError_t launch_diag(const Model& m, const float* copy, const float* fields, d
     if (e != hipSuccess) return e;
     double* out = red + (size_t)kRedBlocks * kRedSlots;
     hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, red, nb, 4, 0x4u, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const Model& m, const float* plane, double* red, hipStream_t st) {
+    const int nb = red_blocks(m);
+    hipLaunchKernelGGL(stats_partial_kernel, dim3(nb), dim3(256), 0, st, m, plane, red);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    double* out = red + (size_t)kRedBlocks * kRedSlots;
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, red, nb, 3, 0x4u, out);
     return hipGetLastError();
 }
 

@@ -55,6 +55,7 @@ SIGNATURES = {
     "lbpf_diagnostics": (_S, [_V, ctypes.POINTER(Diag)]),
     "lbpf_laplace_dp": (_S, [_V, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                              ctypes.POINTER(ctypes.c_double)]),
+    "lbpf_field_stats": (_S, [_V, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "lbpf_state_size": (_S, [_V, ctypes.POINTER(ctypes.c_size_t)]),
     "lbpf_save_state": (_S, [_V, _V]),
     "lbpf_load_state": (_S, [_V, _V]),
@@ -235,6 +236,12 @@ class Simulation:
                                                          device=self.device)
         self._c(self.lib.lbpf_read(self._h, FIELDS[field], _dev_ptr(t, self.torch, (self.ny, self.nx))))
         return t
+
+    def field_stats(self, field):
+        """FP64 mean, standard deviation and largest magnitude of a field (lbpf_field_stats)"""
+        out = (ctypes.c_double * 3)()
+        self._c(self.lib.lbpf_field_stats(self._h, FIELDS[field], out))
+        return {"mean": out[0], "std": out[1], "max_abs": out[2]}
 
     def diagnostics(self, check=True):
         d = Diag()
