@@ -131,6 +131,16 @@ lbpf_status lbpf_read(lbpf_ctx* ctx, int32_t field, float* dst);
  * (with *out filled) when a stored value is not finite. */
 lbpf_status lbpf_diagnostics(lbpf_ctx* ctx, lbpf_diag* out);
 
+/* lbpf_diagnostics for callers that cannot allocate device memory (code under graph capture,
+ * allocation-free serving loops): the same kernels and results, bitwise, but the reduction
+ * partials live in a fixed device array of the library (263 KB per GPU, held until the process
+ * ends) instead of the handle's workspace. Every call on one GPU shares that array and leaves its
+ * contents behind; the partials are rewritten by each call, so nothing needs clearing, and calls
+ * that overlap on one GPU (two streams, two threads) race. Allocates nothing; LBPF_E_NOMEM if the
+ * partials would not fit the array (they always fit: at most 4096 blocks). Synchronizes the
+ * stream. */
+lbpf_status lbpf_diagnostics_noalloc(lbpf_ctx* ctx, lbpf_diag* out);
+
 /* FP64 statistics of one lbpf_field of the current state over all nodes: out3[0] the mean,
  * out3[1] the standard deviation about it, out3[2] the largest magnitude. Reduced on the GPU in
  * a fixed order; synchronizes the stream. (Used to normalize the fields handed to the learned

@@ -24,6 +24,8 @@ hipError_t launch_fields(const Model& m, const float* in, float* fields, hipStre
 hipError_t launch_init(const Model& m, const float* phi0, const float* ux0, const float* uy0,
                        const float* p0, float* copy, hipStream_t st);
 hipError_t launch_stats(const Model& m, const float* plane, double* red, hipStream_t st);
+hipError_t diag_noalloc(const Model& m, const float* copy, const float* fields, hipStream_t st,
+                        double* host4);
 hipError_t launch_diag(const Model& m, const float* copy, const float* fields, double* red,
                        hipStream_t st);
 hipError_t launch_laplace(const Model& m, const float* copy, const float* fields, double* phi64,
@@ -298,6 +300,26 @@ lbpf_status lbpf_diagnostics(lbpf_ctx* c, lbpf_diag* out) {
     e = hipMemcpyAsync(r, red(c) + (size_t)kRedBlocks * kRedSlots, sizeof r, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "diagnostic readback");
+    out->sum_phi = r[0];
+    out->sum_rho = r[1];
+    out->max_u = r[2];
+    out->nonfinite = (int64_t)r[3];
+    out->step = c->step;
+    if (out->nonfinite != 0 || !std::isfinite(r[0]))
+        return fail(c, LBPF_E_UNSTABLE, "%lld non-finite values in the state at step %lld",
+                    (long long)out->nonfinite, (long long)c->step);
+    return LBPF_OK;
+}
+
+lbpf_status lbpf_diagnostics_noalloc(lbpf_ctx* c, lbpf_diag* out) {
+    if (lbpf_status s = check_ctx(c, true)) return s;
+    if (!out) return fail(c, LBPF_E_INVALID, "out is NULL");
+    if (lbpf_status s = run_fields(c)) return s;
+    double r[4];
+    hipError_t e = diag_noalloc(c->m, cur_copy(c), fields(c), c->stream, r);
+    if (e == hipErrorInvalidValue)
+        return fail(c, LBPF_E_NOMEM, "the diagnostic partials exceed the fixed scratch");
+    if (e != hipSuccess) return hip_fail(c, e, "diagnostic kernels (fixed scratch)");
     out->sum_phi = r[0];
     out->sum_rho = r[1];
     out->max_u = r[2];

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "lbpf_cell.hpp"
 #include "lbpf_model.hpp"
@@ -673,6 +674,60 @@ hipError_t launch_stats(const Model& m, const float* plane, double* red, hipStre
     double* out = red + (size_t)kRedBlocks * kRedSlots;
     hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, red, nb, 3, 0x4u, out);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Reduction scratch that needs no allocation: a fixed device array (one copy per GPU, alive
+// until the process ends) for callers that cannot allocate device memory. Host code never passes
+// the array's name to a kernel: on each device it takes the array's device address once with
+// hipGetSymbolAddress (that device current) and passes that address.
+// ---------------------------------------------------------------------------------------------
+constexpr size_t kNoallocDoubles = (size_t)kRedBlocks * kRedSlots + 64;  // 263 KB
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static double* g_scratch_ptr[kMaxDevices];
+
+static hipError_t scratch_on_current_device(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// Diagnostics (as launch_diag) with the partial sums in the fixed scratch of the current device;
+// copies the four results to host and synchronizes the stream. Returns hipErrorInvalidValue when
+// the partials would not fit the scratch (never for the block counts red_blocks() gives).
+hipError_t diag_noalloc(const Model& m, const float* copy, const float* fields, hipStream_t st,
+                        double* host4) {
+    double* red = nullptr;
+    hipError_t e = scratch_on_current_device(&red);
+    if (e != hipSuccess) return e;
+    const int nb = red_blocks(m);
+    if ((size_t)nb * kRedSlots + 4 > kNoallocDoubles) return hipErrorInvalidValue;
+    const long long P = m.plane;
+    // every partial the final pass reads is written by this launch: nothing to clear first
+    hipLaunchKernelGGL(diag_partial_kernel, dim3(nb), dim3(256), 0, st, m, copy + kCopyF * P,
+                       copy + kCopyH * P, copy + kCopyP * P, copy + kCopyPhiU * P, fields, red);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    double* out = red + (size_t)kRedBlocks * kRedSlots;
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, red, nb, 4, 0x4u, out);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(host4, out, 4 * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
 }
 
 hipError_t launch_laplace(const Model& m, const float* copy, const float* fields, double* phi64,

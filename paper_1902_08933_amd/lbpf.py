@@ -56,6 +56,7 @@ SIGNATURES = {
     "lbpf_laplace_dp": (_S, [_V, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                              ctypes.POINTER(ctypes.c_double)]),
     "lbpf_field_stats": (_S, [_V, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "lbpf_diagnostics_noalloc": (_S, [_V, ctypes.POINTER(Diag)]),
     "lbpf_state_size": (_S, [_V, ctypes.POINTER(ctypes.c_size_t)]),
     "lbpf_save_state": (_S, [_V, _V]),
     "lbpf_load_state": (_S, [_V, _V]),
