@@ -471,7 +471,8 @@ static const StripShape kStrips[] = {
     {64, 256, 4, 0},   {64, 256, 16, 0},  {64, 256, 64, 0},  {128, 256, 64, 0}, {128, 256, 16, 0},
     {64, 256, 16, 1},  {64, 256, 64, 1},  {128, 256, 64, 1}, {64, 512, 64, 1},  {32, 128, 32, 0},
     {64, 128, 32, 0},  {256, 512, 64, 0}, {64, 512, 32, 1},  {64, 512, 16, 1},  {128, 512, 32, 1},
-    {256, 512, 32, 1}, {256, 512, 16, 1}, {128, 256, 32, 1}};
+    {256, 512, 32, 1}, {256, 512, 16, 1}, {128, 256, 32, 1}, {256, 512, 64, 1}, {256, 512, 128, 1},
+    {128, 512, 64, 1}};
 constexpr int kNumStrips = sizeof(kStrips) / sizeof(kStrips[0]);
 
 int tile_count() { return kNumStrips; }
@@ -512,7 +513,10 @@ static hipError_t launch_strip_t(const Model& m, const float* fin, float* fout, 
     case 14: return launch_strip_t<128, 512, 32, true, C>(LBPF_ARGS);       \
     case 15: return launch_strip_t<256, 512, 32, true, C>(LBPF_ARGS);       \
     case 16: return launch_strip_t<256, 512, 16, true, C>(LBPF_ARGS);       \
-    case 17: return launch_strip_t<128, 256, 32, true, C>(LBPF_ARGS);
+    case 17: return launch_strip_t<128, 256, 32, true, C>(LBPF_ARGS);       \
+    case 18: return launch_strip_t<256, 512, 64, true, C>(LBPF_ARGS);       \
+    case 19: return launch_strip_t<256, 512, 128, true, C>(LBPF_ARGS);      \
+    case 20: return launch_strip_t<128, 512, 64, true, C>(LBPF_ARGS);
 
 template <bool C>
 static hipError_t launch_fused(int tile, const Model& m, const float* fin, float* fout,
@@ -602,6 +606,9 @@ hipError_t batch_kernel_info(int tile, void** fn, int* nt, int* tx, int* ch, int
         case 15: *fn = batch_fn<256, 512, 32, true>(); break;
         case 16: *fn = batch_fn<256, 512, 16, true>(); break;
         case 17: *fn = batch_fn<128, 256, 32, true>(); break;
+        case 18: *fn = batch_fn<256, 512, 64, true>(); break;
+        case 19: *fn = batch_fn<256, 512, 128, true>(); break;
+        case 20: *fn = batch_fn<128, 512, 64, true>(); break;
         default: return hipErrorInvalidValue;
     }
     *tx = kStrips[tile].tx;
