@@ -110,7 +110,6 @@ def probe_copy_gbs(mib=2048, reps=10):
     return best
 
 
-BATCH_WARMUP = 200  # steps before freezing: the unstable instances diverge within ~40 (FP64 too)
 
 
 def batch_bench(steps, count=256, seed=0):
@@ -123,13 +122,13 @@ def batch_bench(steps, count=256, seed=0):
     import torch
     from paper_1902_08933_amd import lbpf
     from paper_1902_08933_amd import workloads as W
+    from paper_1902_08933_amd.profile_step import BATCH_WARMUP, warm_up_batch
     insts = W.batch_instances(count, seed=seed)
     b = lbpf.Batch([c for c, _ in insts])
     for k, (_, phi) in enumerate(insts):
         b.init(k, torch.from_numpy(np.ascontiguousarray(phi, dtype=np.float32)).cuda())
     del insts
-    b.step(BATCH_WARMUP)
-    flags, _ = b.status()     # freezes the instances that went unstable
+    flags = warm_up_batch(b)  # freezes the instances that went unstable
     frozen_warm = int(sum(flags))
     b.autotune(trial_steps=8)  # strip shape for the active instances
     total = sum(c["nx"] * c["ny"] for c in b.cfgs)
@@ -388,6 +387,57 @@ def d3q15_bench(n=256, steps=200, warmup=20):
             "sum_phi_final": d["sum_phi"]}
 
 
+def _timed_steps(sim, steps):
+    """ms per step of `steps` steps between HIP events on torch's current stream"""
+    import torch
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def paper_workloads_bench():
+    """The paper's other D2Q9 workloads at their full sizes, each with the library's default strip
+    shape: the static droplet (64^2, Sec. 4.2; Laplace's law after 6000 steps), the layered channel
+    (256 x 128, walls, Sec. 4.3) and the rising bubble (512 x 2048, walls, Sec. 4.4) at density
+    ratio 10, where the method stays finite (at the workload's ratio 1000 it does not). Small
+    grids are launch-bound, so their MLUPS are not roofline figures."""
+    import numpy as np
+    import torch
+    from paper_1902_08933_amd import lbpf, workloads as W
+
+    def make(cfg, phi):
+        return lbpf.Simulation(cfg).init(torch.from_numpy(phi.astype(np.float32)).cuda())
+
+    out = {}
+    for variant in ("qim", "im"):
+        cfg, phi = W.static_droplet(n=64, R=16.0, variant=variant)
+        sim = make(cfg, phi)
+        ms = _timed_steps(sim, 6000)
+        dp = sim.laplace_dp(32.0, 32.0, 16.0)
+        out[f"static_droplet_64_{variant}"] = {
+            "steps": 6000, "ms_per_step": round(ms, 5), "MLUPS": round(64 * 64 / (ms * 1e-3) / 1e6, 1),
+            "laplace_dP_over_sigma_by_R_minus_1": round(dp / (cfg["sigma"] / 16.0) - 1.0, 5)}
+    cfg, phi = W.layered_poiseuille()
+    sim = make(cfg, phi)
+    ms = _timed_steps(sim, 20000)
+    out["layered_poiseuille_256x128"] = {"steps": 20000, "ms_per_step": round(ms, 5),
+                                         "MLUPS": round(256 * 128 / (ms * 1e-3) / 1e6, 1)}
+    cfg, phi = W.rising_bubble(nx=512, ny=2048, R=64.0, rho_ratio=10.0)
+    sim = make(cfg, phi)
+    sim.step(100)
+    ms = _timed_steps(sim, 4000)
+    d = sim.diagnostics(check=False)
+    out["rising_bubble_512x2048_ratio10"] = {
+        "steps": 4000, "ms_per_step": round(ms, 5), "MLUPS": round(512 * 2048 / (ms * 1e-3) / 1e6, 1),
+        "finite": d["nonfinite"] == 0,
+        "achieved_GBs": round(BYTES_PER_CELL * 512 * 2048 / (ms * 1e-3) / 1e9, 1)}
+    return out
+
+
 def _oracle_steps(args):
     """one CPU worker: the FP64 oracle on the workload's own grid and field, `steps` steps;
     returns the seconds the steps took (set-up excluded)"""
@@ -447,6 +497,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-single-phase", action="store_true")
     ap.add_argument("--no-d3q15", action="store_true")
+    ap.add_argument("--no-paper-workloads", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=80)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -531,6 +582,8 @@ def main():
         out["single_phase"] = single_phase_bench()
     if not args.no_d3q15:
         out["d3q15"] = d3q15_bench()
+    if not args.no_paper_workloads:
+        out["paper_workloads"] = paper_workloads_bench()
     if not args.no_cpu_baseline:
         model, nproc, usable = host_cpu()
         workers = max(1, min(CPU_WORKERS_MAX, usable))

@@ -88,10 +88,10 @@ if [ "$W" = "d3q15_256" ]; then
     exit $?
 fi
 if [ "$W" = "batch256" ]; then
-    # batched persistent step over the 256 seeded instances (the ones frozen after the warm-up
-    # leave the work list; the node count is that of the active ones): autotuned strip shape,
-    # kernel trace, then HBM traffic (FETCH_SIZE, WRITE_SIZE, scaled by the same counters on the
-    # copy probe)
+    # batched persistent step over the 256 seeded instances (the ones frozen after the 200-step
+    # warm-up leave the work list; the node count is that of the active ones, and the summaries
+    # count only the launches after the warm-up): autotuned strip shape, kernel trace, then HBM
+    # traffic (FETCH_SIZE, WRITE_SIZE, scaled by the same counters on the copy probe)
     OUT=$RAW/prof_batch256
     PROF=${PROFILE_OUT:-profiles}
     mkdir -p "$OUT" "$PROF"
@@ -112,13 +112,13 @@ if [ "$W" = "batch256" ]; then
     echo "profile: probe WRITE_SIZE" && \
     timeout -s KILL 90 rocprofv3 --pmc WRITE_SIZE -d "$OUT/cwrite" -o run -- $PROBE > "$OUT/cwrite.log" 2>&1 && \
     python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --cells $CELLS \
-        --kernel batch_kernel --alg-bytes-per-cell 160 --storage-bytes-per-cell 168 --sources step \
-        --command "bash paper_1902_08933_amd/profile_run.sh batch256  (trace: rocprofv3 --kernel-trace --stats -- $STEP --steps 40 --warmup 8)" \
+        --kernel batch_kernel --alg-bytes-per-cell 160 --storage-bytes-per-cell 168 --sources step --last 40 \
+        --command "bash paper_1902_08933_amd/profile_run.sh batch256  (trace: rocprofv3 --kernel-trace --stats -- $STEP --steps 40 --warmup 8; the last 40 launches counted)" \
         --out "$PROF/batch_step_batch256_trace.txt" && \
     python3 -m paper_1902_08933_amd.rocprof_summary --fetch "$OUT/fetch/run_results.db" --write "$OUT/write/run_results.db" \
         --calib-fetch "$OUT/cfetch/run_results.db" --calib-write "$OUT/cwrite/run_results.db" --calib-bytes 1073741824 \
-        --cells $CELLS --kernel batch_kernel --alg-bytes-per-cell 160 --storage-bytes-per-cell 168 --sources step \
-        --command "bash paper_1902_08933_amd/profile_run.sh batch256  (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE -- $STEP --steps 5 --warmup 1; calibration: same counters on $PROBE)" \
+        --cells $CELLS --kernel batch_kernel --alg-bytes-per-cell 160 --storage-bytes-per-cell 168 --sources step --last 5 \
+        --command "bash paper_1902_08933_amd/profile_run.sh batch256  (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE -- $STEP --steps 5 --warmup 1, the last 5 launches counted; calibration: same counters on $PROBE)" \
         --out "$PROF/batch_step_batch256_pmc.txt"
     exit $?
 fi

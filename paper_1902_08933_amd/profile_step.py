@@ -16,7 +16,19 @@ import sys
 from . import lbpf, workloads
 
 BYTES_PER_CELL = 160  # algorithmic bytes per node update of the D2Q9 step
-BATCH_WARMUP = 200    # steps before the unstable batch instances are frozen
+BATCH_WARMUP = 1000   # warm-up of the batch, in stretches of BATCH_CHECK steps
+BATCH_CHECK = 200     # the instances that went non-finite are frozen after each stretch
+
+
+def warm_up_batch(b, steps=BATCH_WARMUP, every=BATCH_CHECK):
+    """Advance the batch `steps` steps, freezing the instances that went non-finite after every
+    `every` steps (the unstable ones, the largest density ratios, diverge at different times, the
+    last ones after several hundred steps); returns the frozen flags."""
+    flags = None
+    for _ in range(max(1, steps // every)):
+        b.step(every)
+        flags, _ = b.status()
+    return flags
 
 
 def make(name, variant):
@@ -78,8 +90,7 @@ def make_batch(torch, count=256, seed=0, tile=None):
         b.set_tile(tile)
     for k, (_, phi) in enumerate(insts):
         b.init(k, torch.from_numpy(np.ascontiguousarray(phi, dtype=np.float32)).cuda())
-    b.step(BATCH_WARMUP)
-    flags, _ = b.status()
+    flags = warm_up_batch(b)
     active = sum(c["nx"] * c["ny"] for c, f in zip(b.cfgs, flags) if not f)
     total = sum(c["nx"] * c["ny"] for c in b.cfgs)
     return b, active, total

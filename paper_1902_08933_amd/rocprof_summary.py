@@ -35,12 +35,13 @@ def kernel_source_hash(which="step"):
     return h.hexdigest()[:16]
 
 
-def trace_span(db, key):
+def trace_span(db, key, last=0):
     """(dispatches, first start to last end in ns) of the kernel whose name contains key with the
-    most dispatches: for back-to-back launches the span per launch is the time per launch as
-    events around the whole sequence see it (consecutive dispatches overlap at their ends)"""
+    most dispatches (with last > 0: its last `last` dispatches): for back-to-back launches the span
+    per launch is the time per launch as events around the whole sequence see it (consecutive
+    dispatches overlap at their ends)"""
     c = sqlite3.connect(db)
-    rows = c.execute("select name, start, end from kernels").fetchall()
+    rows = c.execute("select name, start, end from kernels order by start").fetchall()
     by = {}
     for name, st, en in rows:
         if key in name:
@@ -48,22 +49,31 @@ def trace_span(db, key):
     if not by:
         raise SystemExit(f"no kernel matching {key!r}")
     v = max(by.values(), key=len)
+    if last:
+        v = v[-last:]
     return len(v), max(e for _, e in v) - min(s for s, _ in v)
 
 
-def trace_stats(db):
+def trace_stats(db, key=None, last=0):
+    """per kernel name: (dispatches, total, mean, median) of the durations in ns; with key and
+    last > 0, the kernels whose name contains key keep only their last `last` dispatches"""
     c = sqlite3.connect(db)
-    rows = c.execute("select name, end - start from kernels").fetchall()
+    rows = c.execute("select name, end - start from kernels order by start").fetchall()
     out = {}
     for name, d in rows:
         out.setdefault(name, []).append(d)
+    if key and last:
+        out = {k: (v[-last:] if key in k else v) for k, v in out.items()}
     return {k: (len(v), sum(v), statistics.mean(v), statistics.median(v)) for k, v in out.items()}
 
 
 def pmc_values(db, counter):
+    """per kernel name: the counter's value per dispatch, in dispatch order"""
     c = sqlite3.connect(db)
-    rows = c.execute("select kernel_name, value from counters_collection where counter_name = ?",
-                     (counter,)).fetchall()
+    cols = {r[1] for r in c.execute("pragma table_info(counters_collection)").fetchall()}
+    order = next((k for k in ("dispatch_id", "correlation_id", "start") if k in cols), "rowid")
+    rows = c.execute("select kernel_name, value from counters_collection where counter_name = ? "
+                     f"order by {order}", (counter,)).fetchall()
     out = {}
     for name, v in rows:
         out.setdefault(name, []).append(v)
@@ -97,6 +107,9 @@ def main():
     ap.add_argument("--flop", type=float, default=0.0, help="with --iterations: FLOP per iteration")
     ap.add_argument("--sources", default="step", choices=sorted(KERNEL_FILES),
                     help="which kernel sources the summary's hash covers")
+    ap.add_argument("--last", type=int, default=0,
+                    help="count only the last N dispatches of --kernel (the timed ones, after a "
+                         "warm-up whose launches differ)")
     ap.add_argument("--command", default="")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
@@ -108,18 +121,21 @@ def main():
         lines.append("")
         lines.append("## kernel trace (durations in microseconds)")
         lines.append(f"{'calls':>6} {'total_us':>12} {'avg_us':>10} {'median_us':>10}  kernel")
-        for k, (n, tot, avg, med) in sorted(trace_stats(a.trace).items(), key=lambda kv: -kv[1][1]):
+        stats = trace_stats(a.trace, a.kernel, a.last)
+        for k, (n, tot, avg, med) in sorted(stats.items(), key=lambda kv: -kv[1][1]):
             lines.append(f"{n:6d} {tot / 1e3:12.1f} {avg / 1e3:10.3f} {med / 1e3:10.3f}  {k[:110]}")
         if a.iterations:
-            total = sum(v[1] for v in trace_stats(a.trace).values()) / a.iterations
+            total = sum(v[1] for v in stats.values()) / a.iterations
             lines.append(f"total_kernel_us_per_iteration: {total / 1e3:.3f}")
             if a.flop:
                 lines.append(f"flop_per_iteration: {a.flop:.6e}")
                 lines.append(f"TFLOPs_at_total: {a.flop / (total * 1e-9) / 1e12:.1f}")
         if a.cells:
-            name, (n, tot, avg, med) = pick(trace_stats(a.trace), a.kernel)
+            name, (n, tot, avg, med) = pick(stats, a.kernel)
             gbs = a.alg_bytes_per_cell * a.cells / (avg * 1e-9) / 1e9
-            n_span, span = trace_span(a.trace, a.kernel)
+            n_span, span = trace_span(a.trace, a.kernel, a.last)
+            if a.last:
+                lines.append(f"counted: the last {a.last} dispatches of {a.kernel}")
             lines.append(f"avg_duration_us_{a.kernel}: {avg / 1e3:.3f}")
             lines.append(f"span_us_per_launch_{a.kernel}: {span / n_span / 1e3:.3f} "
                          f"(first start to last end over {n_span} back-to-back launches)")
@@ -129,6 +145,8 @@ def main():
     if a.fetch and a.write:
         fk, fv = pick(pmc_values(a.fetch, "FETCH_SIZE"), a.kernel)
         wk, wv = pick(pmc_values(a.write, "WRITE_SIZE"), a.kernel)
+        if a.last:
+            fv, wv = fv[-a.last:], wv[-a.last:]
         f_kib, w_kib = statistics.median(fv), statistics.median(wv)
         fs = ws = 1.0
         if a.calib_fetch and a.calib_write and a.calib_bytes:
