@@ -22,6 +22,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 
 SOURCES = ["lbpf_kernels.hip", "lbpf_api.cpp", "lbpf_unet_kernels.hip", "lbpf_unet.cpp", "lbpf_sp.hip",
            "lbpf_d3q15.hip"]
+# Per-source device flags. The MFMA kernels keep their accumulators in VGPRs (the VGPR form of
+# the MFMA instructions): otherwise the compiler holds loop-carried accumulators in VGPRs and
+# copies them to AGPRs and back around every MFMA block.
+SOURCE_FLAGS = {"lbpf_unet_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _run(cmd, verbose):
@@ -36,7 +40,7 @@ def build(verbose=False, jobs=None):
     procs = []
     for src in SOURCES:
         obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + COMMON + DEVICE_FLAGS + SOURCE_FLAGS.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd), src))

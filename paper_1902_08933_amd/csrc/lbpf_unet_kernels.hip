@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 
 #include "lbpf_unet_ops.hpp"
 
@@ -410,6 +411,402 @@ __global__ __launch_bounds__(256, (COT <= 32 && !PFW ? 3 : 2)) void conv_tile_ke
 
     __syncthreads();  // LDS is reused for the output tile
     conv_epilogue<RELU, COT, MF>(a, acc, conv_lds, tx0, ty0, n, co0);
+}
+
+// 3x3 convolution in wave-row form, for Cin, Cl and Cout multiples of 32. Persistent
+// workgroups of 4 waves walk work items (an image tile of 16 rows x 16 PX columns and 32 CG
+// output channels, PX = 4 / CG) in XCD bands: workgroup b runs on XCD b % 8 and takes items of
+// the band of that XCD, so that neighbouring tiles, which share halo pixels, share an L2.
+// Wave w owns 16 rows x 16 columns (column block w / CG) of the item for 32 output channels
+// (group w % CG); the image is at least one patch in size (H >= 18, W >= 16 PX + 2), so patch
+// coordinates wrap by at most one period. Per chunk of 32 input channels (one step of the pipeline):
+//  - the chunk's weights of the wave's 32 channels for all 9 taps sit in registers (18 MFMA
+//    operands); once a column of taps is done its registers take the next step's weights;
+//  - the input patch (18 rows x 16 PX + 2 columns, circular) is in LDS, double-buffered; its
+//    pieces are loaded into registers between the MFMAs of the previous step and stored at
+//    the start of the step;
+//  - the wave reads each patch row once per horizontal tap dx and applies it to the up to three
+//    output rows it reaches (vertical taps), two 16-channel MFMAs each: 54 fragment reads for
+//    288 MFMAs (16x16x32) per chunk.
+// The MFMA computes D = weights (16 channels x 32 K) x patch (32 K x 16 pixels), so lane
+// j + 16 q of an accumulator holds channels 4q .. 4q+3 of pixel j: the epilogue (bias, ReLU,
+// bf16, the 2x2 pool by a lane swap, FP32 copy, prediction) stores from registers, and the
+// fused 1x1 head is one more MFMA whose operand is the wave's own bf16 outputs. One wave per
+// SIMD: a wave holds 512 registers (accumulators 128, weights 72), so nothing is spilled.
+// LDS: pixel p of the patch (row-major, PCOL columns) takes 64 bytes; its 16-byte piece k holds
+// the chunk's channels 8 (k ^ ((col >> 1) & 3)) .. +7, col = p % PCOL. The swizzle puts any 8
+// consecutive pixels' pieces of one channel group on 8 different 4-bank groups, so the
+// fragment reads (16 consecutive pixels of a row) are conflict-free without padding; each store
+// of staged pieces writes 64 consecutive ones.
+constexpr int kWvRows = 16;
+constexpr int kWaveMaxCout = 512;  // output channels of the wave-row kernel at most
+
+template <int CG>
+struct WaveConvGeom {
+    static constexpr int PX = 4 / CG;                 // 16-column blocks of a work item
+    static constexpr int PCOL = 16 * PX + 2;          // patch columns, with the halo
+    static constexpr int PROWS = kWvRows + 2;         // patch rows
+    static constexpr int NPIECE = PROWS * PCOL * 4;   // 16-byte pieces of one chunk's patch
+    static constexpr int NBW = (NPIECE + 255) / 256;  // 64-piece load blocks per wave (one
+                                                      // instruction each, every wave the same)
+    static constexpr int BUF_BYTES = NBW * 4 * 1024;  // a patch buffer, padded to whole blocks
+    static constexpr int LDS_BYTES = 2 * BUF_BYTES + kWaveMaxCout * 4;  // two buffers, the bias
+};
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// two FP32 values as packed bf16 (round to nearest even, one instruction)
+__device__ __forceinline__ uint32_t pack_bf2(float x, float y) {
+    const bf16x2_t v = {(__bf16)x, (__bf16)y};
+    return __builtin_bit_cast(uint32_t, v);
+}
+// the two bf16 halves of a packed pair as FP32
+__device__ __forceinline__ float bf_lo(uint32_t v) { return __uint_as_float(v << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t v) { return __uint_as_float(v & 0xffff0000u); }
+// value of lane l ^ 1
+__device__ __forceinline__ float swap_lane_pair(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+// v mod m for v in [-m, 2m)
+__device__ __forceinline__ int wrap_near(int v, int m) {
+    return v < 0 ? v + m : (v >= m ? v - m : v);
+}
+
+// Outputs of the wave-row kernel, fixed at compile time to keep the code of each variant small:
+// any of ConvArgs' outputs (checked at run time), y only, y and its pool, or the fused head
+// with a 4-field prediction.
+enum WaveOut { kOutAny = 0, kOutY = 1, kOutYPool = 2, kOutHead = 3 };
+
+template <int CG, bool RELU, int OUT>
+__global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, int total_items) {
+    using G = WaveConvGeom<CG>;
+    constexpr int PX = G::PX, PCOL = G::PCOL, NPIECE = G::NPIECE, NBW = G::NBW, R = kWvRows;
+    extern __shared__ __attribute__((aligned(16))) uint8_t wconv_lds[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int jl = lane & 15, q = lane >> 4;
+    const int cg = wave % CG, pxb = wave / CG;
+    const int H = a.H, W = a.W, Cin = a.Cin, Cl = a.Cl, Cout = a.Cout;
+    const int Hl = H >> 1, Wl = W >> 1;
+    const int tiles_x = (W + 16 * PX - 1) / (16 * PX), tiles_y = (H + R - 1) / R;
+    const int groups = Cout / (32 * CG);
+    // the band of work items of this workgroup's XCD (the grid has at least 8 workgroups)
+    const int nwg = gridDim.x, xcd = blockIdx.x % 8, loc = blockIdx.x / 8;
+    const int nloc = (nwg - xcd + 7) / 8;
+    const int band1 = (int)((long long)total_items * (xcd + 1) / 8);
+    int item = (int)((long long)total_items * xcd / 8) + loc;
+    if (item >= band1) return;
+    // the bias of every output channel, behind the two patch buffers (the first barrier
+    // publishes it)
+    float* s_bias = reinterpret_cast<float*>(wconv_lds + 2 * G::BUF_BYTES);
+
+    // origin of the item whose patch is being loaded
+    int l_n = 0, l_ty0 = 0, l_tx0 = 0;
+    auto plan_loads = [&](int it) __attribute__((always_inline)) {
+        int t = it / groups;
+        l_tx0 = (t % tiles_x) * 16 * PX;
+        t /= tiles_x;
+        l_ty0 = (t % tiles_y) * R;
+        l_n = t / tiles_y;
+    };
+    // the lane's piece of load block i: patch row and column, and the channel group its LDS slot
+    // holds (pieces of the padding past the patch take its last pixel; nothing reads them)
+    auto piece = [&](int i, int& prow, int& col, int& gg) __attribute__((always_inline)) {
+        // recomputed at every use: hoisted out of the loop, these values for every block would
+        // take registers the MFMA loop needs (the empty asm hides that they do not change)
+        const int s = (4 * i + wave) * 64 + lane;
+        const int p = (s < NPIECE ? s : NPIECE - 1) >> 2;
+        prow = p / PCOL;
+        col = p - prow * PCOL;
+        gg = (s & 3) ^ ((col >> 1) & 3);
+    };
+    // piece block i of chunk kc into the staging registers: a uniform base (the chunk's first
+    // channel at the patch corner) and a 32-bit per-lane byte offset
+    short8_t stage[NBW];
+    auto issue_block = [&](int i, int kc) __attribute__((always_inline)) {
+        int prow, col, gg;
+        piece(i, prow, col, gg);
+        const int yy = wrap_near(l_ty0 + prow - 1, H), xx = wrap_near(l_tx0 + col - 1, W);
+        const char* src;
+        if (kc < Cl)
+            src = reinterpret_cast<const char*>(a.xl + a.xlo + kc) +
+                  (unsigned)((((l_n * Hl + (yy >> 1)) * Wl + (xx >> 1)) * a.xls + 8 * gg) * 2);
+        else
+            src = reinterpret_cast<const char*>(a.x + a.xo + (kc - Cl)) +
+                  (unsigned)((((l_n * H + yy) * W + xx) * a.xs + 8 * gg) * 2);
+        stage[i] = *reinterpret_cast<const short8_t*>(src);
+    };
+    // the staged pieces into LDS buffer buf: block i of this wave is 64 consecutive pieces
+    auto publish = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < NBW; ++i)
+            *reinterpret_cast<short8_t*>(wconv_lds + buf * G::BUF_BYTES + (4 * i + wave) * 1024 + lane * 16) = stage[i];
+    };
+    // A operands of the three taps (0, dx), (1, dx), (2, dx): lane jl + 16 q holds
+    // w[co][tap][kc + 8q .. +7] of channel co = base + 16 jj + jl (a uniform base and one per-lane
+    // byte offset)
+    const unsigned woff = (unsigned)((jl * 9 * Cin + 8 * q) * 2);
+    auto load_w = [&](int it, int kc, int dx, short8_t (&wr)[9][2]) __attribute__((always_inline)) {
+        const bf16* wb = a.w + ((it % groups) * 32 * CG + 32 * cg) * 9 * Cin + kc;
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj)
+                wr[3 * dy + dx][jj] = *reinterpret_cast<const short8_t*>(
+                    reinterpret_cast<const char*>(wb + (16 * jj * 9 + 3 * dy + dx) * Cin) + woff);
+    };
+    // B operands: lane jl + 16 q reads pixel column 16 pxb + jl + dx of a patch row, channels
+    // 8q .. 8q+7 of the chunk
+    int boff[3];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+        const int col = 16 * pxb + jl + dx;
+        boff[dx] = col * 64 + 16 * (q ^ ((col >> 1) & 3));
+    }
+
+    float4_t acc[R][2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = float4_t{0.f, 0.f, 0.f, 0.f};
+
+    // ---- epilogue of a finished item, one output row at a time -------------------------------
+    int e_n = 0, e_ty0 = 0, e_xx = 0, e_cb = 0;
+    bool e_xin = false;
+    float e_bias[2][4];
+    auto begin_item_out = [&](int it) __attribute__((always_inline)) {
+        const int cgp = it % groups;
+        int t = it / groups;
+        const int tx = t % tiles_x;
+        t /= tiles_x;
+        e_ty0 = (t % tiles_y) * R;
+        e_n = t / tiles_y;
+        e_xx = tx * 16 * PX + 16 * pxb + jl;
+        e_cb = cgp * 32 * CG + 32 * cg;
+        e_xin = e_xx < W;
+    };
+    // the bias of the item's channels, from its copy in LDS
+    auto load_bias = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            const float4 b = *reinterpret_cast<const float4*>(s_bias + e_cb + 16 * jj + 4 * q);
+            e_bias[jj][0] = b.x, e_bias[jj][1] = b.y, e_bias[jj][2] = b.z, e_bias[jj][3] = b.w;
+        }
+    };
+    // the fused head's A operand: lane c + 16 g holds hw[c][ch(g, e)], ch(g, e) = 4g + e for
+    // e < 4 and 16 + 4g + e - 4 otherwise, the channel order of the bf16 outputs in a lane's B
+    // operand (channels 4g .. 4g+3 of both 16-channel halves); and the head's bias
+    short8_t head_a = {0, 0, 0, 0, 0, 0, 0, 0};
+    float head_b[4] = {0.f, 0.f, 0.f, 0.f};
+    if (CG == 1 && (OUT == kOutHead || (OUT == kOutAny && a.hw))) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int ch = e < 4 ? 4 * q + e : 16 + 4 * q + e - 4;
+            if (jl < a.rc) head_a[e] = (short)a.hw[jl * Cout + ch];
+        }
+        // with 4 outputs every lane adds them (rows are spread over the lanes, below)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = (OUT == kOutHead || a.rc == 4) ? e : 4 * q + e;
+            if (a.hb && c < a.rc) head_b[e] = a.hb[c];
+        }
+    }
+    uint32_t prev_bf[2][2];  // bf16 outputs of the previous (even) row, for the pool
+    auto epi_row = [&](int r, const float4& res_row) __attribute__((always_inline)) {
+        const int yy = e_ty0 + r;
+        const bool in = yy < H && e_xin;
+        const int pix = (e_n * H + yy) * W + e_xx;
+        float v[2][4];
+        uint32_t vb[2][2];
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float x = acc[r][jj][e] + e_bias[jj][e];
+                if (RELU) x = fmaxf(x, 0.0f);
+                v[jj][e] = x;
+            }
+            vb[jj][0] = pack_bf2(v[jj][0], v[jj][1]);
+            vb[jj][1] = pack_bf2(v[jj][2], v[jj][3]);
+        }
+        if (OUT != kOutHead && in) {
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) {
+                const int c4 = e_cb + 16 * jj + 4 * q;
+                if (OUT != kOutAny || a.y) *reinterpret_cast<uint2*>(a.y + pix * a.ys + a.yo + c4) = make_uint2(vb[jj][0], vb[jj][1]);
+                if (OUT == kOutAny && a.yf)
+                    *reinterpret_cast<float4*>(a.yf + pix * Cout + c4) = make_float4(v[jj][0], v[jj][1], v[jj][2], v[jj][3]);
+                if (OUT == kOutAny && a.pred && !a.hw) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (c4 + e < a.rc) a.pred[pix * a.rc + c4 + e] = a.res[pix * a.rc + c4 + e] + v[jj][e];
+                }
+            }
+        }
+        if (OUT == kOutYPool || (OUT == kOutAny && a.yp)) {
+            if (r & 1) {
+                // 2x2 mean of the bf16 outputs: rows r-1, r are this lane's, the odd column is
+                // the neighbouring lane's; summed in the order (0,0), (0,1), (1,0), (1,1)
+                const int Hp = H >> 1, Wp = W >> 1, Y = (e_ty0 + r) >> 1, X = e_xx >> 1;
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj) {
+                    float sm[4];
+#pragma unroll
+                    for (int h2 = 0; h2 < 2; ++h2) {
+                        const float a0 = bf_lo(prev_bf[jj][h2]), a1 = bf_lo(vb[jj][h2]);
+                        const float b0 = bf_hi(prev_bf[jj][h2]), b1 = bf_hi(vb[jj][h2]);
+                        sm[2 * h2] = ((a0 + swap_lane_pair(a0)) + a1) + swap_lane_pair(a1);
+                        sm[2 * h2 + 1] = ((b0 + swap_lane_pair(b0)) + b1) + swap_lane_pair(b1);
+                    }
+                    if ((jl & 1) == 0 && Y < Hp && X < Wp)
+                        *reinterpret_cast<uint2*>(a.yp + ((e_n * Hp + Y) * Wp + X) * a.yps + a.ypo + e_cb + 16 * jj + 4 * q) =
+                            make_uint2(pack_bf2(0.25f * sm[0], 0.25f * sm[1]), pack_bf2(0.25f * sm[2], 0.25f * sm[3]));
+                }
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj) prev_bf[jj][0] = vb[jj][0], prev_bf[jj][1] = vb[jj][1];
+            }
+        }
+        if (CG == 1 && (OUT == kOutHead || (OUT == kOutAny && a.hw))) {
+            // head output c of pixel jl lands in lane jl + 16 (c / 4), element c % 4 (the
+            // operand order: see head_a)
+            short8_t hb;
+            hb[0] = (short)(vb[0][0] & 0xffff); hb[1] = (short)(vb[0][0] >> 16);
+            hb[2] = (short)(vb[0][1] & 0xffff); hb[3] = (short)(vb[0][1] >> 16);
+            hb[4] = (short)(vb[1][0] & 0xffff); hb[5] = (short)(vb[1][0] >> 16);
+            hb[6] = (short)(vb[1][1] & 0xffff); hb[7] = (short)(vb[1][1] >> 16);
+            const float4_t d = mfma32(head_a, hb, float4_t{0.f, 0.f, 0.f, 0.f});
+            if (OUT == kOutHead || a.rc == 4) {
+                // the row's 4 outputs of pixel jl (lane jl) go to lane jl + 16 (r % 4), which
+                // holds the residual of this row
+                float dd[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dd[e] = __shfl(d[e], jl);
+                if (q == (r & 3) && in) {
+                    const float4 rs = res_row;
+                    *reinterpret_cast<float4*>(a.pred + pix * 4) =
+                        make_float4(rs.x + (dd[0] + head_b[0]), rs.y + (dd[1] + head_b[1]),
+                                    rs.z + (dd[2] + head_b[2]), rs.w + (dd[3] + head_b[3]));
+                }
+            } else if (OUT == kOutAny && in) {
+                {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int c = 4 * q + e;
+                        if (c < a.rc) a.pred[pix * a.rc + c] = a.res[pix * a.rc + c] + (d[e] + head_b[e]);
+                    }
+                }
+            }
+        }
+    };
+
+    // the item's output rows. With the fused head and 4 fields, lane jl + 16 k first reads the
+    // residual of rows k, k+4, k+8, k+12 of pixel jl (rows outside the image read a clamped
+    // one), so that every load is issued before the first store
+    auto epilogue = [&]() __attribute__((always_inline)) {
+        constexpr bool HEAD = CG == 1 && (OUT == kOutHead || OUT == kOutAny);
+        float4 rq[R / 4];
+#pragma unroll
+        for (int m = 0; m < R / 4; ++m) rq[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (HEAD && a.hw && (OUT == kOutHead || a.rc == 4)) {
+            const int xc = e_xx < W ? e_xx : W - 1;
+#pragma unroll
+            for (int m = 0; m < R / 4; ++m) {
+                const int yr = e_ty0 + 4 * m + q, yy = yr < H ? yr : H - 1;
+                rq[m] = *reinterpret_cast<const float4*>(a.res + ((e_n * H + yy) * W + xc) * 4);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) epi_row(r, rq[r / 4]);
+    };
+    // ---- the MFMAs of one step -----------------------------------------------------------------
+    // by horizontal tap dx and patch row, with the next step's patch loads between the first
+    // column's rows; once a tap column is done its registers take the next step's weights
+    // (next_it, next_kc)
+    short8_t wr[9][2];
+    auto compute = [&](int buf, int next_it, int next_kc) __attribute__((always_inline)) {
+        const uint8_t* base = wconv_lds + buf * G::BUF_BYTES;
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            short8_t bn = *reinterpret_cast<const short8_t*>(base + boff[dx]);
+#pragma unroll
+            for (int ir = 0; ir < R + 2; ++ir) {
+                const short8_t bx = bn;
+                if (ir + 1 < R + 2) bn = *reinterpret_cast<const short8_t*>(base + (ir + 1) * PCOL * 64 + boff[dx]);
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const int orow = ir - dy;
+                    if (orow < 0 || orow >= R) continue;
+#pragma unroll
+                    for (int jj = 0; jj < 2; ++jj) acc[orow][jj] = mfma32(wr[3 * dy + dx][jj], bx, acc[orow][jj]);
+                }
+                if (dx == 0) {
+                    // this column's 18 rows carry up to 18 load blocks, the rest go after it
+                    if (ir < NBW) issue_block(ir, next_kc);
+                    if (ir == R + 1)
+#pragma unroll
+                        for (int i = R + 2; i < NBW; ++i) issue_block(i, next_kc);
+                }
+            }
+            // compiler barriers keep the weight loads here, ahead of the next step, to which the
+            // compiler would otherwise move them and wait for them at once; the last column's
+            // go after the epilogue (below)
+            if (dx < 2) {
+                asm volatile("" ::: "memory");
+                load_w(next_it, next_kc, dx, wr);
+                asm volatile("" ::: "memory");
+            }
+        }
+    };
+
+    for (int c = tid; c < Cout; c += 256) s_bias[c] = a.bias ? a.bias[c] : 0.0f;
+    int kc = 0, buf = 0;
+    plan_loads(item);
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) issue_block(i, 0);
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) load_w(item, 0, dx, wr);
+    for (;;) {
+        int nitem = item, nkc = kc + 32;
+        if (nkc >= Cin) {
+            nkc = 0;
+            nitem = item + nloc;
+        }
+        const bool more = nitem < band1;
+        // the loads for the next step are issued on every path, so that the compiler counts
+        // outstanding loads exactly (it counts only loads every path issues); after the last
+        // step they fetch this step's data again, which nothing reads
+        const int lit = more ? nitem : item, lkc = more ? nkc : kc;
+        // this step's patch goes from the staging registers into buffer buf, which every wave
+        // finished reading two steps ago (the barrier of the last step is behind that); after
+        // the barrier every wave's pieces are there. Fence-free barrier (__syncthreads' release
+        // would wait for every outstanding load); compiler barriers keep memory accesses on
+        // their side.
+        publish(buf);
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the stores above (and the bias)
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (more && nkc == 0) plan_loads(nitem);
+        compute(buf, lit, lkc);
+        if (nkc == 0) {
+            begin_item_out(item);
+            load_bias();
+            epilogue();
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = float4_t{0.f, 0.f, 0.f, 0.f};
+            // the item's stores complete before more loads are issued: with stores and loads
+            // outstanding together the compiler can no longer count loads in order and waits for
+            // all of them wherever it needs one
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
+        }
+        asm volatile("" ::: "memory");
+        load_w(lit, lkc, 2, wr);
+        asm volatile("" ::: "memory");
+        if (!more) break;
+        item = nitem;
+        kc = nkc;
+        buf ^= 1;
+    }
 }
 
 // dgrad weights: W'[ci][tap'][co] = W[co][KS*KS-1-tap'][ci], so that the data gradient of a
@@ -817,6 +1214,51 @@ static hipError_t launch_first_t(const ConvArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int CG, bool R, int OUT>
+static hipError_t launch_wave_o(const ConvArgs& a, hipStream_t st) {
+    using G = WaveConvGeom<CG>;
+    static int grid_cap = 0;  // workgroups resident at once on this device (set once)
+    if (!grid_cap) {
+        hipError_t e = hipFuncSetAttribute((const void*)&conv3_wave_kernel<CG, R, OUT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, G::LDS_BYTES);
+        if (e != hipSuccess) return e;
+        int dev = 0, cus = 0, per = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)&conv3_wave_kernel<CG, R, OUT>, 256,
+                                                              G::LDS_BYTES)) != hipSuccess)
+            return e;
+        grid_cap = (per < 1 ? 1 : per) * cus;
+    }
+    const long long items = (long long)a.N * ((a.H + kWvRows - 1) / kWvRows) *
+                            ((a.W + 16 * G::PX - 1) / (16 * G::PX)) * (a.Cout / (32 * CG));
+    if (items > (1LL << 30)) return hipErrorInvalidValue;
+    long long grid = items < grid_cap ? items : grid_cap;
+    if (grid < 8) grid = 8;  // every XCD band has a workgroup
+    hipLaunchKernelGGL((conv3_wave_kernel<CG, R, OUT>), dim3((unsigned)grid), dim3(256), G::LDS_BYTES, st, a, (int)items);
+    return hipGetLastError();
+}
+
+template <int CG, bool R>
+static hipError_t launch_wave_t(const ConvArgs& a, hipStream_t st) {
+    if constexpr (CG == 1)
+        if (a.hw && a.rc == 4 && !a.y && !a.yp && !a.yf) return launch_wave_o<CG, R, kOutHead>(a, st);
+    if (!a.hw && !a.yf && !a.pred && a.y) {
+        if (a.yp) return launch_wave_o<CG, R, kOutYPool>(a, st);
+        return launch_wave_o<CG, R, kOutY>(a, st);
+    }
+    return launch_wave_o<CG, R, kOutAny>(a, st);
+}
+
+// the wave-row kernel unless LBPF_CONV_WAVE=0 is set (read once)
+static bool wave_conv_enabled() {
+    static const bool on = [] {
+        const char* v = getenv("LBPF_CONV_WAVE");
+        return !(v && v[0] == '0');
+    }();
+    return on;
+}
+
 hipError_t unet_conv_plan(int ks, const ConvArgs& a, ConvPlan* plan) {
     ConvPlan p{};
     if (a.xin) {
@@ -842,6 +1284,21 @@ hipError_t unet_conv_plan(int ks, const ConvArgs& a, ConvPlan* plan) {
                          (!a.hw || (a.pred && a.res && a.Cout <= 32 && a.rc >= 1 && a.rc <= 16));
     if (!aligned || (ks != 1 && ks != 3) || a.Cl > a.Cin || a.N < 1 || a.H < 1 || a.W < 1)
         return hipErrorInvalidValue;
+    // 3x3 with whole 32-channel chunks and 32-channel output groups: the wave-row kernel
+    auto al16 = [](const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15) == 0; };
+    const int wcot = a.Cout % 128 == 0 ? 128 : (a.Cout % 64 == 0 ? 64 : 32);
+    if (ks == 3 && wave_conv_enabled() && a.Cin % 32 == 0 && a.Cl % 32 == 0 && a.Cout % 32 == 0 &&
+        a.Cout <= kWaveMaxCout &&
+        a.H >= kWvRows + 2 && a.W >= 16 * (128 / wcot) + 2 &&
+        (long long)a.N * a.H * a.W * (a.Cin + a.Cout) < (1LL << 30) &&
+        (!a.hw || a.Cout == 32) && al16(a.x) && (a.Cl == 0 || al16(a.xl)) && al16(a.w) && (!a.yf || al16(a.yf)) &&
+        (!a.y || al16(a.y)) && (!a.yp || al16(a.yp)) && (!a.hw || a.rc != 4 || (al16(a.res) && al16(a.pred)))) {
+        p.first = 2;
+        p.cot = wcot;
+        p.pfw = 0;
+        *plan = p;
+        return hipSuccess;
+    }
     int cot = a.Cout <= 16 ? 16 : (a.Cout <= 32 ? 32 : 64);
     if (a.hw) cot = 32;  // the fused head needs every output channel in one workgroup
     // fewer than ~2 workgroups per CU with 64 channels each: take 32 (more workgroups)
@@ -863,6 +1320,11 @@ hipError_t unet_conv(int ks, bool relu, const ConvArgs& a, hipStream_t st) {
     ConvPlan p;
     const hipError_t e = unet_conv_plan(ks, a, &p);
     if (e != hipSuccess) return e;
+    if (p.first == 2) {
+        if (p.cot == 128) return relu ? launch_wave_t<4, true>(a, st) : launch_wave_t<4, false>(a, st);
+        if (p.cot == 64) return relu ? launch_wave_t<2, true>(a, st) : launch_wave_t<2, false>(a, st);
+        return relu ? launch_wave_t<1, true>(a, st) : launch_wave_t<1, false>(a, st);
+    }
     if (p.first) {
         if (p.cot == 32) return relu ? launch_first_t<true, 32>(a, st) : launch_first_t<false, 32>(a, st);
         return relu ? launch_first_t<true, 64>(a, st) : launch_first_t<false, 64>(a, st);

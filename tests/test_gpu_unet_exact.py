@@ -97,27 +97,41 @@ def assert_bitwise(got, exp):
             (k, int((g != e).sum()), float(np.abs(g - e).max()))
 
 
-# (name, kwargs, expected variant (first-layer kernel, output channels per workgroup, weight prefetch))
+# (name, kwargs, expected variant (kernel: 0 tiled, 1 first layer, 2 wave-row; output channels per
+# workgroup; weight prefetch of the tiled kernel))
 CASES = [
     # the first layer of the 1024^2 pass: FP32 fields in, (tap, field)-ordered K
     ("first_1024", dict(ks=3, n=1, h=1024, w=1024, cin=16, cout=32, first=4, pool=True), (1, 32, 0)),
     ("first_cout64", dict(ks=3, n=2, h=40, w=24, cin=16, cout=64, first=3), (1, 64, 0)),
-    # E1 of the 1024^2 pass (level 1, 32 -> 64 channels): a single input chunk, so 32 channels per
-    # workgroup at three workgroups per CU without the weight prefetch
-    ("enc1_512", dict(ks=3, n=1, h=512, w=512, cin=32, cout=64, pool=True), (0, 32, 0)),
-    # E2 of the 1024^2 pass (level 2, 64 -> 128): 64 channels per workgroup with the prefetch
-    ("enc2_256", dict(ks=3, n=1, h=256, w=256, cin=64, cout=128, pool=True), (0, 64, 1)),
-    # E3 (level 3, 128 -> 256): too few tiles for 64 channels
-    ("enc3_128", dict(ks=3, n=1, h=128, w=128, cin=128, cout=256), (0, 32, 1)),
-    # D2 (level 2, [up(E3), E2] 384 -> 128) and D1 (level 1, [up(D2), E1] 192 -> 64), upsampling fused
-    ("dec2_256", dict(ks=3, n=1, h=256, w=256, cin=384, cl=256, cout=128), (0, 64, 1)),
-    ("dec1_512", dict(ks=3, n=1, h=512, w=512, cin=192, cl=128, cout=64), (0, 64, 1)),
-    # D0 with the fused 1 x 1 head and the prediction epilogue (level 0, [up(D1), E0] 96 -> 32)
-    ("dec0_head_1024", dict(ks=3, n=1, h=1024, w=1024, cin=96, cl=64, cout=32, head_rc=4), (0, 32, 0)),
-    # small grids and ragged tiles: the prefetching COT = 32 variant, and COT = 16 (1 x 1 head
-    # of the training pass, FP32 outputs, no activation)
-    ("dec0_head_ragged", dict(ks=3, n=2, h=40, w=24, cin=96, cl=64, cout=32, head_rc=4), (0, 32, 1)),
-    ("tile32_ragged_pool", dict(ks=3, n=3, h=24, w=72, cin=64, cout=32, pool=True), (0, 32, 1)),
+    # the 3x3 layers of the 1024^2 pass run the wave-row kernel (whole 32-channel chunks):
+    # E1 (level 1, 32 -> 64, one input chunk, fused pool), E2 (64 -> 128), E3 (128 -> 256),
+    # D2 ([up(E3), E2] 384 -> 128) and D1 ([up(D2), E1] 192 -> 64) with the upsampling fused,
+    # D0 ([up(D1), E0] 96 -> 32) with the fused 1 x 1 head and prediction; 1024^2 D0 has four
+    # work items per workgroup, so the persistent loop and its chunk pipeline across items run
+    ("enc1_512", dict(ks=3, n=1, h=512, w=512, cin=32, cout=64, pool=True), (2, 64, 0)),
+    ("enc2_256", dict(ks=3, n=1, h=256, w=256, cin=64, cout=128, pool=True), (2, 128, 0)),
+    ("enc3_128", dict(ks=3, n=1, h=128, w=128, cin=128, cout=256), (2, 128, 0)),
+    ("dec2_256", dict(ks=3, n=1, h=256, w=256, cin=384, cl=256, cout=128), (2, 128, 0)),
+    ("dec1_512", dict(ks=3, n=1, h=512, w=512, cin=192, cl=128, cout=64), (2, 64, 0)),
+    ("dec0_head_1024", dict(ks=3, n=1, h=1024, w=1024, cin=96, cl=64, cout=32, head_rc=4), (2, 32, 0)),
+    # ragged tiles (rows and columns beyond the image), several images, no activation, a head
+    # with rc != 4, the pool at every channel grouping, images of one patch
+    ("dec0_head_ragged", dict(ks=3, n=2, h=40, w=72, cin=96, cl=64, cout=32, head_rc=4), (2, 32, 0)),
+    ("wave_head_rc3", dict(ks=3, n=1, h=20, w=70, cin=64, cl=32, cout=32, head_rc=3), (2, 32, 0)),
+    ("wave32_ragged_pool", dict(ks=3, n=3, h=24, w=72, cin=64, cout=32, pool=True), (2, 32, 0)),
+    ("wave64_ragged_pool", dict(ks=3, n=2, h=34, w=50, cin=96, cl=32, cout=64, pool=True, relu=False), (2, 64, 0)),
+    ("wave128_ragged_pool", dict(ks=3, n=1, h=18, w=30, cin=32, cout=384, pool=True), (2, 128, 0)),
+    ("wave32_one_patch", dict(ks=3, n=2, h=18, w=66, cin=32, cout=32), (2, 32, 0)),
+    # the tiled kernel, which takes images smaller than one patch of the wave-row kernel (with
+    # the fused head) and channel counts that are not whole 32-channel chunks: COT 64
+    # with the weight prefetch, COT 32 with and without it (three workgroups per CU on a grid of
+    # at least 768 workgroups), and COT 16 (the 1 x 1 head of the training pass, FP32 outputs,
+    # no activation)
+    ("tile64_cin40", dict(ks=3, n=2, h=256, w=256, cin=40, cl=16, cout=64, pool=True), (0, 64, 1)),
+    ("tile32_cin48_ragged", dict(ks=3, n=3, h=24, w=72, cin=48, cout=32, pool=True), (0, 32, 1)),
+    ("tile32_head_small", dict(ks=3, n=2, h=40, w=24, cin=96, cl=64, cout=32, head_rc=4), (0, 32, 1)),
+    ("tile32_tiny", dict(ks=3, n=1, h=4, w=6, cin=32, cout=32), (0, 32, 1)),
+    ("tile32_cin24_large", dict(ks=3, n=1, h=512, w=512, cin=24, cout=40), (0, 32, 0)),
     ("head_1x1_cout16", dict(ks=1, n=2, h=48, w=40, cin=32, cout=16, relu=False), (0, 16, 1)),
 ]
 
