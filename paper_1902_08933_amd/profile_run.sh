@@ -122,6 +122,25 @@ if [ "$W" = "batch256" ]; then
         --out "$PROF/batch_step_batch256_pmc.txt"
     exit $?
 fi
+if [ "$W" = "bench1024" ] || [ "$W" = "bench4096" ]; then
+    # the benchmark's own command (its headline leg only) under the kernel trace: the summary gives
+    # the traced average duration of the timed launches of the fused step beside the ms_per_step
+    # that the same run's bench.py line reports
+    N=${W#bench}
+    STEPS=$([ "$N" = "1024" ] && echo 2000 || echo 200)
+    OUT=$RAW/prof_$W
+    PROF=${PROFILE_OUT:-profiles}
+    mkdir -p "$OUT" "$PROF"
+    export TMPDIR=/tmp
+    CMD="python3 bench.py --workload spinodal$N --steps $STEPS --warmup 20 --no-large --no-im --no-batch --no-surrogate --no-single-phase --no-d3q15 --no-paper-workloads --no-cpu-baseline"
+    echo "profile: kernel trace of bench.py on spinodal$N" && \
+    timeout -k 10 300 rocprofv3 --kernel-trace --stats -d "$OUT/trace" -o run -- $CMD > "$OUT/trace.log" 2>&1 && \
+    python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --cells $((N * N)) \
+        --alg-bytes-per-cell 160 --storage-bytes-per-cell 168 --last $STEPS --bench-log "$OUT/trace.log" \
+        --command "bash paper_1902_08933_amd/profile_run.sh $W  (rocprofv3 --kernel-trace --stats -- $CMD; the last $STEPS launches of the fused step, the timed ones, counted)" \
+        --out "$PROF/fused_step_bench$N""_trace.txt"
+    exit $?
+fi
 if [ "$W" = "unet1024" ]; then
     # surrogate forward pass at 1024^2: kernel trace of 1 + 10 forwards (214 GFLOP each)
     OUT=$RAW/prof_unet1024

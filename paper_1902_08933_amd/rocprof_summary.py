@@ -89,6 +89,21 @@ def pick(d, key):
     return k, d[k]
 
 
+def bench_line(path):
+    """the last JSON line a bench.py run printed, or None"""
+    import json
+    found = None
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("{") and '"ms_per_step"' in line:
+                try:
+                    found = json.loads(line)
+                except ValueError:
+                    pass
+    return found
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace")
@@ -110,6 +125,9 @@ def main():
     ap.add_argument("--last", type=int, default=0,
                     help="count only the last N dispatches of --kernel (the timed ones, after a "
                          "warm-up whose launches differ)")
+    ap.add_argument("--bench-log", default="",
+                    help="stdout of a bench.py run under the trace: its JSON line's ms_per_step is "
+                         "reported beside the traced average duration of --kernel")
     ap.add_argument("--command", default="")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
@@ -142,6 +160,14 @@ def main():
             lines.append(f"algorithmic_bytes_per_cell: {a.alg_bytes_per_cell:.0f}")
             lines.append(f"algorithmic_GBs_at_avg_duration: {gbs:.1f}")
             lines.append(f"algorithmic_GBs_at_span: {a.alg_bytes_per_cell * a.cells / (span / n_span * 1e-9) / 1e9:.1f}")
+            if a.bench_log:
+                bench = bench_line(a.bench_log)
+                if bench is not None:
+                    bms = bench["ms_per_step"] * 1e3
+                    lines.append(f"bench_ms_per_step_us: {bms:.3f} (the same run's bench.py JSON line: "
+                                 f"value {bench['value']} {bench['unit']}, strip {bench['config'].get('strip')})")
+                    lines.append(f"trace_avg_over_bench: {avg / 1e3 / bms:.4f}; "
+                                 f"trace_span_over_bench: {span / n_span / 1e3 / bms:.4f}")
     if a.fetch and a.write:
         fk, fv = pick(pmc_values(a.fetch, "FETCH_SIZE"), a.kernel)
         wk, wv = pick(pmc_values(a.write, "WRITE_SIZE"), a.kernel)
