@@ -220,8 +220,14 @@ def eval_one_stride(net, x, y):
     return float(np.mean(errs)), float(np.mean(pers))
 
 
+def _healthy(sim, max_u, max_phi):
+    """finite, |u| <= max_u and |phi| <= max_phi"""
+    d = sim.diagnostics(check=False)
+    return d["status"] == 0 and d["max_u"] <= max_u and sim.field_stats("phi")["max_abs"] <= max_phi
+
+
 def hybrid_cycle(sim, net, bufs, ckpt=None, lb_every=500, lb_steps=K_STEPS, max_u=0.1, norm=None,
-                 max_growth=10.0, max_phi=1.1):
+                 max_growth=10.0, max_phi=1.1, ckpt_prev=None):
     """One cycle of the hybrid: (lb_every - lb_steps) / K network strides from the solver's
     current fields, then one LB stride of lb_steps steps re-started from the network's fields
     (equilibrium populations). The cycle ends on an LB state at step + lb_every. The fields are
@@ -230,8 +236,11 @@ def hybrid_cycle(sim, net, bufs, ckpt=None, lb_every=500, lb_steps=K_STEPS, max_
     Fallback: with a checkpoint buffer (lbpf.Simulation.state_size() bytes), the state is saved
     first and restored, and the cycle redone with the plain LB, if the LB stride ends with a
     non-finite state, |u| > max_u, |phi| > max_phi, or a largest |u| or |mu| or a standard
-    deviation of phi or u more than max_growth times its value at the cycle's start. Returns True
-    when the network's cycle was kept."""
+    deviation of phi or u more than max_growth times its value at the cycle's start. A state that
+    an earlier cycle left can pass that test and still diverge later: with ckpt_prev (the
+    checkpoint saved at the start of the previous cycle), a plain-LB redo that itself ends
+    non-finite or out of range is replaced by two cycles of the plain LB from ckpt_prev.
+    Returns True when the network's cycle was kept."""
     a, b = bufs
     step0 = sim.step_count
     if ckpt is not None:
@@ -263,6 +272,9 @@ def hybrid_cycle(sim, net, bufs, ckpt=None, lb_every=500, lb_steps=K_STEPS, max_
             return True
     sim.load_state(ckpt)
     sim.step(lb_every)
+    if ckpt_prev is not None and not _healthy(sim, max_u, max_phi):
+        sim.load_state(ckpt_prev)
+        sim.step(2 * lb_every)
     return False
 
 
@@ -357,7 +369,8 @@ def horizon_eval(net, cfg, phi0, cycles=20, t0=1000, lb_every=500):
     co = coarse_lb_start(lb, cc)
     co_steps = lb_every // 4
     bufs = hybrid_buffers(hy)
-    ckpt = torch.empty(hy.state_size(), dtype=torch.uint8, device=hy.device)
+    # two checkpoints, used in turn: the current cycle's and the previous one's
+    ckpts = [torch.empty(hy.state_size(), dtype=torch.uint8, device=hy.device) for _ in range(2)]
     co.step(co_steps)  # first-call set-up of the coarse grid's kernels, outside the timing
     co = coarse_lb_start(lb, cc)
 
@@ -377,7 +390,8 @@ def horizon_eval(net, cfg, phi0, cycles=20, t0=1000, lb_every=500):
     rows = []
     for c in range(cycles):
         _, t_lb = timed(lambda: lb.step(lb_every))
-        kept, t_hy = timed(lambda: hybrid_cycle(hy, net, bufs, ckpt=ckpt, lb_every=lb_every))
+        kept, t_hy = timed(lambda: hybrid_cycle(hy, net, bufs, ckpt=ckpts[c % 2], lb_every=lb_every,
+                                                ckpt_prev=ckpts[(c + 1) % 2] if c > 0 else None))
         lb_reinit_cycle(ctl, bufs, lb_every=lb_every)
         _, t_co = timed(lambda: co.step(co_steps))
         ref, h, r, cg = host(lb), host(hy), host(ctl), host(co, up=True)

@@ -99,6 +99,27 @@ def test_fallback_reproduces_plain_lb(trained):
         np.testing.assert_array_equal(a.read(f).cpu().numpy(), b.read(f).cpu().numpy())
 
 
+def test_fallback_rolls_back_two_cycles(trained):
+    # a plain-LB redo that ends out of range (here forced with max_u = 0) is replaced by two
+    # cycles of the plain LB from the previous cycle's checkpoint: bit for bit the plain LB
+    import torch
+    from paper_1902_08933_amd import lbpf, surrogate as S, workloads as W
+    net, _, _ = trained
+    cfg, phi = W.spinodal(n=256, seed=6)
+    a = lbpf.Simulation(cfg).init(torch.from_numpy(phi.astype(np.float32)).cuda())
+    b = lbpf.Simulation(cfg).init(torch.from_numpy(phi.astype(np.float32)).cuda())
+    a.step(800)
+    prev, cur = (torch.empty(a.state_size(), dtype=torch.uint8, device="cuda") for _ in range(2))
+    a.save_state(out=prev)
+    a.step(500)
+    kept = S.hybrid_cycle(a, net, S.hybrid_buffers(a), ckpt=cur, ckpt_prev=prev, max_u=0.0)
+    assert not kept
+    b.step(1800)
+    assert a.step_count == b.step_count == 1800
+    for f in ("phi", "ux", "uy", "p"):
+        np.testing.assert_array_equal(a.read(f).cpu().numpy(), b.read(f).cpu().numpy())
+
+
 def test_field_stats_against_host():
     # lbpf_field_stats (FP64 on the GPU) against the same statistics of the read fields
     import torch
