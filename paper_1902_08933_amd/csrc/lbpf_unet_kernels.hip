@@ -520,21 +520,39 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
         col = p - prow * PCOL;
         gg = (s & 3) ^ ((col >> 1) & 3);
     };
-    // piece block i of chunk kc into the staging registers: a uniform base (the chunk's first
-    // channel at the patch corner) and a 32-bit per-lane byte offset
+    // the chunk whose patch is being loaded, as uniform values set once per step: the chunk's
+    // first channel in image l_n, the byte strides of a row and a pixel, and the shift of the
+    // coordinates (1 for the channels below Cl, read at half resolution). The tensors' bases and
+    // strides are copied into registers once (opaque to the compiler, which would otherwise
+    // reload them from the kernel arguments at every block and wait for the scalar loads).
+    using gchar = const __attribute__((address_space(1))) char;  // global memory
+    const char* xb0 = reinterpret_cast<const char*>(a.x + a.xo);
+    const char* xlb0 = reinterpret_cast<const char*>(a.xl + a.xlo);
+    int xs2 = 2 * a.xs, xls2 = 2 * a.xls;
+    asm volatile("" : "+s"(xb0), "+s"(xlb0), "+s"(xs2), "+s"(xls2));
+    gchar* xb = (gchar*)xb0;
+    gchar* xlb = (gchar*)xlb0;
+    gchar* c_base = xb;
+    int c_rs = 0, c_ps = 0, c_sh = 0;
+    auto plan_chunk = [&](int kc) __attribute__((always_inline)) {
+        if (kc < Cl) {
+            c_ps = xls2, c_rs = Wl * xls2, c_sh = 1;
+            c_base = xlb + 2 * kc + (long long)l_n * Hl * c_rs;
+        } else {
+            c_ps = xs2, c_rs = W * xs2, c_sh = 0;
+            c_base = xb + 2 * (kc - Cl) + (long long)l_n * H * c_rs;
+        }
+    };
+    // piece block i of the planned chunk into the staging registers: the uniform base and a
+    // 32-bit per-lane byte offset (24-bit products: rows of at most 16 MB, checked on the host)
     short8_t stage[NBW];
-    auto issue_block = [&](int i, int kc) __attribute__((always_inline)) {
+    auto issue_block = [&](int i) __attribute__((always_inline)) {
         int prow, col, gg;
         piece(i, prow, col, gg);
         const int yy = wrap_near(l_ty0 + prow - 1, H), xx = wrap_near(l_tx0 + col - 1, W);
-        const char* src;
-        if (kc < Cl)
-            src = reinterpret_cast<const char*>(a.xl + a.xlo + kc) +
-                  (unsigned)((((l_n * Hl + (yy >> 1)) * Wl + (xx >> 1)) * a.xls + 8 * gg) * 2);
-        else
-            src = reinterpret_cast<const char*>(a.x + a.xo + (kc - Cl)) +
-                  (unsigned)((((l_n * H + yy) * W + xx) * a.xs + 8 * gg) * 2);
-        stage[i] = *reinterpret_cast<const short8_t*>(src);
+        const unsigned off = __umul24((unsigned)(yy >> c_sh), (unsigned)c_rs) +
+                             __umul24((unsigned)(xx >> c_sh), (unsigned)c_ps) + 16 * gg;
+        stage[i] = *reinterpret_cast<const __attribute__((address_space(1))) short8_t*>(c_base + off);
     };
     // the staged pieces into LDS buffer buf: block i of this wave is 64 consecutive pieces
     auto publish = [&](int buf) __attribute__((always_inline)) {
@@ -593,14 +611,18 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
     };
     // the fused head's A operand: lane c + 16 g holds hw[c][ch(g, e)], ch(g, e) = 4g + e for
     // e < 4 and 16 + 4g + e - 4 otherwise, the channel order of the bf16 outputs in a lane's B
-    // operand (channels 4g .. 4g+3 of both 16-channel halves); and the head's bias
+    // operand (channels 4g .. 4g+3 of both 16-channel halves); and the head's bias. With 4
+    // outputs the 4 weight rows are repeated in A's rows 4..15, so that every lane group of the
+    // product holds the pixel's 4 outputs (lane j + 16 g, element c: D[4g + c][j] = out c).
     short8_t head_a = {0, 0, 0, 0, 0, 0, 0, 0};
     float head_b[4] = {0.f, 0.f, 0.f, 0.f};
     if (CG == 1 && (OUT == kOutHead || (OUT == kOutAny && a.hw))) {
+        const bool rep = OUT == kOutHead || a.rc == 4;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int ch = e < 4 ? 4 * q + e : 16 + 4 * q + e - 4;
-            if (jl < a.rc) head_a[e] = (short)a.hw[jl * Cout + ch];
+            if (rep) head_a[e] = (short)a.hw[(jl & 3) * Cout + ch];
+            else if (jl < a.rc) head_a[e] = (short)a.hw[jl * Cout + ch];
         }
         // with 4 outputs every lane adds them (rows are spread over the lanes, below)
 #pragma unroll
@@ -666,8 +688,8 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
             }
         }
         if (CG == 1 && (OUT == kOutHead || (OUT == kOutAny && a.hw))) {
-            // head output c of pixel jl lands in lane jl + 16 (c / 4), element c % 4 (the
-            // operand order: see head_a)
+            // head output c of pixel jl lands in lane jl + 16 (c / 4), element c % 4, and with
+            // 4 outputs in every lane jl + 16 g (the operand order: see head_a)
             short8_t hb;
             hb[0] = (short)(vb[0][0] & 0xffff); hb[1] = (short)(vb[0][0] >> 16);
             hb[2] = (short)(vb[0][1] & 0xffff); hb[3] = (short)(vb[0][1] >> 16);
@@ -675,16 +697,13 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
             hb[6] = (short)(vb[1][1] & 0xffff); hb[7] = (short)(vb[1][1] >> 16);
             const float4_t d = mfma32(head_a, hb, float4_t{0.f, 0.f, 0.f, 0.f});
             if (OUT == kOutHead || a.rc == 4) {
-                // the row's 4 outputs of pixel jl (lane jl) go to lane jl + 16 (r % 4), which
-                // holds the residual of this row
-                float dd[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) dd[e] = __shfl(d[e], jl);
+                // every lane holds its pixel's 4 outputs; lane jl + 16 (r % 4) holds the
+                // residual of this row and writes the prediction
                 if (q == (r & 3) && in) {
                     const float4 rs = res_row;
                     *reinterpret_cast<float4*>(a.pred + pix * 4) =
-                        make_float4(rs.x + (dd[0] + head_b[0]), rs.y + (dd[1] + head_b[1]),
-                                    rs.z + (dd[2] + head_b[2]), rs.w + (dd[3] + head_b[3]));
+                        make_float4(rs.x + (d[0] + head_b[0]), rs.y + (d[1] + head_b[1]),
+                                    rs.z + (d[2] + head_b[2]), rs.w + (d[3] + head_b[3]));
                 }
             } else if (OUT == kOutAny && in) {
                 {
@@ -740,10 +759,10 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
                 }
                 if (dx == 0) {
                     // this column's 18 rows carry up to 18 load blocks, the rest go after it
-                    if (ir < NBW) issue_block(ir, next_kc);
+                    if (ir < NBW) issue_block(ir);
                     if (ir == R + 1)
 #pragma unroll
-                        for (int i = R + 2; i < NBW; ++i) issue_block(i, next_kc);
+                        for (int i = R + 2; i < NBW; ++i) issue_block(i);
                 }
             }
             // compiler barriers keep the weight loads here, ahead of the next step, to which the
@@ -760,10 +779,14 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
     for (int c = tid; c < Cout; c += 256) s_bias[c] = a.bias ? a.bias[c] : 0.0f;
     int kc = 0, buf = 0;
     plan_loads(item);
+    plan_chunk(0);
 #pragma unroll
-    for (int i = 0; i < NBW; ++i) issue_block(i, 0);
+    for (int i = 0; i < NBW; ++i) issue_block(i);
+    // the patch before the weights (the first step's top then waits for the patch only)
+    asm volatile("" ::: "memory");
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) load_w(item, 0, dx, wr);
+    asm volatile("" ::: "memory");
     for (;;) {
         int nitem = item, nkc = kc + 32;
         if (nkc >= Cin) {
@@ -786,6 +809,7 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
         if (more && nkc == 0) plan_loads(nitem);
+        plan_chunk(lkc);
         compute(buf, lit, lkc);
         if (nkc == 0) {
             begin_item_out(item);
@@ -793,12 +817,14 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
             epilogue();
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = float4_t{0.f, 0.f, 0.f, 0.f};
-            // the item's stores complete before more loads are issued: with stores and loads
-            // outstanding together the compiler can no longer count loads in order and waits for
-            // all of them wherever it needs one
-            asm volatile("" ::: "memory");
-            __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
         }
+        // the step's loads (and an item's stores) complete before more loads are issued: with
+        // stores and loads outstanding together the compiler can no longer count loads in order
+        // and waits for all of them wherever it needs one; and with the same loads outstanding
+        // on both paths (item finished or not) it counts exactly at the next step's top, where
+        // nothing then waits for the next step's patch
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
         asm volatile("" ::: "memory");
         load_w(lit, lkc, 2, wr);
         asm volatile("" ::: "memory");
@@ -1291,6 +1317,7 @@ hipError_t unet_conv_plan(int ks, const ConvArgs& a, ConvPlan* plan) {
         a.Cout <= kWaveMaxCout &&
         a.H >= kWvRows + 2 && a.W >= 16 * (128 / wcot) + 2 &&
         (long long)a.N * a.H * a.W * (a.Cin + a.Cout) < (1LL << 30) &&
+        (long long)a.W * a.xs * 2 < (1LL << 24) && (a.Cl == 0 || (long long)(a.W >> 1) * a.xls * 2 < (1LL << 24)) &&
         (!a.hw || a.Cout == 32) && al16(a.x) && (a.Cl == 0 || al16(a.xl)) && al16(a.w) && (!a.yf || al16(a.yf)) &&
         (!a.y || al16(a.y)) && (!a.yp || al16(a.yp)) && (!a.hw || a.rc != 4 || (al16(a.res) && al16(a.pred)))) {
         p.first = 2;
