@@ -561,9 +561,11 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
             *reinterpret_cast<short8_t*>(wconv_lds + buf * G::BUF_BYTES + (4 * i + wave) * 1024 + lane * 16) = stage[i];
     };
     // A operands of the three taps (0, dx), (1, dx), (2, dx): lane jl + 16 q holds
-    // w[co][tap][kc + 8q .. +7] of channel co = base + 16 jj + jl (a uniform base and one per-lane
-    // byte offset)
-    const unsigned woff = (unsigned)((jl * 9 * Cin + 8 * q) * 2);
+    // w[co][tap][kc + 8q .. +7] of channel co = base + 8 (jl / 4) + 4 jj + jl % 4 (a uniform base
+    // and one per-lane byte offset). Row i of the product for half jj is then channel
+    // 8 (i / 4) + 4 jj + i % 4, so that lane j + 16 g ends with channels 8g .. 8g+7 of pixel j
+    // (elements 0..3 of half 0, then of half 1): 16 contiguous bytes of bf16 output.
+    const unsigned woff = (unsigned)(((8 * (jl >> 2) + (jl & 3)) * 9 * Cin + 8 * q) * 2);
     auto load_w = [&](int it, int kc, int dx, short8_t (&wr)[9][2]) __attribute__((always_inline)) {
         const bf16* wb = a.w + ((it % groups) * 32 * CG + 32 * cg) * 9 * Cin + kc;
 #pragma unroll
@@ -571,7 +573,7 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
 #pragma unroll
             for (int jj = 0; jj < 2; ++jj)
                 wr[3 * dy + dx][jj] = *reinterpret_cast<const short8_t*>(
-                    reinterpret_cast<const char*>(wb + (16 * jj * 9 + 3 * dy + dx) * Cin) + woff);
+                    reinterpret_cast<const char*>(wb + (4 * jj * 9 + 3 * dy + dx) * Cin) + woff);
     };
     // B operands: lane jl + 16 q reads pixel column 16 pxb + jl + dx of a patch row, channels
     // 8q .. 8q+7 of the chunk
@@ -605,22 +607,21 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
     auto load_bias = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int jj = 0; jj < 2; ++jj) {
-            const float4 b = *reinterpret_cast<const float4*>(s_bias + e_cb + 16 * jj + 4 * q);
+            const float4 b = *reinterpret_cast<const float4*>(s_bias + e_cb + 8 * q + 4 * jj);
             e_bias[jj][0] = b.x, e_bias[jj][1] = b.y, e_bias[jj][2] = b.z, e_bias[jj][3] = b.w;
         }
     };
-    // the fused head's A operand: lane c + 16 g holds hw[c][ch(g, e)], ch(g, e) = 4g + e for
-    // e < 4 and 16 + 4g + e - 4 otherwise, the channel order of the bf16 outputs in a lane's B
-    // operand (channels 4g .. 4g+3 of both 16-channel halves); and the head's bias. With 4
-    // outputs the 4 weight rows are repeated in A's rows 4..15, so that every lane group of the
-    // product holds the pixel's 4 outputs (lane j + 16 g, element c: D[4g + c][j] = out c).
+    // the fused head's A operand: lane c + 16 g holds hw[c][8g .. 8g+7], the channels of the
+    // bf16 outputs in lane g's B operand; and the head's bias. With 4 outputs the 4 weight rows
+    // are repeated in A's rows 4..15, so that every lane group of the product holds the pixel's
+    // 4 outputs (lane j + 16 g, element c: D[4g + c][j] = out c).
     short8_t head_a = {0, 0, 0, 0, 0, 0, 0, 0};
     float head_b[4] = {0.f, 0.f, 0.f, 0.f};
     if (CG == 1 && (OUT == kOutHead || (OUT == kOutAny && a.hw))) {
         const bool rep = OUT == kOutHead || a.rc == 4;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const int ch = e < 4 ? 4 * q + e : 16 + 4 * q + e - 4;
+            const int ch = 8 * q + e;
             if (rep) head_a[e] = (short)a.hw[(jl & 3) * Cout + ch];
             else if (jl < a.rc) head_a[e] = (short)a.hw[jl * Cout + ch];
         }
@@ -649,11 +650,14 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
             vb[jj][0] = pack_bf2(v[jj][0], v[jj][1]);
             vb[jj][1] = pack_bf2(v[jj][2], v[jj][3]);
         }
+        // the lane's channels: c8 .. c8+3 (half 0) and c8+4 .. c8+7 (half 1)
+        const int c8 = e_cb + 8 * q;
         if (OUT != kOutHead && in) {
+            if (OUT != kOutAny || a.y)
+                *reinterpret_cast<uint4*>(a.y + pix * a.ys + a.yo + c8) = make_uint4(vb[0][0], vb[0][1], vb[1][0], vb[1][1]);
 #pragma unroll
             for (int jj = 0; jj < 2; ++jj) {
-                const int c4 = e_cb + 16 * jj + 4 * q;
-                if (OUT != kOutAny || a.y) *reinterpret_cast<uint2*>(a.y + pix * a.ys + a.yo + c4) = make_uint2(vb[jj][0], vb[jj][1]);
+                const int c4 = c8 + 4 * jj;
                 if (OUT == kOutAny && a.yf)
                     *reinterpret_cast<float4*>(a.yf + pix * Cout + c4) = make_float4(v[jj][0], v[jj][1], v[jj][2], v[jj][3]);
                 if (OUT == kOutAny && a.pred && !a.hw) {
@@ -668,6 +672,7 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
                 // 2x2 mean of the bf16 outputs: rows r-1, r are this lane's, the odd column is
                 // the neighbouring lane's; summed in the order (0,0), (0,1), (1,0), (1,1)
                 const int Hp = H >> 1, Wp = W >> 1, Y = (e_ty0 + r) >> 1, X = e_xx >> 1;
+                uint32_t pb[2][2];
 #pragma unroll
                 for (int jj = 0; jj < 2; ++jj) {
                     float sm[4];
@@ -678,10 +683,12 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
                         sm[2 * h2] = ((a0 + swap_lane_pair(a0)) + a1) + swap_lane_pair(a1);
                         sm[2 * h2 + 1] = ((b0 + swap_lane_pair(b0)) + b1) + swap_lane_pair(b1);
                     }
-                    if ((jl & 1) == 0 && Y < Hp && X < Wp)
-                        *reinterpret_cast<uint2*>(a.yp + ((e_n * Hp + Y) * Wp + X) * a.yps + a.ypo + e_cb + 16 * jj + 4 * q) =
-                            make_uint2(pack_bf2(0.25f * sm[0], 0.25f * sm[1]), pack_bf2(0.25f * sm[2], 0.25f * sm[3]));
+                    pb[jj][0] = pack_bf2(0.25f * sm[0], 0.25f * sm[1]);
+                    pb[jj][1] = pack_bf2(0.25f * sm[2], 0.25f * sm[3]);
                 }
+                if ((jl & 1) == 0 && Y < Hp && X < Wp)
+                    *reinterpret_cast<uint4*>(a.yp + ((e_n * Hp + Y) * Wp + X) * a.yps + a.ypo + c8) =
+                        make_uint4(pb[0][0], pb[0][1], pb[1][0], pb[1][1]);
             } else {
 #pragma unroll
                 for (int jj = 0; jj < 2; ++jj) prev_bf[jj][0] = vb[jj][0], prev_bf[jj][1] = vb[jj][1];
