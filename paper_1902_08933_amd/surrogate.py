@@ -238,8 +238,10 @@ def hybrid_cycle(sim, net, bufs, ckpt=None, lb_every=500, lb_steps=K_STEPS, max_
     non-finite state, |u| > max_u, |phi| > max_phi, or a largest |u| or |mu| or a standard
     deviation of phi or u more than max_growth times its value at the cycle's start. A state that
     an earlier cycle left can pass that test and still diverge later: with ckpt_prev (the
-    checkpoint saved at the start of the previous cycle), a plain-LB redo that itself ends
-    non-finite or out of range is replaced by two cycles of the plain LB from ckpt_prev.
+    checkpoint saved at the start of the previous cycle, or a list of the checkpoints of the
+    previous cycles, newest first), a plain-LB redo that itself ends non-finite or out of range
+    is replaced by j + 2 cycles of the plain LB from the checkpoint j cycles further back, for
+    j = 0, 1, ... until one ends in range (or the list ends).
     Returns True when the network's cycle was kept."""
     a, b = bufs
     step0 = sim.step_count
@@ -272,9 +274,12 @@ def hybrid_cycle(sim, net, bufs, ckpt=None, lb_every=500, lb_steps=K_STEPS, max_
             return True
     sim.load_state(ckpt)
     sim.step(lb_every)
-    if ckpt_prev is not None and not _healthy(sim, max_u, max_phi):
-        sim.load_state(ckpt_prev)
-        sim.step(2 * lb_every)
+    older = [] if ckpt_prev is None else (list(ckpt_prev) if isinstance(ckpt_prev, (list, tuple)) else [ckpt_prev])
+    for j, ck in enumerate(older):
+        if _healthy(sim, max_u, max_phi):
+            break
+        sim.load_state(ck)
+        sim.step((j + 2) * lb_every)
     return False
 
 
@@ -369,8 +374,9 @@ def horizon_eval(net, cfg, phi0, cycles=20, t0=1000, lb_every=500):
     co = coarse_lb_start(lb, cc)
     co_steps = lb_every // 4
     bufs = hybrid_buffers(hy)
-    # two checkpoints, used in turn: the current cycle's and the previous one's
-    ckpts = [torch.empty(hy.state_size(), dtype=torch.uint8, device=hy.device) for _ in range(2)]
+    # a ring of checkpoints: the current cycle's and those of the previous ones, for roll-backs
+    depth = 4
+    ckpts = [torch.empty(hy.state_size(), dtype=torch.uint8, device=hy.device) for _ in range(depth)]
     co.step(co_steps)  # first-call set-up of the coarse grid's kernels, outside the timing
     co = coarse_lb_start(lb, cc)
 
@@ -390,8 +396,8 @@ def horizon_eval(net, cfg, phi0, cycles=20, t0=1000, lb_every=500):
     rows = []
     for c in range(cycles):
         _, t_lb = timed(lambda: lb.step(lb_every))
-        kept, t_hy = timed(lambda: hybrid_cycle(hy, net, bufs, ckpt=ckpts[c % 2], lb_every=lb_every,
-                                                ckpt_prev=ckpts[(c + 1) % 2] if c > 0 else None))
+        kept, t_hy = timed(lambda: hybrid_cycle(hy, net, bufs, ckpt=ckpts[c % depth], lb_every=lb_every,
+                                                ckpt_prev=[ckpts[(c - k) % depth] for k in range(1, min(c, depth - 1) + 1)]))
         lb_reinit_cycle(ctl, bufs, lb_every=lb_every)
         _, t_co = timed(lambda: co.step(co_steps))
         ref, h, r, cg = host(lb), host(hy), host(ctl), host(co, up=True)

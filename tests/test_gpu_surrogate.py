@@ -120,6 +120,29 @@ def test_fallback_rolls_back_two_cycles(trained):
         np.testing.assert_array_equal(a.read(f).cpu().numpy(), b.read(f).cpu().numpy())
 
 
+def test_fallback_rolls_back_further(trained):
+    # with the checkpoints of the two previous cycles (newest first) and every state out of range
+    # (max_u = 0), the redo goes back two cycles, then three: bit for bit the plain LB
+    import torch
+    from paper_1902_08933_amd import lbpf, surrogate as S, workloads as W
+    net, _, _ = trained
+    cfg, phi = W.spinodal(n=256, seed=7)
+    a = lbpf.Simulation(cfg).init(torch.from_numpy(phi.astype(np.float32)).cuda())
+    b = lbpf.Simulation(cfg).init(torch.from_numpy(phi.astype(np.float32)).cuda())
+    a.step(300)
+    old, prev, cur = (torch.empty(a.state_size(), dtype=torch.uint8, device="cuda") for _ in range(3))
+    a.save_state(out=old)
+    a.step(500)
+    a.save_state(out=prev)
+    a.step(500)
+    kept = S.hybrid_cycle(a, net, S.hybrid_buffers(a), ckpt=cur, ckpt_prev=[prev, old], max_u=0.0)
+    assert not kept
+    b.step(1800)
+    assert a.step_count == b.step_count == 1800
+    for f in ("phi", "ux", "uy", "p"):
+        np.testing.assert_array_equal(a.read(f).cpu().numpy(), b.read(f).cpu().numpy())
+
+
 def test_field_stats_against_host():
     # lbpf_field_stats (FP64 on the GPU) against the same statistics of the read fields
     import torch
