@@ -316,7 +316,8 @@ lbpf_status lbpf_mfma_probe(int32_t k, const void* A, const void* B, float* D, v
  * yf out in FP32; pred = res + out[:, :rc], or with hw set (cout <= 32) res + hb + the 1 x 1
  * head hw [rc][cout] applied to y. Channel counts, cl and cin - cl multiples of 8 except in
  * first-layer mode. variant (3 int32, may be NULL) receives the kernel chosen: tiled (0),
- * first-layer (1) or wave-row (2, ks = 3 with cin, cl and cout multiples of 32), the output
+ * first-layer (1), wave-row (2, ks = 3 with cin, cl and cout multiples of 32) or persistent
+ * first-layer (3: 4 fields, cout 32, y and/or yp only, h and w multiples of 16), the output
  * channels per workgroup (16, 32, 64 or 128), and 1 if the tiled kernel prefetches the next
  * input chunk's weights into registers. Asynchronous; LBPF_E_INVALID for shapes the kernels do
  * not take. Defined by the network description above; used by its tests. */

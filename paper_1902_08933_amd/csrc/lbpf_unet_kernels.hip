@@ -28,6 +28,14 @@ __device__ __forceinline__ bf16 f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(bf16 b) { return __uint_as_float((uint32_t)b << 16); }
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// two FP32 values as packed bf16 (round to nearest even as f2bf, one instruction)
+__device__ __forceinline__ uint32_t pack_bf2(float x, float y) {
+    const bf16x2_t v = {(__bf16)x, (__bf16)y};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
 __device__ __forceinline__ float4_t mfma16(short4_t a, short4_t b, float4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
@@ -299,6 +307,137 @@ __global__ __launch_bounds__(256, 2) void conv_first_kernel(const ConvArgs a) {
     conv_epilogue<RELU, COT, MF>(a, acc, conv_lds, tx0, ty0, n, co0);
 }
 
+// First layer, persistent (inference: 4 FP32 fields in, 32 output channels, the bf16 output and
+// its 2x2 pool out, images of whole 16 x 16 tiles): the arithmetic of conv_first_kernel, with
+// the weights staged and turned into B operands once per workgroup, and the next tile's input
+// patch loaded into registers while the current one is computed and stored. Three separate LDS
+// areas (output tile, patch, weights), so that a tile's patch can be written while nothing reads
+// it; fence-free barriers, because __syncthreads would also wait for the prefetched patch.
+template <bool RELU>
+__global__ __launch_bounds__(256) void conv_first_loop_kernel(const ConvArgs a, int ntiles) {
+    constexpr int TR = kConvTR, TC = kConvTC, PR = TR + 2, PC = TC + 2, C = 32, NF = C / 16, MF = TR / 4;
+    constexpr int NPIX = PR * PC, COTP = C + 8;
+    static_assert(NPIX > 256 && NPIX <= 512, "two patch pixels per thread at most");
+    __shared__ __attribute__((aligned(16))) bf16 s_o[TR * TC * COTP];
+    __shared__ __attribute__((aligned(16))) bf16 s_x[NPIX * 4];
+    __shared__ __attribute__((aligned(16))) bf16 s_wf[C * 9 * 4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, m = lane & 15, g = lane >> 4;
+    const int H = a.H, W = a.W, wcin = a.Cin;
+    const int tiles_x = W / TC, tiles_y = H / TR;
+    for (int r = tid; r < C * 9; r += 256) {
+        const bf16* src = a.w + ((size_t)(r / 9) * 9 + r % 9) * wcin;
+        *reinterpret_cast<short4_t*>(s_wf + r * 4) = *reinterpret_cast<const short4_t*>(src);
+    }
+    float bb[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) bb[j] = a.bias ? a.bias[16 * j + m] : 0.0f;
+    __syncthreads();
+    // B operands as in conv_first_kernel: lane (m + 16 g) holds k = 32 s + 8 g + e, i.e. taps
+    // 8 s + 2 g (e < 4) and 8 s + 2 g + 1 (e >= 4), field e % 4, of channel 16 j + m
+    short8_t b[2][NF];
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            const int r = (16 * j + m) * 9, t0 = 8 * st + 2 * g;
+            const short4_t w0 = t0 < 9 ? *reinterpret_cast<const short4_t*>(s_wf + (r + t0) * 4) : short4_t{0, 0, 0, 0};
+            const short4_t w1 = t0 + 1 < 9 ? *reinterpret_cast<const short4_t*>(s_wf + (r + t0 + 1) * 4)
+                                           : short4_t{0, 0, 0, 0};
+            b[st][j] = short8_t{w0[0], w0[1], w0[2], w0[3], w1[0], w1[1], w1[2], w1[3]};
+        }
+    // the patch of a tile (pixels tid and tid + 256 of its 18 x 18, circular), into registers
+    float4 px0, px1;
+    auto fetch = [&](int tile) __attribute__((always_inline)) {
+        const int tx0 = (tile % tiles_x) * TC, ty0 = ((tile / tiles_x) % tiles_y) * TR, n = tile / (tiles_x * tiles_y);
+        const int p1 = tid + 256 < NPIX ? tid + 256 : NPIX - 1;
+        const int y0 = wrap_coord(ty0 + tid / PC - 1, H), x0 = wrap_coord(tx0 + tid % PC - 1, W);
+        const int y1 = wrap_coord(ty0 + p1 / PC - 1, H), x1 = wrap_coord(tx0 + p1 % PC - 1, W);
+        px0 = *reinterpret_cast<const float4*>(a.xin + ((size_t)(n * H + y0) * W + x0) * 4);
+        px1 = *reinterpret_cast<const float4*>(a.xin + ((size_t)(n * H + y1) * W + x1) * 4);
+    };
+    auto put = [&](int pix, const float4& f) __attribute__((always_inline)) {
+        *reinterpret_cast<uint2*>(s_x + pix * 4) = make_uint2(pack_bf2(f.x, f.y), pack_bf2(f.z, f.w));
+    };
+    int tile = blockIdx.x;
+    if (tile < ntiles) fetch(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const int tx0 = (tile % tiles_x) * TC, ty0 = ((tile / tiles_x) % tiles_y) * TR, n = tile / (tiles_x * tiles_y);
+        put(tid, px0);
+        if (tid + 256 < NPIX) put(tid + 256, px1);
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        // the next tile's patch (this one's again after the last tile)
+        const int nt = tile + (int)gridDim.x;
+        fetch(nt < ntiles ? nt : tile);
+        float4_t acc[MF][NF];
+#pragma unroll
+        for (int f = 0; f < MF; ++f) {
+            const int row = wave * MF + f;
+#pragma unroll
+            for (int j = 0; j < NF; ++j) acc[f][j] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < 2; ++st) {
+                const int t0 = 8 * st + 2 * g, t1 = t0 + 1;
+                short4_t x0 = {0, 0, 0, 0}, x1 = {0, 0, 0, 0};
+                if (t0 < 9) x0 = *reinterpret_cast<const short4_t*>(s_x + ((row + t0 / 3) * PC + m + t0 % 3) * 4);
+                if (t1 < 9) x1 = *reinterpret_cast<const short4_t*>(s_x + ((row + t1 / 3) * PC + m + t1 % 3) * 4);
+                const short8_t av = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
+#pragma unroll
+                for (int j = 0; j < NF; ++j) acc[f][j] = mfma32(av, b[st][j], acc[f][j]);
+            }
+        }
+        // D fragment: lane (16 g + c) holds pixels 4g .. 4g+3 of the row, channel 16 j + c
+#pragma unroll
+        for (int j = 0; j < NF; ++j)
+#pragma unroll
+            for (int f = 0; f < MF; ++f)
+#pragma unroll
+                for (int e = 0; e < 4; e += 2) {
+                    float v0 = acc[f][j][e] + bb[j], v1 = acc[f][j][e + 1] + bb[j];
+                    if (RELU) v0 = fmaxf(v0, 0.0f), v1 = fmaxf(v1, 0.0f);
+                    const uint32_t pk = pack_bf2(v0, v1);
+                    s_o[((wave * MF + f) * TC + 4 * g + e) * COTP + 16 * j + m] = (bf16)(pk & 0xffff);
+                    s_o[((wave * MF + f) * TC + 4 * g + e + 1) * COTP + 16 * j + m] = (bf16)(pk >> 16);
+                }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (a.y) {
+#pragma unroll
+            for (int k = 0; k < TR * TC * (C / 8) / 256; ++k) {
+                const int piece = tid + 256 * k, q = piece % (C / 8), pix = piece / (C / 8);
+                const int yy = ty0 + pix / TC, xx = tx0 + pix % TC;
+                *reinterpret_cast<short8_t*>(a.y + ((size_t)(n * H + yy) * W + xx) * a.ys + a.yo + 8 * q) =
+                    *reinterpret_cast<const short8_t*>(s_o + pix * COTP + 8 * q);
+            }
+        }
+        if (a.yp) {
+            // 2x2 mean of the bf16 outputs, summed (0,0), (0,1), (1,0), (1,1)
+            static_assert((TR / 2) * (TC / 2) * (C / 8) == 256, "one pooled piece per thread");
+            const int q = tid % (C / 8), pix = tid / (C / 8), py = pix / (TC / 2), px = pix % (TC / 2);
+            const int Hp = H >> 1, Wp = W >> 1, yy = (ty0 >> 1) + py, xx = (tx0 >> 1) + px;
+            const bf16* o = s_o + ((2 * py) * TC + 2 * px) * COTP + 8 * q;
+            const short8_t v0 = *reinterpret_cast<const short8_t*>(o);
+            const short8_t v1 = *reinterpret_cast<const short8_t*>(o + COTP);
+            const short8_t v2 = *reinterpret_cast<const short8_t*>(o + TC * COTP);
+            const short8_t v3 = *reinterpret_cast<const short8_t*>(o + (TC + 1) * COTP);
+            uint32_t r[4];
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) {
+                const float s0 = bf2f((bf16)v0[k]) + bf2f((bf16)v1[k]) + bf2f((bf16)v2[k]) + bf2f((bf16)v3[k]);
+                const float s1 = bf2f((bf16)v0[k + 1]) + bf2f((bf16)v1[k + 1]) + bf2f((bf16)v2[k + 1]) +
+                                 bf2f((bf16)v3[k + 1]);
+                r[k / 2] = pack_bf2(0.25f * s0, 0.25f * s1);
+            }
+            *reinterpret_cast<uint4*>(a.yp + ((size_t)(n * Hp + yy) * Wp + xx) * a.yps + a.ypo + 8 * q) =
+                make_uint4(r[0], r[1], r[2], r[3]);
+        }
+    }
+}
+
 // PFW: the next chunk's weights are fetched into registers with the patch, so that no global
 // latency is exposed when a chunk is published. It costs registers: COT = 32 then runs at two
 // workgroups per CU instead of three (taken when the grid is too small to fill three), and
@@ -453,13 +592,6 @@ struct WaveConvGeom {
     static constexpr int LDS_BYTES = 2 * BUF_BYTES + kWaveMaxCout * 4;  // two buffers, the bias
 };
 
-typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-
-// two FP32 values as packed bf16 (round to nearest even, one instruction)
-__device__ __forceinline__ uint32_t pack_bf2(float x, float y) {
-    const bf16x2_t v = {(__bf16)x, (__bf16)y};
-    return __builtin_bit_cast(uint32_t, v);
-}
 // the two bf16 halves of a packed pair as FP32
 __device__ __forceinline__ float bf_lo(uint32_t v) { return __uint_as_float(v << 16); }
 __device__ __forceinline__ float bf_hi(uint32_t v) { return __uint_as_float(v & 0xffff0000u); }
@@ -1247,6 +1379,25 @@ static hipError_t launch_first_t(const ConvArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <bool R>
+static hipError_t launch_first_loop(const ConvArgs& a, hipStream_t st) {
+    static int grid_cap = 0;  // workgroups resident at once on this device (set once)
+    if (!grid_cap) {
+        int dev = 0, cus = 0, per = 0;
+        hipError_t e;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)&conv_first_loop_kernel<R>, 256, 0)) !=
+            hipSuccess)
+            return e;
+        grid_cap = (per < 1 ? 1 : per) * cus;
+    }
+    const long long tiles = (long long)a.N * (a.H / kConvTR) * (a.W / kConvTC);
+    const long long grid = tiles < grid_cap ? tiles : grid_cap;
+    hipLaunchKernelGGL((conv_first_loop_kernel<R>), dim3((unsigned)grid), dim3(256), 0, st, a, (int)tiles);
+    return hipGetLastError();
+}
+
 template <int CG, bool R, int OUT>
 static hipError_t launch_wave_o(const ConvArgs& a, hipStream_t st) {
     using G = WaveConvGeom<CG>;
@@ -1301,7 +1452,13 @@ hipError_t unet_conv_plan(int ks, const ConvArgs& a, ConvPlan* plan) {
                                    a.H % 2 == 0 && a.W % 2 == 0)) &&
                         (!a.pred || a.res) && a.N >= 1 && a.H >= 1 && a.W >= 1;
         if (!ok) return hipErrorInvalidValue;
-        p.first = 1;
+        auto al = [](const void* ptr, int b) { return (reinterpret_cast<uintptr_t>(ptr) & (b - 1)) == 0; };
+        // the persistent kernel: 4 fields, 32 channels, y and/or its pool only, whole tiles
+        const bool loop = a.xin_c == 4 && a.Cin % 4 == 0 && a.Cout == 32 && (a.y || a.yp) && !a.yf && !a.pred &&
+                          a.H % kConvTR == 0 && a.W % kConvTC == 0 && al(a.xin, 16) && al(a.w, 8) &&
+                          (!a.y || al(a.y, 16)) && (!a.yp || al(a.yp, 16)) &&
+                          (long long)a.N * (a.H / kConvTR) * (a.W / kConvTC) < (1LL << 30);
+        p.first = loop ? 3 : 1;
         p.cot = a.Cout <= 32 ? 32 : 64;
         p.pfw = 0;
         *plan = p;
@@ -1359,6 +1516,7 @@ hipError_t unet_conv(int ks, bool relu, const ConvArgs& a, hipStream_t st) {
         if (p.cot == 64) return relu ? launch_wave_t<2, true>(a, st) : launch_wave_t<2, false>(a, st);
         return relu ? launch_wave_t<1, true>(a, st) : launch_wave_t<1, false>(a, st);
     }
+    if (p.first == 3) return relu ? launch_first_loop<true>(a, st) : launch_first_loop<false>(a, st);
     if (p.first) {
         if (p.cot == 32) return relu ? launch_first_t<true, 32>(a, st) : launch_first_t<false, 32>(a, st);
         return relu ? launch_first_t<true, 64>(a, st) : launch_first_t<false, 64>(a, st);

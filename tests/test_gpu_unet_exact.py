@@ -41,8 +41,10 @@ def dev(a, dtype=None):
     return (t if dtype is None else t.to(dtype)).cuda()
 
 
-def run_conv(rng, ks, n, h, w, cin, cout, cl=0, relu=True, pool=False, head_rc=0, first=0):
-    """one convolution through lbpf_unet_conv_probe and its exact FP64 reference"""
+def run_conv(rng, ks, n, h, w, cin, cout, cl=0, relu=True, pool=False, head_rc=0, first=0, net=False):
+    """one convolution through lbpf_unet_conv_probe and its exact FP64 reference; with net, only
+    the outputs the network's own layer writes (y and its pool, or with a head the prediction
+    alone), which selects the kernels' specialized output paths"""
     import torch
     from paper_1902_08933_amd import lbpf
     wt = small(rng, (cout, ks * ks, cin), -2, 2)
@@ -65,8 +67,8 @@ def run_conv(rng, ks, n, h, w, cin, cout, cl=0, relu=True, pool=False, head_rc=0
     out = U.conv(x_full, wt, bias)  # FP64, exact
     if relu:
         out = np.maximum(out, 0.0)
-    y = torch.empty((n, h, w, cout), dtype=torch.int16, device="cuda")
-    yf = torch.empty((n, h, w, cout), dtype=torch.float32, device="cuda")
+    y = None if (net and head_rc) else torch.empty((n, h, w, cout), dtype=torch.int16, device="cuda")
+    yf = None if net else torch.empty((n, h, w, cout), dtype=torch.float32, device="cuda")
     yp = torch.empty((n, h // 2, w // 2, cout), dtype=torch.int16, device="cuda") if pool else None
     extra = {}
     if head_rc:
@@ -78,14 +80,17 @@ def run_conv(rng, ks, n, h, w, cin, cout, cl=0, relu=True, pool=False, head_rc=0
     variant = lbpf.conv_probe(ks, relu, n, h, w, cin, cout, dev(bits(wt)), cl=cl,
                               bias=dev(bias.astype(np.float32)), y=y, yf=yf, yp=yp, **args, **extra)
     torch.cuda.synchronize()
-    got = {"yf": yf.double().cpu().numpy(), "y": from_bits(y)}
-    exp = {"yf": out, "y": U.bf16_round(out)}
+    got, exp = {}, {}
+    if yf is not None:
+        got["yf"], exp["yf"] = yf.double().cpu().numpy(), out
+    if y is not None:
+        got["y"], exp["y"] = from_bits(y), U.bf16_round(out)
     if pool:
         got["yp"] = from_bits(yp)
-        exp["yp"] = U.bf16_round(U.pool(exp["y"]))
+        exp["yp"] = U.bf16_round(U.pool(U.bf16_round(out)))
     if head_rc:
         got["pred"] = extra["pred"].double().cpu().numpy()
-        exp["pred"] = res + hb + exp["y"] @ hw.T
+        exp["pred"] = res + hb + U.bf16_round(out) @ hw.T
     return variant, got, exp
 
 
@@ -97,11 +102,15 @@ def assert_bitwise(got, exp):
             (k, int((g != e).sum()), float(np.abs(g - e).max()))
 
 
-# (name, kwargs, expected variant (kernel: 0 tiled, 1 first layer, 2 wave-row; output channels per
-# workgroup; weight prefetch of the tiled kernel))
+# (name, kwargs, expected variant (kernel: 0 tiled, 1 first layer, 2 wave-row, 3 persistent first
+# layer; output channels per workgroup; weight prefetch of the tiled kernel))
 CASES = [
-    # the first layer of the 1024^2 pass: FP32 fields in, (tap, field)-ordered K
-    ("first_1024", dict(ks=3, n=1, h=1024, w=1024, cin=16, cout=32, first=4, pool=True), (1, 32, 0)),
+    # the first layer of the 1024^2 pass: FP32 fields in, (tap, field)-ordered K; the persistent
+    # kernel when only y and its pool are written (the network's case), whole tiles, 4 fields
+    ("first_1024", dict(ks=3, n=1, h=1024, w=1024, cin=16, cout=32, first=4, pool=True, net=True), (3, 32, 0)),
+    ("first_loop_images", dict(ks=3, n=3, h=48, w=80, cin=16, cout=32, first=4, pool=True, net=True, relu=False),
+     (3, 32, 0)),
+    ("first_fp32_out", dict(ks=3, n=1, h=64, w=64, cin=16, cout=32, first=4, pool=True), (1, 32, 0)),
     ("first_cout64", dict(ks=3, n=2, h=40, w=24, cin=16, cout=64, first=3), (1, 64, 0)),
     # the 3x3 layers of the 1024^2 pass run the wave-row kernel (whole 32-channel chunks):
     # E1 (level 1, 32 -> 64, one input chunk, fused pool), E2 (64 -> 128), E3 (128 -> 256),
@@ -114,6 +123,17 @@ CASES = [
     ("dec2_256", dict(ks=3, n=1, h=256, w=256, cin=384, cl=256, cout=128), (2, 128, 0)),
     ("dec1_512", dict(ks=3, n=1, h=512, w=512, cin=192, cl=128, cout=64), (2, 64, 0)),
     ("dec0_head_1024", dict(ks=3, n=1, h=1024, w=1024, cin=96, cl=64, cout=32, head_rc=4), (2, 32, 0)),
+    # the same layers with only the outputs the network writes (the output paths specialized
+    # at compile time: y; y and its pool; the head's prediction alone)
+    ("enc1_512_net", dict(ks=3, n=1, h=512, w=512, cin=32, cout=64, pool=True, net=True), (2, 64, 0)),
+    ("enc2_256_net", dict(ks=3, n=1, h=256, w=256, cin=64, cout=128, pool=True, net=True), (2, 128, 0)),
+    ("enc3_128_net", dict(ks=3, n=1, h=128, w=128, cin=128, cout=256, net=True), (2, 128, 0)),
+    ("dec2_256_net", dict(ks=3, n=1, h=256, w=256, cin=384, cl=256, cout=128, net=True), (2, 128, 0)),
+    ("dec1_512_net", dict(ks=3, n=1, h=512, w=512, cin=192, cl=128, cout=64, net=True), (2, 64, 0)),
+    ("dec0_head_1024_net", dict(ks=3, n=1, h=1024, w=1024, cin=96, cl=64, cout=32, head_rc=4, net=True),
+     (2, 32, 0)),
+    ("dec0_head_ragged_net", dict(ks=3, n=2, h=40, w=72, cin=96, cl=64, cout=32, head_rc=4, net=True), (2, 32, 0)),
+    ("wave32_ragged_pool_net", dict(ks=3, n=3, h=24, w=72, cin=64, cout=32, pool=True, net=True), (2, 32, 0)),
     # ragged tiles (rows and columns beyond the image), several images, no activation, a head
     # with rc != 4, the pool at every channel grouping, images of one patch
     ("dec0_head_ragged", dict(ks=3, n=2, h=40, w=72, cin=96, cl=64, cout=32, head_rc=4), (2, 32, 0)),
