@@ -319,7 +319,8 @@ lbpf_status lbpf_mfma_probe(int32_t k, const void* A, const void* B, float* D, v
  * first-layer (1), wave-row (2, ks = 3 with cin, cl and cout multiples of 32) or persistent
  * first-layer (3: 4 fields, cout 32, y and/or yp only, h and w multiples of 16), the output
  * channels per workgroup (16, 32, 64 or 128), and 1 if the tiled kernel prefetches the next
- * input chunk's weights into registers. Asynchronous; LBPF_E_INVALID for shapes the kernels do
+ * input chunk's weights into registers or the wave-row kernel's work items are 8 rows high
+ * instead of 16. Asynchronous; LBPF_E_INVALID for shapes the kernels do
  * not take. Defined by the network description above; used by its tests. */
 typedef struct lbpf_unet_conv_desc {
     int32_t ks, relu;  /* 1 or 3; nonzero: ReLU after the bias */

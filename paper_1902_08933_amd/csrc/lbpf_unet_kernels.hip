@@ -577,14 +577,15 @@ __global__ __launch_bounds__(256, (COT <= 32 && !PFW ? 3 : 2)) void conv_tile_ke
 // consecutive pixels' pieces of one channel group on 8 different 4-bank groups, so the
 // fragment reads (16 consecutive pixels of a row) are conflict-free without padding; each store
 // of staged pieces writes 64 consecutive ones.
-constexpr int kWvRows = 16;
+constexpr int kWvRows = 16;      // rows of a work item
+constexpr int kWvRowsHalf = 8;   // rows of a work item on small grids (128 channels per item)
 constexpr int kWaveMaxCout = 512;  // output channels of the wave-row kernel at most
 
-template <int CG>
+template <int CG, int RW = kWvRows>
 struct WaveConvGeom {
     static constexpr int PX = 4 / CG;                 // 16-column blocks of a work item
     static constexpr int PCOL = 16 * PX + 2;          // patch columns, with the halo
-    static constexpr int PROWS = kWvRows + 2;         // patch rows
+    static constexpr int PROWS = RW + 2;              // patch rows
     static constexpr int NPIECE = PROWS * PCOL * 4;   // 16-byte pieces of one chunk's patch
     static constexpr int NBW = (NPIECE + 255) / 256;  // 64-piece load blocks per wave (one
                                                       // instruction each, every wave the same)
@@ -609,10 +610,11 @@ __device__ __forceinline__ int wrap_near(int v, int m) {
 // with a 4-field prediction.
 enum WaveOut { kOutAny = 0, kOutY = 1, kOutYPool = 2, kOutHead = 3 };
 
-template <int CG, bool RELU, int OUT>
+template <int CG, bool RELU, int OUT, int RW = kWvRows>
 __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, int total_items) {
-    using G = WaveConvGeom<CG>;
-    constexpr int PX = G::PX, PCOL = G::PCOL, NPIECE = G::NPIECE, NBW = G::NBW, R = kWvRows;
+    using G = WaveConvGeom<CG, RW>;
+    constexpr int PX = G::PX, PCOL = G::PCOL, NPIECE = G::NPIECE, NBW = G::NBW, R = RW;
+    static_assert(R % 4 == 0, "whole groups of 4 rows (the head's residual, the pool)");
     extern __shared__ __attribute__((aligned(16))) uint8_t wconv_lds[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1398,40 +1400,40 @@ static hipError_t launch_first_loop(const ConvArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int CG, bool R, int OUT>
+template <int CG, bool R, int OUT, int RW>
 static hipError_t launch_wave_o(const ConvArgs& a, hipStream_t st) {
-    using G = WaveConvGeom<CG>;
+    using G = WaveConvGeom<CG, RW>;
     static int grid_cap = 0;  // workgroups resident at once on this device (set once)
     if (!grid_cap) {
-        hipError_t e = hipFuncSetAttribute((const void*)&conv3_wave_kernel<CG, R, OUT>,
+        hipError_t e = hipFuncSetAttribute((const void*)&conv3_wave_kernel<CG, R, OUT, RW>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, G::LDS_BYTES);
         if (e != hipSuccess) return e;
         int dev = 0, cus = 0, per = 0;
         if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
         if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)&conv3_wave_kernel<CG, R, OUT>, 256,
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)&conv3_wave_kernel<CG, R, OUT, RW>, 256,
                                                               G::LDS_BYTES)) != hipSuccess)
             return e;
         grid_cap = (per < 1 ? 1 : per) * cus;
     }
-    const long long items = (long long)a.N * ((a.H + kWvRows - 1) / kWvRows) *
+    const long long items = (long long)a.N * ((a.H + RW - 1) / RW) *
                             ((a.W + 16 * G::PX - 1) / (16 * G::PX)) * (a.Cout / (32 * CG));
     if (items > (1LL << 30)) return hipErrorInvalidValue;
     long long grid = items < grid_cap ? items : grid_cap;
     if (grid < 8) grid = 8;  // every XCD band has a workgroup
-    hipLaunchKernelGGL((conv3_wave_kernel<CG, R, OUT>), dim3((unsigned)grid), dim3(256), G::LDS_BYTES, st, a, (int)items);
+    hipLaunchKernelGGL((conv3_wave_kernel<CG, R, OUT, RW>), dim3((unsigned)grid), dim3(256), G::LDS_BYTES, st, a, (int)items);
     return hipGetLastError();
 }
 
-template <int CG, bool R>
+template <int CG, bool R, int RW = kWvRows>
 static hipError_t launch_wave_t(const ConvArgs& a, hipStream_t st) {
     if constexpr (CG == 1)
-        if (a.hw && a.rc == 4 && !a.y && !a.yp && !a.yf) return launch_wave_o<CG, R, kOutHead>(a, st);
+        if (a.hw && a.rc == 4 && !a.y && !a.yp && !a.yf) return launch_wave_o<CG, R, kOutHead, RW>(a, st);
     if (!a.hw && !a.yf && !a.pred && a.y) {
-        if (a.yp) return launch_wave_o<CG, R, kOutYPool>(a, st);
-        return launch_wave_o<CG, R, kOutY>(a, st);
+        if (a.yp) return launch_wave_o<CG, R, kOutYPool, RW>(a, st);
+        return launch_wave_o<CG, R, kOutY, RW>(a, st);
     }
-    return launch_wave_o<CG, R, kOutAny>(a, st);
+    return launch_wave_o<CG, R, kOutAny, RW>(a, st);
 }
 
 // the wave-row kernel unless LBPF_CONV_WAVE=0 is set (read once)
@@ -1486,7 +1488,10 @@ hipError_t unet_conv_plan(int ks, const ConvArgs& a, ConvPlan* plan) {
         (!a.y || al16(a.y)) && (!a.yp || al16(a.yp)) && (!a.hw || a.rc != 4 || (al16(a.res) && al16(a.pred)))) {
         p.first = 2;
         p.cot = wcot;
-        p.pfw = 0;
+        // 128-channel work items of 8 rows instead of 16 when the 16-row ones would not give
+        // every CU one (a 128^2 level: 128 items)
+        const long long items16 = (long long)a.N * ((a.H + kWvRows - 1) / kWvRows) * ((a.W + 15) / 16) * (a.Cout / 128);
+        p.pfw = (wcot == 128 && items16 < 256 && a.H >= kWvRowsHalf + 2) ? 1 : 0;
         *plan = p;
         return hipSuccess;
     }
@@ -1512,6 +1517,8 @@ hipError_t unet_conv(int ks, bool relu, const ConvArgs& a, hipStream_t st) {
     const hipError_t e = unet_conv_plan(ks, a, &p);
     if (e != hipSuccess) return e;
     if (p.first == 2) {
+        if (p.cot == 128 && p.pfw)
+            return relu ? launch_wave_t<4, true, kWvRowsHalf>(a, st) : launch_wave_t<4, false, kWvRowsHalf>(a, st);
         if (p.cot == 128) return relu ? launch_wave_t<4, true>(a, st) : launch_wave_t<4, false>(a, st);
         if (p.cot == 64) return relu ? launch_wave_t<2, true>(a, st) : launch_wave_t<2, false>(a, st);
         return relu ? launch_wave_t<1, true>(a, st) : launch_wave_t<1, false>(a, st);

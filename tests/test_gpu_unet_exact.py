@@ -103,7 +103,8 @@ def assert_bitwise(got, exp):
 
 
 # (name, kwargs, expected variant (kernel: 0 tiled, 1 first layer, 2 wave-row, 3 persistent first
-# layer; output channels per workgroup; weight prefetch of the tiled kernel))
+# layer; output channels per workgroup; weight prefetch of the tiled kernel, or 8-row work items
+# of the wave-row kernel))
 CASES = [
     # the first layer of the 1024^2 pass: FP32 fields in, (tap, field)-ordered K; the persistent
     # kernel when only y and its pool are written (the network's case), whole tiles, 4 fields
@@ -119,7 +120,7 @@ CASES = [
     # work items per workgroup, so the persistent loop and its chunk pipeline across items run
     ("enc1_512", dict(ks=3, n=1, h=512, w=512, cin=32, cout=64, pool=True), (2, 64, 0)),
     ("enc2_256", dict(ks=3, n=1, h=256, w=256, cin=64, cout=128, pool=True), (2, 128, 0)),
-    ("enc3_128", dict(ks=3, n=1, h=128, w=128, cin=128, cout=256), (2, 128, 0)),
+    ("enc3_128", dict(ks=3, n=1, h=128, w=128, cin=128, cout=256), (2, 128, 1)),
     ("dec2_256", dict(ks=3, n=1, h=256, w=256, cin=384, cl=256, cout=128), (2, 128, 0)),
     ("dec1_512", dict(ks=3, n=1, h=512, w=512, cin=192, cl=128, cout=64), (2, 64, 0)),
     ("dec0_head_1024", dict(ks=3, n=1, h=1024, w=1024, cin=96, cl=64, cout=32, head_rc=4), (2, 32, 0)),
@@ -127,7 +128,7 @@ CASES = [
     # at compile time: y; y and its pool; the head's prediction alone)
     ("enc1_512_net", dict(ks=3, n=1, h=512, w=512, cin=32, cout=64, pool=True, net=True), (2, 64, 0)),
     ("enc2_256_net", dict(ks=3, n=1, h=256, w=256, cin=64, cout=128, pool=True, net=True), (2, 128, 0)),
-    ("enc3_128_net", dict(ks=3, n=1, h=128, w=128, cin=128, cout=256, net=True), (2, 128, 0)),
+    ("enc3_128_net", dict(ks=3, n=1, h=128, w=128, cin=128, cout=256, net=True), (2, 128, 1)),
     ("dec2_256_net", dict(ks=3, n=1, h=256, w=256, cin=384, cl=256, cout=128, net=True), (2, 128, 0)),
     ("dec1_512_net", dict(ks=3, n=1, h=512, w=512, cin=192, cl=128, cout=64, net=True), (2, 64, 0)),
     ("dec0_head_1024_net", dict(ks=3, n=1, h=1024, w=1024, cin=96, cl=64, cout=32, head_rc=4, net=True),
@@ -140,7 +141,9 @@ CASES = [
     ("wave_head_rc3", dict(ks=3, n=1, h=20, w=70, cin=64, cl=32, cout=32, head_rc=3), (2, 32, 0)),
     ("wave32_ragged_pool", dict(ks=3, n=3, h=24, w=72, cin=64, cout=32, pool=True), (2, 32, 0)),
     ("wave64_ragged_pool", dict(ks=3, n=2, h=34, w=50, cin=96, cl=32, cout=64, pool=True, relu=False), (2, 64, 0)),
-    ("wave128_ragged_pool", dict(ks=3, n=1, h=18, w=30, cin=32, cout=384, pool=True), (2, 128, 0)),
+    ("wave128_ragged_pool", dict(ks=3, n=1, h=18, w=30, cin=32, cout=384, pool=True), (2, 128, 1)),
+    ("wave128_half_ragged", dict(ks=3, n=2, h=26, w=40, cin=64, cl=32, cout=128, pool=True, net=True), (2, 128, 1)),
+    ("wave128_full_ragged", dict(ks=3, n=8, h=60, w=72, cin=64, cout=256, pool=True), (2, 128, 0)),
     ("wave32_one_patch", dict(ks=3, n=2, h=18, w=66, cin=32, cout=32), (2, 32, 0)),
     # the tiled kernel, which takes images smaller than one patch of the wave-row kernel (with
     # the fused head) and channel counts that are not whole 32-channel chunks: COT 64
