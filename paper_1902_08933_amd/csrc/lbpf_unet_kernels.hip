@@ -643,16 +643,30 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
         l_ty0 = (t % tiles_y) * R;
         l_n = t / tiles_y;
     };
-    // the lane's piece of load block i: patch row and column, and the channel group its LDS slot
-    // holds (pieces of the padding past the patch take its last pixel; nothing reads them)
-    auto piece = [&](int i, int& prow, int& col, int& gg) __attribute__((always_inline)) {
-        // recomputed at every use: hoisted out of the loop, these values for every block would
-        // take registers the MFMA loop needs (the empty asm hides that they do not change)
-        const int s = (4 * i + wave) * 64 + lane;
-        const int p = (s < NPIECE ? s : NPIECE - 1) >> 2;
-        prow = p / PCOL;
-        col = p - prow * PCOL;
-        gg = (s & 3) ^ ((col >> 1) & 3);
+    // Load blocks. The patch in LDS is [patch row][column][4 slots of 16 bytes], slot g of
+    // column c holding channel group g ^ ((c >> 1) & 3). Load block w = 4 i + wave (64 lanes,
+    // 16 bytes each): the first REG blocks are row segments, patch row w / BPR, columns
+    // 16 (w % BPR) .. +15, lane l taking column 16 (w % BPR) + l / 4, slot l % 4, so that a
+    // block's LDS slots are contiguous and its patch row is uniform; the last two columns of
+    // every row (8 pieces a row) follow in LFB blocks, piece t = 64 (w - REG) + lane at row
+    // t / 8, column 16 PX + (t % 8) / 4, slot t % 4 (past the end: the last piece again).
+    constexpr int BPR = PX, REG = G::PROWS * BPR, LEFTN = G::PROWS * 8, LFB = (LEFTN + 63) / 64;
+    static_assert(REG + LFB <= 4 * NBW, "every piece in a load block");
+    // block i is a row segment on every wave: its row is uniform and its column (b = wave % BPR,
+    // since BPR divides 4) is the same in every such block of the wave
+    auto all_rows = [](int i) constexpr { return 4 * i + 3 < REG; };
+    const int rb = wave % BPR;
+    const int r_col = 16 * rb + (lane >> 2), r_gs = lane & 3, r_gg = r_gs ^ ((lane >> 3) & 3);
+    // any block: the lane's patch row, column and slot (uniform branch on the block)
+    auto piece = [&](int i, int& prow, int& col, int& gs) __attribute__((always_inline)) {
+        const int w = 4 * i + wave;
+        if (w < REG) {
+            prow = w / BPR, col = 16 * (w % BPR) + (lane >> 2), gs = lane & 3;
+        } else {
+            int t = (w - REG) * 64 + lane;
+            t = t < LEFTN ? t : LEFTN - 1;
+            prow = t >> 3, col = 16 * PX + ((t & 7) >> 2), gs = t & 3;
+        }
     };
     // the chunk whose patch is being loaded, as uniform values set once per step: the chunk's
     // first channel in image l_n, the byte strides of a row and a pixel, and the shift of the
@@ -677,22 +691,48 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
             c_base = xb + 2 * (kc - Cl) + (long long)l_n * H * c_rs;
         }
     };
-    // piece block i of the planned chunk into the staging registers: the uniform base and a
-    // 32-bit per-lane byte offset (24-bit products: rows of at most 16 MB, checked on the host)
+    // load block i of the planned chunk into the staging registers: a uniform base and a 32-bit
+    // per-lane byte offset (24-bit products: rows of at most 16 MB, checked on the host). A row
+    // segment takes its row in the base (scalar arithmetic, the circular wrap included) and the
+    // lane's column offset c_xoff, computed once per step; other blocks compute both per lane.
     short8_t stage[NBW];
-    auto issue_block = [&](int i) __attribute__((always_inline)) {
-        int prow, col, gg;
-        piece(i, prow, col, gg);
-        const int yy = wrap_near(l_ty0 + prow - 1, H), xx = wrap_near(l_tx0 + col - 1, W);
-        const unsigned off = __umul24((unsigned)(yy >> c_sh), (unsigned)c_rs) +
-                             __umul24((unsigned)(xx >> c_sh), (unsigned)c_ps) + 16 * gg;
-        stage[i] = *reinterpret_cast<const __attribute__((address_space(1))) short8_t*>(c_base + off);
+    unsigned c_xoff = 0;
+    int c_y0 = 0;  // the patch row of this wave's first row segment, as an image row (unwrapped)
+    auto plan_cols = [&]() __attribute__((always_inline)) {
+        const int xx = wrap_near(l_tx0 + r_col - 1, W);
+        c_xoff = __umul24((unsigned)(xx >> c_sh), (unsigned)c_ps) + 16 * r_gg;
+        c_y0 = l_ty0 - 1 + wave / BPR;
     };
-    // the staged pieces into LDS buffer buf: block i of this wave is 64 consecutive pieces
+    auto issue_block = [&](int i) __attribute__((always_inline)) {
+        using gs8 = const __attribute__((address_space(1))) short8_t;
+        if (all_rows(i)) {
+            // row segments of wave w: patch rows w / BPR + i (4 / BPR)
+            // (only the first can lie above the image)
+            const int y = c_y0 + i * (4 / BPR), yy = i == 0 ? wrap_near(y, H) : (y >= H ? y - H : y);
+            stage[i] = *reinterpret_cast<gs8*>(c_base + (unsigned)((yy >> c_sh) * c_rs) + c_xoff);
+        } else {
+            int prow, col, gs;
+            piece(i, prow, col, gs);
+            const int yy = wrap_near(l_ty0 + prow - 1, H), xx = wrap_near(l_tx0 + col - 1, W);
+            const unsigned off = __umul24((unsigned)(yy >> c_sh), (unsigned)c_rs) +
+                                 __umul24((unsigned)(xx >> c_sh), (unsigned)c_ps) + 16 * (gs ^ ((col >> 1) & 3));
+            stage[i] = *reinterpret_cast<gs8*>(c_base + off);
+        }
+    };
+    // the staged pieces into LDS buffer buf
     auto publish = [&](int buf) __attribute__((always_inline)) {
+        uint8_t* b = wconv_lds + buf * G::BUF_BYTES;
 #pragma unroll
-        for (int i = 0; i < NBW; ++i)
-            *reinterpret_cast<short8_t*>(wconv_lds + buf * G::BUF_BYTES + (4 * i + wave) * 1024 + lane * 16) = stage[i];
+        for (int i = 0; i < NBW; ++i) {
+            if (all_rows(i)) {
+                const int w = 4 * i + wave;
+                *reinterpret_cast<short8_t*>(b + (w / BPR) * PCOL * 64 + rb * 1024 + lane * 16) = stage[i];
+            } else {
+                int prow, col, gs;
+                piece(i, prow, col, gs);
+                *reinterpret_cast<short8_t*>(b + (prow * PCOL + col) * 64 + gs * 16) = stage[i];
+            }
+        }
     };
     // A operands of the three taps (0, dx), (1, dx), (2, dx): lane jl + 16 q holds
     // w[co][tap][kc + 8q .. +7] of channel co = base + 8 (jl / 4) + 4 jj + jl % 4 (a uniform base
@@ -921,6 +961,7 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
     int kc = 0, buf = 0;
     plan_loads(item);
     plan_chunk(0);
+    plan_cols();
 #pragma unroll
     for (int i = 0; i < NBW; ++i) issue_block(i);
     // the patch before the weights (the first step's top then waits for the patch only)
@@ -951,6 +992,7 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
         asm volatile("" ::: "memory");
         if (more && nkc == 0) plan_loads(nitem);
         plan_chunk(lkc);
+        plan_cols();
         compute(buf, lit, lkc);
         if (nkc == 0) {
             begin_item_out(item);
