@@ -37,7 +37,7 @@ hipError_t launch_fields_to_nhwc(const Model& m, const float* fields, float* dst
                                  const float* scale, hipStream_t st);
 hipError_t launch_nhwc_to_dense(const Model& m, const float* src, float* phi, float* ux, float* uy,
                                 float* p, const float* shift, const float* scale, hipStream_t st);
-hipError_t launch_batch(int tile, const BatchInst* insts, const BatchItem* items, int nitems,
+hipError_t launch_batch(int tile, float* wsb, const BatchInst* insts, const BatchItem* items, int nitems,
                         int grid, int parity, int* ctrs, int slot, hipStream_t st);
 }  // namespace lbpf
 
@@ -625,7 +625,8 @@ static lbpf_status batch_setup(lbpf_batch* b) {
     for (int k = 0; k < b->n; ++k) {
         const Model& m = b->inst[k]->m;
         hi[k].m = m;
-        hi[k].ws = b->inst[k]->ws;
+        // every instance's workspace lies in the batch's (float-aligned offsets)
+        hi[k].ws_off = (long long)(reinterpret_cast<char*>(b->inst[k]->ws) - b->ws) / (long long)sizeof(float);
         hi[k].nsx = (m.nx + tx - 1) / tx;
         hi[k].nsy = (m.ny + ch - 1) / ch;
         if (b->frozen[k]) continue;  // held fixed: no work, its state stays in its copy
@@ -654,11 +655,12 @@ static lbpf_status batch_setup(lbpf_batch* b) {
         for (int sidx = 0; sidx < kBatchGraphSteps && e == hipSuccess; ++sidx) {
             parities[sidx] = (start + sidx) & 1;
             slots[sidx] = sidx;
+            float* wsb = reinterpret_cast<float*>(b->ws);
             const BatchInst* di = b->d_insts;
             const BatchItem* dt = b->d_items;
             int ni = b->nitems;
             int* dc = b->d_ctr;
-            void* args[] = {(void*)&di, (void*)&dt, (void*)&ni, (void*)&parities[sidx], (void*)&dc,
+            void* args[] = {(void*)&wsb, (void*)&di, (void*)&dt, (void*)&ni, (void*)&parities[sidx], (void*)&dc,
                             (void*)&slots[sidx]};
             hipKernelNodeParams kp{};
             kp.func = fn;
@@ -793,8 +795,8 @@ lbpf_status lbpf_batch_step(lbpf_batch* b, int64_t nsteps) {
     // graph replays (slots 0 .. 7), then single launches for the rest
     int64_t done = 0;
     auto single = [&]() -> lbpf_status {
-        hipError_t e = launch_batch(b->tile, b->d_insts, b->d_items, b->nitems, b->grid, b->parity, b->d_ctr,
-                                    b->slot, b->stream);
+        hipError_t e = launch_batch(b->tile, reinterpret_cast<float*>(b->ws), b->d_insts, b->d_items, b->nitems,
+                                    b->grid, b->parity, b->d_ctr, b->slot, b->stream);
         if (e != hipSuccess) return bfail(b, LBPF_E_HIP, "batch kernel: %s", hipGetErrorString(e));
         b->slot = (b->slot + 1) % kBatchSlots;
         batch_advance(b, 1);

@@ -545,7 +545,7 @@ static hipError_t launch_fused(int tile, const Model& m, const float* fin, float
 // ---------------------------------------------------------------------------------------------
 
 template <int TX, int NT, int CH, bool PF>
-__global__ __launch_bounds__(NT) void batch_kernel(const BatchInst* __restrict__ insts,
+__global__ __launch_bounds__(NT) void batch_kernel(float* __restrict__ wsb, const BatchInst* __restrict__ insts,
                                                    const BatchItem* __restrict__ items,
                                                    int nitems, int parity, int* __restrict__ ctrs,
                                                    int slot) {
@@ -567,8 +567,12 @@ __global__ __launch_bounds__(NT) void batch_kernel(const BatchInst* __restrict__
         const BatchInst& I = insts[w.inst];
         const Model m = I.m;
         const long long P = m.plane;
-        const float* in = I.ws + parity * m.copy;
-        float* out = I.ws + (1 - parity) * m.copy;
+        // the workspace as an offset from the kernel argument wsb (a pointer read from memory would
+        // not be known to be global: its accesses would be flat ones, which also count in the LDS
+        // counter and make the stencil's LDS waits wait for them)
+        float* ws = wsb + I.ws_off;
+        const float* in = ws + parity * m.copy;
+        float* out = ws + (1 - parity) * m.copy;
         const int x0 = (w.chunk % I.nsx) * TX, ys = (w.chunk / I.nsx) * CH;
         if (m.bc == 1)
             march_chunk<TX, NT, CH, PF, true, 1, true>(m, in + kCopyF * P, out + kCopyF * P, in + kCopyH * P,
@@ -620,13 +624,14 @@ hipError_t batch_kernel_info(int tile, void** fn, int* nt, int* tx, int* ch, int
     return e;
 }
 
-hipError_t launch_batch(int tile, const BatchInst* insts, const BatchItem* items, int nitems,
+hipError_t launch_batch(int tile, float* wsb, const BatchInst* insts, const BatchItem* items, int nitems,
                         int grid, int parity, int* ctrs, int slot, hipStream_t st) {
     void* fn;
     int nt, tx, ch, per;
     hipError_t e = batch_kernel_info(tile, &fn, &nt, &tx, &ch, &per);
     if (e != hipSuccess) return e;
-    void* args[] = {(void*)&insts, (void*)&items, (void*)&nitems, (void*)&parity, (void*)&ctrs, (void*)&slot};
+    void* args[] = {(void*)&wsb, (void*)&insts, (void*)&items, (void*)&nitems, (void*)&parity, (void*)&ctrs,
+                    (void*)&slot};
     return hipLaunchKernel(fn, dim3(grid), dim3(nt), args, 0, st);
 }
 

@@ -75,7 +75,8 @@ struct Model {
 // One simulation of a batch, as the batched kernel sees it (device memory).
 struct BatchInst {
     Model m;
-    float* ws;        // base of the instance's workspace (population copies as above)
+    long long ws_off;  // the instance's workspace (population copies as above), in floats from
+                       // the start of the batch's workspace
     int nsx, nsy;     // strips and chunks of the batch's strip shape
 };
 // Counter slots of the batched kernel (launches use them in cyclic order; see batch_kernel).

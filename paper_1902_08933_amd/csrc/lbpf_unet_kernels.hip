@@ -589,7 +589,8 @@ struct WaveConvGeom {
     static constexpr int NPIECE = PROWS * PCOL * 4;   // 16-byte pieces of one chunk's patch
     static constexpr int NBW = (NPIECE + 255) / 256;  // 64-piece load blocks per wave (one
                                                       // instruction each, every wave the same)
-    static constexpr int BUF_BYTES = NBW * 4 * 1024;  // a patch buffer, padded to whole blocks
+    static constexpr int BUF_BYTES = NPIECE * 16;     // a patch buffer (padding lanes of the
+                                                      // last load block rewrite its last piece)
     static constexpr int LDS_BYTES = 2 * BUF_BYTES + kWaveMaxCout * 4;  // two buffers, the bias
 };
 
