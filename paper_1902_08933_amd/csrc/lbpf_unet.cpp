@@ -235,7 +235,11 @@ static lbpf_status forward(lbpf_unet* u, const float* in, int n, int h, int w, f
     const bool direct_in = !keep && u->cfg.in_ch <= 4;
     if (!direct_in) UCHK(unet_pack_input(in, u->cfg.in_ch, u->act[X0], np0, st));
     // encoder: E_l goes into the second part of the concat buffer of its level, and its 2x2
-    // average pool P_{l+1} (the next layer's input) is written by the same kernel
+    // average pool P_{l+1} (the next layer's input) is written by the same kernel. In inference
+    // the concat is never formed, so E_l is stored dense at the start of that buffer instead
+    // (its own channel stride): the decoder's reads of it, and the encoder's writes, are then
+    // whole cache lines.
+    const bool dense = !keep;
     auto enc = [&](int i, Buf xin, int cin, int sx, Buf out, int so, int oo, Buf pool, int cout,
                    int lev) -> lbpf_status {
         ConvArgs a{};
@@ -249,16 +253,16 @@ static lbpf_status forward(lbpf_unet* u, const float* in, int n, int h, int w, f
         return LBPF_OK;
     };
     lbpf_status s;
-    if ((s = enc(0, X0, 16, 16, U0, su0, c[1], P1, c[0], 0))) return s;
-    if ((s = enc(1, P1, c[0], c[0], U1, su1, c[2], P2, c[1], 1))) return s;
-    if ((s = enc(2, P2, c[1], c[1], U2, su2, c[3], P3, c[2], 2))) return s;
+    if ((s = enc(0, X0, 16, 16, U0, dense ? c[0] : su0, dense ? 0 : c[1], P1, c[0], 0))) return s;
+    if ((s = enc(1, P1, c[0], c[0], U1, dense ? c[1] : su1, dense ? 0 : c[2], P2, c[1], 1))) return s;
+    if ((s = enc(2, P2, c[1], c[1], U2, dense ? c[2] : su2, dense ? 0 : c[3], P3, c[2], 2))) return s;
     if ((s = enc(3, P3, c[2], c[2], E3, c[3], 0, kNumBufs, c[3], 3))) return s;
     // decoder: layer i reads [up(low), skip] with low = (buffer, channels), skip at offset cl of
     // the concat buffer cat (stride scat), at level lev
     auto dec = [&](int i, Buf low, int cl, Buf cat, int scat, Buf out, int cout, int lev) -> lbpf_status {
         if (keep) UCHK(unet_upsample(u->act[low], cl, 0, u->act[cat], scat, 0, cl, n, h >> lev, w >> lev, st));
         ConvArgs a{};
-        a.x = u->act[cat]; a.xs = scat; a.xo = cl;
+        a.x = u->act[cat]; a.xs = dense ? scat - cl : scat; a.xo = dense ? 0 : cl;
         a.xl = u->act[low]; a.xls = cl; a.xlo = 0; a.Cl = cl;
         a.Cin = scat; a.w = W(i); a.bias = B(i);
         a.y = u->act[out]; a.ys = cout; a.yo = 0;
@@ -271,7 +275,7 @@ static lbpf_status forward(lbpf_unet* u, const float* in, int n, int h, int w, f
     if (!keep && c[0] <= 32) {
         // inference: D0 stays on chip; its workgroups apply the 1x1 head and write the prediction
         ConvArgs a{};
-        a.x = u->act[U0]; a.xs = su0; a.xo = c[1];
+        a.x = u->act[U0]; a.xs = c[0]; a.xo = 0;  // dense (inference)
         a.xl = u->act[D1]; a.xls = c[1]; a.xlo = 0; a.Cl = c[1];
         a.Cin = su0; a.w = W(6); a.bias = B(6);
         a.hw = W(7); a.hb = B(7); a.res = in; a.pred = pred; a.rc = u->cfg.in_ch;
