@@ -22,14 +22,17 @@ FIELD_SCALE = (0.5, 1e-4, 1e-4, 1e-4)
 MIN_SCALE = (1e-3, 1e-6, 1e-7)
 
 
-def normalization(sim):
+def normalization(sim, phi_stats=None):
     """(shift, scale) of the network's channels for the current state of a simulation, or None
     when the state is not finite: phi and p shifted by their means and divided by their standard
     deviations, u_x and u_y divided by the larger of their two standard deviations (FP64
     statistics on the GPU, lbpf_field_stats). Over a spinodal run the fluctuations of phi grow
     from 1e-2 to 1/2 and those of u and p by three orders, so every state is brought to unit
-    scale. A pair (x_t, x_{t+K}) is normalized with the statistics of x_t."""
+    scale. A pair (x_t, x_{t+K}) is normalized with the statistics of x_t. With phi_stats (a
+    dict), phi's statistics are also left there."""
     sphi, sx, sy, sp = (sim.field_stats(f) for f in ("phi", "ux", "uy", "p"))
+    if phi_stats is not None:
+        phi_stats.update(sphi)
     vals = [sphi["mean"], sphi["std"], sx["std"], sy["std"], sp["mean"], sp["std"]]
     if not all(math.isfinite(v) for v in vals):
         return None
@@ -227,7 +230,7 @@ def _healthy(sim, max_u, max_phi):
 
 
 def hybrid_cycle(sim, net, bufs, ckpt=None, lb_every=500, lb_steps=K_STEPS, max_u=0.1, norm=None,
-                 max_growth=10.0, max_phi=1.1, ckpt_prev=None):
+                 max_growth=10.0, max_phi=1.1, ckpt_prev=None, carry=None):
     """One cycle of the hybrid: (lb_every - lb_steps) / K network strides from the solver's
     current fields, then one LB stride of lb_steps steps re-started from the network's fields
     (equilibrium populations). The cycle ends on an LB state at step + lb_every. The fields are
@@ -242,15 +245,21 @@ def hybrid_cycle(sim, net, bufs, ckpt=None, lb_every=500, lb_steps=K_STEPS, max_
     previous cycles, newest first), a plain-LB redo that itself ends non-finite or out of range
     is replaced by j + 2 cycles of the plain LB from the checkpoint j cycles further back, for
     j = 0, 1, ... until one ends in range (or the list ends).
+    carry (a dict, optional) passes the statistics of a kept cycle's final state to the next
+    cycle, which starts from that state and so need not compute them again (each one waits for
+    the GPU); it is emptied when the cycle ends with the plain LB.
     Returns True when the network's cycle was kept."""
     a, b = bufs
     step0 = sim.step_count
+    have = carry is not None and "u0" in carry
     if ckpt is not None:
         sim.save_state(out=ckpt)
-        u0 = sim.diagnostics(check=False)["max_u"]
-        mu0 = sim.field_stats("mu")["max_abs"]
+        u0 = carry["u0"] if have else sim.diagnostics(check=False)["max_u"]
+        mu0 = carry["mu0"] if have else sim.field_stats("mu")["max_abs"]
     if norm is None:
-        norm = normalization(sim)
+        norm = carry["norm"] if have else normalization(sim)
+    if carry is not None:
+        carry.clear()
     if norm is None:  # the state is not finite: nothing for the network to start from
         sim.step(lb_every)
         return False
@@ -266,11 +275,13 @@ def hybrid_cycle(sim, net, bufs, ckpt=None, lb_every=500, lb_steps=K_STEPS, max_
         return True
     d = sim.diagnostics(check=False)
     if d["status"] == 0 and d["max_u"] <= min(max_u, max(max_growth * u0, 1e-4)):
-        new = normalization(sim)
-        sphi = sim.field_stats("phi")
+        sphi = {}
+        new = normalization(sim, phi_stats=sphi)
         mu1 = sim.field_stats("mu")["max_abs"]
         if (new is not None and sphi["max_abs"] <= max_phi and new[1][0] <= max_growth * scale[0]
                 and new[1][1] <= max_growth * scale[1] and mu1 <= max_growth * max(mu0, 1e-6)):
+            if carry is not None:
+                carry.update(u0=d["max_u"], mu0=mu1, norm=new)
             return True
     sim.load_state(ckpt)
     sim.step(lb_every)
@@ -394,10 +405,12 @@ def horizon_eval(net, cfg, phi0, cycles=20, t0=1000, lb_every=500):
         return f
 
     rows = []
+    carry = {}  # statistics of the hybrid's state, from its last kept cycle
     for c in range(cycles):
         _, t_lb = timed(lambda: lb.step(lb_every))
         kept, t_hy = timed(lambda: hybrid_cycle(hy, net, bufs, ckpt=ckpts[c % depth], lb_every=lb_every,
-                                                ckpt_prev=[ckpts[(c - k) % depth] for k in range(1, min(c, depth - 1) + 1)]))
+                                                ckpt_prev=[ckpts[(c - k) % depth] for k in range(1, min(c, depth - 1) + 1)],
+                                                carry=carry))
         lb_reinit_cycle(ctl, bufs, lb_every=lb_every)
         _, t_co = timed(lambda: co.step(co_steps))
         ref, h, r, cg = host(lb), host(hy), host(ctl), host(co, up=True)
