@@ -147,6 +147,12 @@ lbpf_status lbpf_diagnostics_noalloc(lbpf_ctx* ctx, lbpf_diag* out);
  * surrogate; equally a diagnostic of the state.) */
 lbpf_status lbpf_field_stats(lbpf_ctx* ctx, int32_t field, double* out3);
 
+/* lbpf_field_stats of n (1 to 6) fields at once, with one synchronization: out (3 n doubles,
+ * host) receives for field[k] its mean, standard deviation and largest magnitude at out[3 k],
+ * bit for bit what lbpf_field_stats returns for it. LBPF_E_INVALID for n out of range, an unknown
+ * field or NULL arrays. (The hybrid surrogate reads the statistics of five fields per cycle.) */
+lbpf_status lbpf_field_stats_many(lbpf_ctx* ctx, int32_t n, const int32_t* field, double* out);
+
 /* Laplace-law pressure jump of Sec. 4.2 in FP64: P = p0 - kappa phi lap(phi)
  * + kappa |grad phi|^2 / 2 + p with p0 = phi psi'(phi) - psi(phi), averaged over nodes with
  * periodic distance r <= R/2 from (xc, yc) minus the average over r >= R + 3W.

@@ -351,6 +351,39 @@ lbpf_status lbpf_field_stats(lbpf_ctx* c, int32_t field, double* out3) {
     return LBPF_OK;
 }
 
+lbpf_status lbpf_field_stats_many(lbpf_ctx* c, int32_t n, const int32_t* which, double* out) {
+    if (lbpf_status s = check_ctx(c, true)) return s;
+    constexpr int kMax = LBPF_FIELD_MU + 1;
+    if (n < 1 || n > kMax || !which || !out) return fail(c, LBPF_E_INVALID, "n in 1..%d and both arrays required", kMax);
+    for (int k = 0; k < n; ++k)
+        if (which[k] < LBPF_FIELD_PHI || which[k] > LBPF_FIELD_MU)
+            return fail(c, LBPF_E_INVALID, "unknown field %d", which[k]);
+    if (lbpf_status s = run_fields(c)) return s;
+    // each field's three sums go from the reduction's result slots to slots 16 + 4 k of the same
+    // 64-double area (stream order), then all of them come back in one copy
+    double* res = red(c) + (size_t)kRedBlocks * kRedSlots;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < n && e == hipSuccess; ++k) {
+        e = launch_stats(c->m, fields(c) + (size_t)which[k] * c->m.plane, red(c), c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(res + 16 + 4 * k, res, 3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "field statistics kernels");
+    double r[4 * kMax];
+    e = hipMemcpyAsync(r, res + 16, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "field statistics readback");
+    const double cells = (double)c->m.nx * (double)c->m.ny;
+    for (int k = 0; k < n; ++k) {
+        const double mean = r[4 * k] / cells;
+        const double var = r[4 * k + 1] / cells - mean * mean;
+        out[3 * k] = mean;
+        out[3 * k + 1] = var > 0.0 ? std::sqrt(var) : 0.0;
+        out[3 * k + 2] = r[4 * k + 2];
+    }
+    return LBPF_OK;
+}
+
 lbpf_status lbpf_laplace_dp(lbpf_ctx* c, double xc, double yc, double R, double* dP) {
     if (lbpf_status s = check_ctx(c, true)) return s;
     if (!dP) return fail(c, LBPF_E_INVALID, "dP is NULL");

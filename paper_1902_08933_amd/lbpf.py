@@ -56,6 +56,7 @@ SIGNATURES = {
     "lbpf_laplace_dp": (_S, [_V, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                              ctypes.POINTER(ctypes.c_double)]),
     "lbpf_field_stats": (_S, [_V, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "lbpf_field_stats_many": (_S, [_V, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "lbpf_diagnostics_noalloc": (_S, [_V, ctypes.POINTER(Diag)]),
     "lbpf_state_size": (_S, [_V, ctypes.POINTER(ctypes.c_size_t)]),
     "lbpf_save_state": (_S, [_V, _V]),
@@ -243,6 +244,15 @@ class Simulation:
         out = (ctypes.c_double * 3)()
         self._c(self.lib.lbpf_field_stats(self._h, FIELDS[field], out))
         return {"mean": out[0], "std": out[1], "max_abs": out[2]}
+
+    def field_stats_many(self, fields):
+        """field_stats of several fields with one synchronization (lbpf_field_stats_many):
+        {name: {mean, std, max_abs}}"""
+        names = list(fields)
+        ids = (ctypes.c_int32 * len(names))(*[FIELDS[f] for f in names])
+        out = (ctypes.c_double * (3 * len(names)))()
+        self._c(self.lib.lbpf_field_stats_many(self._h, len(names), ids, out))
+        return {f: {"mean": out[3 * k], "std": out[3 * k + 1], "max_abs": out[3 * k + 2]} for k, f in enumerate(names)}
 
     def diagnostics(self, check=True):
         d = Diag()

@@ -30,9 +30,18 @@ def normalization(sim, phi_stats=None):
     from 1e-2 to 1/2 and those of u and p by three orders, so every state is brought to unit
     scale. A pair (x_t, x_{t+K}) is normalized with the statistics of x_t. With phi_stats (a
     dict), phi's statistics are also left there."""
-    sphi, sx, sy, sp = (sim.field_stats(f) for f in ("phi", "ux", "uy", "p"))
+    st = sim.field_stats_many(("phi", "ux", "uy", "p"))
     if phi_stats is not None:
-        phi_stats.update(sphi)
+        phi_stats.update(st["phi"])
+    return _norm_of(st)
+
+
+_STATE_FIELDS = ("phi", "ux", "uy", "p", "mu")
+
+
+def _norm_of(st):
+    """normalization() from the statistics of phi, ux, uy and p"""
+    sphi, sx, sy, sp = st["phi"], st["ux"], st["uy"], st["p"]
     vals = [sphi["mean"], sphi["std"], sx["std"], sy["std"], sp["mean"], sp["std"]]
     if not all(math.isfinite(v) for v in vals):
         return None
@@ -252,12 +261,15 @@ def hybrid_cycle(sim, net, bufs, ckpt=None, lb_every=500, lb_steps=K_STEPS, max_
     a, b = bufs
     step0 = sim.step_count
     have = carry is not None and "u0" in carry
+    st0 = None
     if ckpt is not None:
         sim.save_state(out=ckpt)
+        if not have:
+            st0 = sim.field_stats_many(_STATE_FIELDS)
         u0 = carry["u0"] if have else sim.diagnostics(check=False)["max_u"]
-        mu0 = carry["mu0"] if have else sim.field_stats("mu")["max_abs"]
+        mu0 = carry["mu0"] if have else st0["mu"]["max_abs"]
     if norm is None:
-        norm = carry["norm"] if have else normalization(sim)
+        norm = carry["norm"] if have else (_norm_of(st0) if st0 is not None else normalization(sim))
     if carry is not None:
         carry.clear()
     if norm is None:  # the state is not finite: nothing for the network to start from
@@ -275,9 +287,8 @@ def hybrid_cycle(sim, net, bufs, ckpt=None, lb_every=500, lb_steps=K_STEPS, max_
         return True
     d = sim.diagnostics(check=False)
     if d["status"] == 0 and d["max_u"] <= min(max_u, max(max_growth * u0, 1e-4)):
-        sphi = {}
-        new = normalization(sim, phi_stats=sphi)
-        mu1 = sim.field_stats("mu")["max_abs"]
+        st1 = sim.field_stats_many(_STATE_FIELDS)
+        new, sphi, mu1 = _norm_of(st1), st1["phi"], st1["mu"]["max_abs"]
         if (new is not None and sphi["max_abs"] <= max_phi and new[1][0] <= max_growth * scale[0]
                 and new[1][1] <= max_growth * scale[1] and mu1 <= max_growth * max(mu0, 1e-6)):
             if carry is not None:

@@ -143,6 +143,21 @@ def test_fallback_rolls_back_further(trained):
         np.testing.assert_array_equal(a.read(f).cpu().numpy(), b.read(f).cpu().numpy())
 
 
+def test_field_stats_many_equals_single_calls():
+    # lbpf_field_stats_many: bit for bit the statistics of one lbpf_field_stats call per field,
+    # in any order and with repeats
+    import torch
+    from paper_1902_08933_amd import lbpf, workloads as W
+    cfg, phi = W.spinodal(n=192, seed=9, amplitude=0.05)
+    sim = lbpf.Simulation(cfg).init(torch.from_numpy(phi.astype(np.float32)).cuda())
+    sim.step(200)
+    names = ("mu", "phi", "p", "ux", "uy", "rho")
+    many = sim.field_stats_many(names)
+    for f in names:
+        assert many[f] == sim.field_stats(f), f
+    assert sim.field_stats_many(("uy",)) == {"uy": sim.field_stats("uy")}
+
+
 def test_field_stats_against_host():
     # lbpf_field_stats (FP64 on the GPU) against the same statistics of the read fields
     import torch
