@@ -921,17 +921,27 @@ __global__ __launch_bounds__(256, 1) void conv3_wave_kernel(const ConvArgs a, in
     // ---- the MFMAs of one step -----------------------------------------------------------------
     // by horizontal tap dx and patch row, with the next step's patch loads between the first
     // column's rows; once a tap column is done its registers take the next step's weights
-    // (next_it, next_kc)
+    // (next_it, next_kc). B fragment t (column t / (R+2), patch row t % (R+2)) is read D
+    // fragments ahead of its MFMAs, across column ends: 3 (about 12-18 MFMAs, more than the
+    // LDS latency) where the 32-channel item's registers leave room for the extra fragments,
+    // else 1 (with more, the compiler moves the reads back next to their MFMAs).
     short8_t wr[9][2];
     auto compute = [&](int buf, int next_it, int next_kc) __attribute__((always_inline)) {
         const uint8_t* base = wconv_lds + buf * G::BUF_BYTES;
+        constexpr int T = 3 * (R + 2), D = CG == 1 ? 3 : 1;
+        auto frag = [&](int t) __attribute__((always_inline)) {
+            return *reinterpret_cast<const short8_t*>(base + (t % (R + 2)) * PCOL * 64 + boff[t / (R + 2)]);
+        };
+        short8_t bq[D + 1];
+#pragma unroll
+        for (int t = 0; t < D; ++t) bq[t] = frag(t);
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
-            short8_t bn = *reinterpret_cast<const short8_t*>(base + boff[dx]);
 #pragma unroll
             for (int ir = 0; ir < R + 2; ++ir) {
-                const short8_t bx = bn;
-                if (ir + 1 < R + 2) bn = *reinterpret_cast<const short8_t*>(base + (ir + 1) * PCOL * 64 + boff[dx]);
+                const int t = dx * (R + 2) + ir;
+                if (t + D < T) bq[(t + D) % (D + 1)] = frag(t + D);
+                const short8_t bx = bq[t % (D + 1)];
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy) {
                     const int orow = ir - dy;
