@@ -25,6 +25,7 @@ BYTES_PER_CELL = 160
 # population (an FP32 hi/lo pair), read and written: 21 + 21 values.
 STORAGE_BYTES_PER_CELL = 168
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+FWD_WARMUP = 100       # untimed U-Net forward passes before the timed ones (the clocks settle)
 ROOFLINE_GATE = 0.70   # target fraction of the peak, judged at a footprint far above the 256 MB cache
 
 
@@ -232,17 +233,23 @@ def surrogate_bench(train_steps=20000, cycles=20, seeds=SURROGATE_SEEDS, n_traj=
     big = lbpf.UNet(max_batch=1, max_h=1024, max_w=1024, train=False, seed=1)
     big.set_params(net.get_params())
     del net
-    xin = torch.zeros(1, 1024, 1024, 4, device="cuda")
+    # sustained rate: normalized fields of unit scale (seeded), 100 untimed passes while the
+    # clocks settle, then the median of 5 timed groups of 20
+    xin = torch.randn(1, 1024, 1024, 4, generator=torch.Generator().manual_seed(7)).cuda()
     yout = torch.empty_like(xin)
-    big.forward(xin, out=yout)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
+    for _ in range(FWD_WARMUP):
         big.forward(xin, out=yout)
-    e1.record()
     torch.cuda.synchronize()
-    fwd_ms = e0.elapsed_time(e1) / 10
+    groups = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            big.forward(xin, out=yout)
+        e1.record()
+        torch.cuda.synchronize()
+        groups.append(e0.elapsed_time(e1) / 20)
+    fwd_ms = float(np.median(groups))
     flops = unet_flops(big, 1024, 1024)
     del xin, yout
     per_seed = {}
@@ -287,7 +294,9 @@ def surrogate_bench(train_steps=20000, cycles=20, seeds=SURROGATE_SEEDS, n_traj=
             "one_stride_mse_normalized": {"channels": ["phi", "u_x", "u_y", "p"],
                                           "network": [float(f"{v:.3g}") for v in e_net],
                                           "persistence": [float(f"{v:.3g}") for v in e_pers]},
-            "forward_1024": {"ms": round(fwd_ms, 3), "flop": flops,
+            "forward_1024": {"ms": round(fwd_ms, 3), "warmup_passes": FWD_WARMUP,
+                             "input": "seeded N(0,1) fields, 1 x 1024 x 1024 x 4",
+                             "ms_timed_groups": [round(g, 4) for g in groups], "flop": flops,
                              "TFLOPs": round(flops / (fwd_ms * 1e-3) / 1e12, 1),
                              "frac_of_bf16_peak": round(flops / (fwd_ms * 1e-3) / 2.5e15, 4)},
             "horizon": {"grid": "1024x1024 spinodal", "t_start": 1000, "cycles": cycles, "steps_per_cycle": 500,

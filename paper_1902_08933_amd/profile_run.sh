@@ -142,15 +142,17 @@ if [ "$W" = "bench1024" ] || [ "$W" = "bench4096" ]; then
     exit $?
 fi
 if [ "$W" = "unet1024" ]; then
-    # surrogate forward pass at 1024^2: kernel trace of 1 + 10 forwards (214 GFLOP each)
+    # surrogate forward pass at 1024^2 (214 GFLOP): kernel trace of 100 warm-up forwards (the
+    # clocks settle) and 10 timed ones; the summary counts the library's kernels of the last 10
     OUT=$RAW/prof_unet1024
     PROF=${PROFILE_OUT:-profiles}
     mkdir -p "$OUT" "$PROF"
     export TMPDIR=/tmp
-    CMD="python3 -m paper_1902_08933_amd.profile_unet --h 1024 --w 1024 --reps 10"
+    CMD="python3 -m paper_1902_08933_amd.profile_unet --h 1024 --w 1024 --warmup 100 --reps 10"
     echo "profile: kernel trace unet1024" && \
     timeout -k 10 180 rocprofv3 --kernel-trace --stats -d "$OUT/trace" -o run -- $CMD > "$OUT/trace.log" 2>&1 && \
-    python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --iterations 11 --sources unet \
+    python3 -m paper_1902_08933_amd.rocprof_summary --trace "$OUT/trace/run_results.db" --iterations 10 --sources unet \
+        --kernel "lbpf::" --last 10 \
         --flop "$(python3 -m paper_1902_08933_amd.profile_unet --h 1024 --w 1024 --flop-only)" \
         --command "bash paper_1902_08933_amd/profile_run.sh unet1024  (rocprofv3 --kernel-trace --stats -- $CMD)" \
         --out "$PROF/unet_forward_1024_trace.txt"

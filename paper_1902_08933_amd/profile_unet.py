@@ -1,7 +1,7 @@
 """Profiling driver for the surrogate network (run it under rocprofv3 --kernel-trace --stats):
 forward passes at one resolution, optionally training steps.
 
-python -m paper_1902_08933_amd.profile_unet --h 1024 --w 1024 --reps 10
+python -m paper_1902_08933_amd.profile_unet --h 1024 --w 1024 --warmup 100 --reps 10
 python -m paper_1902_08933_amd.profile_unet --train --batch 8 --h 256 --w 256 --reps 10
 """
 import argparse
@@ -29,6 +29,8 @@ def main():
     ap.add_argument("--w", type=int, default=1024)
     ap.add_argument("--batch", type=int, default=1)
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1,
+                    help="untimed passes first (the clocks settle over about 100 forward passes)")
     ap.add_argument("--train", action="store_true")
     ap.add_argument("--flop-only", action="store_true",
                     help="print the multiply-add FLOPs of one forward pass and exit (no GPU)")
@@ -40,11 +42,12 @@ def main():
     g = torch.Generator().manual_seed(0)
     x = (torch.randn(a.batch, a.h, a.w, 4, generator=g) * 0.1).cuda()
     y = x * 0.9
-    if a.train:
-        net.train_step(x, y, 1e-4)
-    else:
-        out = torch.empty_like(x)
-        net.forward(x, out=out)
+    out = None if a.train else torch.empty_like(x)
+    for _ in range(max(1, a.warmup)):
+        if a.train:
+            net.train_step(x, y, 1e-4)
+        else:
+            net.forward(x, out=out)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()

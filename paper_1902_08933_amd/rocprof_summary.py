@@ -143,7 +143,13 @@ def main():
         for k, (n, tot, avg, med) in sorted(stats.items(), key=lambda kv: -kv[1][1]):
             lines.append(f"{n:6d} {tot / 1e3:12.1f} {avg / 1e3:10.3f} {med / 1e3:10.3f}  {k[:110]}")
         if a.iterations:
-            total = sum(v[1] for v in stats.values()) / a.iterations
+            # with --last, the kernels matching --kernel that ran at least once per timed
+            # iteration (their last dispatches); otherwise every kernel of the program
+            total = sum(v[1] for k, v in stats.items()
+                        if not a.last or (a.kernel in k and v[0] >= a.iterations)) / a.iterations
+            if a.last:
+                lines.append(f"counted: the last {a.last} dispatches of each kernel matching {a.kernel!r} "
+                             f"that runs every iteration")
             lines.append(f"total_kernel_us_per_iteration: {total / 1e3:.3f}")
             if a.flop:
                 lines.append(f"flop_per_iteration: {a.flop:.6e}")
