@@ -439,6 +439,41 @@ def horizon_eval(net, cfg, phi0, cycles=20, t0=1000, lb_every=500):
     return rows
 
 
+def continuous_run(net, cfg, phi0, cycles=20, t0=1000, lb_every=500):
+    """The hybrid and the plain LB, each run for `cycles` cycles of lb_every steps from the LB
+    state at t0 without stopping between cycles (no per-cycle scoring), each timed as a whole:
+    the end-to-end rate of the two. The hybrid keeps its checkpoint ring and fallback, so its
+    decisions are those of horizon_eval. Returns the times, the speedup, the cycles kept and the
+    final state's phi error and domain-length ratio against the plain LB."""
+    import torch
+    def mk():
+        return lbpf.Simulation(cfg).init(torch.from_numpy(np.asarray(phi0, dtype=np.float32)).cuda())
+    lb, hy = mk(), mk()
+    for s_ in (lb, hy):
+        s_.step(t0)
+    bufs = hybrid_buffers(hy)
+    depth = 4
+    ckpts = [torch.empty(hy.state_size(), dtype=torch.uint8, device=hy.device) for _ in range(depth)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lb.step(cycles * lb_every)
+    torch.cuda.synchronize()
+    t_lb = (time.perf_counter() - t1) * 1e3
+    carry, kept = {}, 0
+    t1 = time.perf_counter()
+    for c in range(cycles):
+        kept += bool(hybrid_cycle(hy, net, bufs, ckpt=ckpts[c % depth], lb_every=lb_every,
+                                  ckpt_prev=[ckpts[(c - k) % depth] for k in range(1, min(c, depth - 1) + 1)],
+                                  carry=carry))
+    torch.cuda.synchronize()
+    t_hy = (time.perf_counter() - t1) * 1e3
+    ref = lb.read("phi").double().cpu().numpy()
+    got = hy.read("phi").double().cpu().numpy()
+    return {"lb_ms": round(t_lb, 1), "hybrid_ms": round(t_hy, 1), "speedup": round(t_lb / t_hy, 2),
+            "cycles_kept": kept, "phi_rel_l2_end": float(f"{phi_rel_l2(got, ref):.4g}"),
+            "domain_length_ratio_end": round(domain_length(got) / domain_length(ref), 4)}
+
+
 def speedups(rows):
     """Per cycle: raw speedup t(LB) / t(hybrid); and the speedup at equal phi error, against the
     cheapest plain LB whose phi error is at most the hybrid's (the coarse LB when its error is

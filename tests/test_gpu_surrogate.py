@@ -81,6 +81,22 @@ def test_hybrid_faster_than_lb_at_stated_error(trained):
     assert abs(S.domain_length(a) / S.domain_length(b) - 1) < 0.02
 
 
+def test_continuous_run_faster_than_lb(trained):
+    # two cycles from t = 1000 run through without stopping, each method timed as a whole
+    from paper_1902_08933_amd import lbpf, surrogate as S, workloads as W
+    net, _, _ = trained
+    big = lbpf.UNet(max_batch=1, max_h=1024, max_w=1024, train=False, seed=1)
+    big.set_params(net.get_params())
+    cfg, phi = W.spinodal(n=1024, seed=99)
+    S.continuous_run(big, cfg, phi, cycles=1, t0=0)  # first calls of both paths
+    r = S.continuous_run(big, cfg, phi, cycles=2, t0=1000)
+    print(f"continuous 2 cycles: {r}", flush=True)
+    assert r["cycles_kept"] == 2
+    assert r["speedup"] > 1.0
+    assert r["phi_rel_l2_end"] < 0.15
+    assert abs(r["domain_length_ratio_end"] - 1) < 0.03
+
+
 def test_fallback_reproduces_plain_lb(trained):
     import torch
     from paper_1902_08933_amd import lbpf, surrogate as S, workloads as W
